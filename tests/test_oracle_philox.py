@@ -1,0 +1,50 @@
+"""Statistical pins of the oracle's Philox4x32-10 (the generator's known-answer
+vectors are not available offline, so its exact identity is parity-unpinned)."""
+import math
+
+import numpy as np
+
+from oracle.philox import philox4x32_10, draw_u128
+
+
+def test_outputs_uniform_over_counters():
+    words = []
+    for j in range(4000):
+        words.extend(philox4x32_10((j, 0, 0, 0), (42, 0)))
+    w = np.array(words, dtype=np.uint64)
+    # 16 equal bins on the top four bits
+    obs = np.bincount((w >> np.uint64(28)).astype(np.int64), minlength=16)
+    exp = len(words) / 16
+    chi2 = float(np.sum((obs - exp) ** 2 / exp))
+    assert chi2 < 45.0          # dof 15, p ~ 1e-4
+    # every bit position is balanced
+    bits = np.array([[(int(x) >> b) & 1 for b in range(32)] for x in words[:8000]])
+    frac = bits.mean(axis=0)
+    assert np.all(np.abs(frac - 0.5) < 5 * 0.5 / math.sqrt(8000))
+
+
+def test_avalanche_on_counter_and_key():
+    rng = np.random.default_rng(0)
+    flips = []
+    for _ in range(300):
+        c = [int(x) for x in rng.integers(0, 2 ** 32, 4)]
+        k = [int(x) for x in rng.integers(0, 2 ** 32, 2)]
+        base = philox4x32_10(c, k)
+        b = int(rng.integers(0, 6 * 32))
+        c2, k2 = list(c), list(k)
+        if b < 128:
+            c2[b // 32] ^= 1 << (b % 32)
+        else:
+            k2[(b - 128) // 32] ^= 1 << (b % 32)
+        other = philox4x32_10(c2, k2)
+        flips.append(sum(bin(x ^ y).count("1") for x, y in zip(base, other)))
+    m = float(np.mean(flips))
+    assert 60 < m < 68, m
+
+
+def test_distinct_counters_give_distinct_outputs():
+    seen = set(draw_u128(9, j) for j in range(20000))
+    assert len(seen) == 20000
+    assert draw_u128(9, 0, step=1) != draw_u128(9, 0, step=0)
+    assert draw_u128(9, 0, tensor=1) != draw_u128(9, 0)
+    assert draw_u128(9, 1 << 32) != draw_u128(9, 0)

@@ -1,0 +1,294 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+Each test ties one part of the oracle to the paper's statements, to closed
+forms, to a library routine the method reduces to, or to brute force, so a
+plausible slip (dropped term, wrong index or sign, transposed operand) fails.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import ctd
+from oracle.philox import draw_u128
+from workloads import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dense(t):
+    X = np.zeros(t.dims)
+    X[tuple(t.idx.astype(np.int64))] = t.val
+    return X
+
+
+def _small(seed=7, dims=(30, 25, 12), nnz=900):
+    return synth.uniform_tensor(dims, nnz, seed)
+
+
+# --- Section 2.1: matricization and the n-mode product (Eqs. 2-3) ----------
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_matricization_matches_textbook_unfolding(mode):
+    t = _small()
+    u = ctd.unfold(t.dims, t.idx, t.val, mode)
+    X = _dense(t)
+    # textbook unfolding: mode-n index to rows, the rest column-major (Fortran order)
+    Xn = np.reshape(np.moveaxis(X, mode, 0), (t.dims[mode], -1), order="F")
+    full = np.zeros_like(Xn)
+    full[:, u.fids] = u.mat.toarray()
+    assert np.array_equal(full, Xn)
+    assert u.norm2 == pytest.approx(float(np.sum(X * X)), rel=1e-15)
+
+
+def test_n_mode_product_reconstruction():
+    """X~ = C x_alpha (R U) elementwise (Eq. 2) equals R U C_(alpha) (Eq. 3)."""
+    t = _small(seed=9)
+    mode = 0
+    r = ctd.ctd_s(t.dims, t.idx, t.val, mode, 40, seed=3, want_C=True)
+    I, J, K = t.dims
+    s_t = r.R.shape[1]
+    Cfull = np.zeros((s_t, J * K))
+    Cfull[:, r.unfolding.fids] = r.C
+    Ctensor = np.reshape(Cfull, (s_t, J, K), order="F")
+    RU = r.R @ r.U
+    Xt = np.einsum("ic,cjk->ijk", RU, Ctensor)
+    Xunf = np.reshape(Xt, (I, J * K), order="F")
+    assert np.allclose(Xunf[:, r.unfolding.fids], RU @ r.C, rtol=1e-12, atol=1e-12)
+    X = _dense(t)
+    err = float(np.sum((X - Xt) ** 2))
+    assert err == pytest.approx(r.err2, rel=1e-9)
+
+
+def test_matricization_rejects_bad_input():
+    t = _small()
+    bad = t.idx.copy()
+    bad[0, 0] = t.dims[0]
+    with pytest.raises(ValueError):
+        ctd.unfold(t.dims, bad, t.val, 0)
+    dup = np.concatenate([t.idx, t.idx[:, :1]], axis=1)
+    with pytest.raises(ValueError):
+        ctd.unfold(t.dims, dup, np.concatenate([t.val, t.val[:1]]), 0)
+    v = t.val.copy()
+    v[3] = np.nan
+    with pytest.raises(ValueError):
+        ctd.unfold(t.dims, t.idx, v, 0)
+    u = ctd.unfold(t.dims, t.idx, np.zeros_like(t.val), 0)
+    with pytest.raises(ValueError):
+        ctd.quantized_weights(u)
+    with pytest.raises(ValueError):
+        ctd.ctd_s(t.dims, t.idx, t.val, 0, 0, 0)
+    with pytest.raises(ValueError):
+        ctd.ctd_s(t.dims, t.idx, t.val, 0, t.dims[1] * t.dims[2] + 1, 0)
+
+
+# --- Algorithm 1 lines 2-3: column distribution and sampling ---------------
+
+def test_quantized_weights_exact_bound():
+    """Each fiber weight is within nnz_f of ||x_f||^2 * 2^sigma (exact rationals)."""
+    t = synth.power_law_tensor((40, 30, 10), 2000, 5, zipf_a=1.2)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    w, W = ctd.quantized_weights(u)
+    v2 = [Fraction(x) ** 2 for x in u.mat.data.tolist()]
+    vmax = max(v2)
+    e = math.frexp(float(vmax))[1]
+    assert Fraction(2) ** (e - 1) <= vmax < Fraction(2) ** e
+    sigma = 62 - (len(v2) - 1).bit_length() - e
+    assert W < 2 ** 62
+    assert W == sum(int(x) for x in w.tolist())
+    for j in range(u.n_f):
+        a, b = u.mat.indptr[j], u.mat.indptr[j + 1]
+        exact = sum(v2[a:b]) * Fraction(2) ** sigma
+        assert exact - (b - a) < int(w[j]) <= exact
+
+
+def test_draw_target_closed_forms():
+    """t = floor(r W / 2^128) hits the first and last positive-weight column at the extremes."""
+    w = np.array([0, 5, 0, 3, 7, 0], dtype=np.uint64)
+    W = 15
+    cdf = np.cumsum(w.astype(np.int64))
+    for r, expect in ((0, 1), ((1 << 128) - 1, 4)):
+        t = (r * W) >> 128
+        assert int(np.searchsorted(cdf, t, side="right")) == expect
+    # boundaries between columns: target t lands in column j iff cdf[j-1] <= t < cdf[j]
+    for t, expect in ((4, 1), (5, 3), (7, 3), (8, 4), (14, 4)):
+        assert int(np.searchsorted(cdf, t, side="right")) == expect
+
+
+def test_sampler_frequencies_match_exact_distribution():
+    """Brute force: draw frequencies over many counters against P(i) (chi-square)."""
+    t = synth.uniform_tensor((6, 4, 2), 20, 3)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    w, W = ctd.quantized_weights(u)
+    n = 40000
+    pos = ctd.sample_columns(w, W, n, seed=12345)
+    obs = np.bincount(pos, minlength=u.n_f)
+    col_norm2 = np.asarray(u.mat.multiply(u.mat).sum(axis=0)).ravel()
+    p = col_norm2 / col_norm2.sum()
+    exp = n * p
+    chi2 = float(np.sum((obs - exp) ** 2 / exp))
+    dof = u.n_f - 1
+    # p-value 1e-4 bound via Wilson-Hilferty
+    z = 3.72
+    bound = dof * (1 - 2 / (9 * dof) + z * math.sqrt(2 / (9 * dof))) ** 3
+    assert chi2 < bound, (chi2, bound)
+
+
+def test_zero_weight_columns_never_drawn():
+    w = np.array([0, 3, 0, 0, 9, 0], dtype=np.uint64)
+    pos = ctd.sample_columns(w, 12, 2000, seed=1)
+    assert set(np.unique(pos).tolist()) <= {1, 4}
+
+
+# --- Algorithm 1 line 4 and the duplicate-merge scale ----------------------
+
+def _cols(u, positions):
+    return np.stack([u.column(j) for j in positions], axis=1)
+
+
+def test_merge_scale_preserves_outer_product_sum():
+    t = synth.power_law_tensor((30, 20, 8), 600, 8, zipf_a=1.2)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    w, W = ctd.quantized_weights(u)
+    s = 60
+    pos = ctd.sample_columns(w, W, s, seed=4)
+    uniq, counts, p, omega = ctd.unique_with_scale(pos, w, W, s)
+    assert np.array_equal(uniq, np.unique(pos))
+    assert counts.sum() == s
+    D = _cols(u, pos)
+    pw = np.array([int(w[j]) / W for j in pos.tolist()])
+    lhs = (D / (s * pw)) @ D.T
+    Rp = _cols(u, uniq)
+    rhs = (Rp * omega ** 2) @ Rp.T
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12 * np.abs(lhs).max())
+
+
+def test_merged_estimator_is_unbiased():
+    """mean over seeds of R' Omega^2 R'^T approaches X_(alpha) X_(alpha)^T."""
+    t = synth.uniform_tensor((5, 4, 3), 25, 21)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    w, W = ctd.quantized_weights(u)
+    s, n_rep = 8, 3000
+    acc = []
+    for rep in range(n_rep):
+        pos = ctd.sample_columns(w, W, s, seed=1000 + rep)
+        uniq, counts, p, omega = ctd.unique_with_scale(pos, w, W, s)
+        Rp = _cols(u, uniq)
+        acc.append(((Rp * omega ** 2) @ Rp.T).ravel())
+    acc = np.array(acc)
+    mean = acc.mean(axis=0)
+    se = acc.std(axis=0) / math.sqrt(n_rep)
+    X = u.mat.toarray()
+    target = (X @ X.T).ravel()
+    assert np.all(np.abs(mean - target) <= 5 * se + 1e-12)
+
+
+def test_column_scaling_leaves_error_unchanged():
+    t = _small(seed=13)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    w, W = ctd.quantized_weights(u)
+    pos = ctd.sample_columns(w, W, 30, seed=2)
+    uniq, counts, p, omega = ctd.unique_with_scale(pos, w, W, 30)
+    R = _cols(u, uniq)
+    e1 = ctd.lstsq_error(R, u)
+    e2 = ctd.lstsq_error(R * omega, u)
+    assert e1 == pytest.approx(e2, rel=1e-10)
+
+
+# --- Algorithm 1 lines 5-15 and Lemma 2 ------------------------------------
+
+@pytest.mark.parametrize("seed,s", [(0, 10), (1, 40), (2, 120)])
+def test_lemma2_error_equals_least_squares(seed, s):
+    t = _small(seed=17 + seed)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    w, W = ctd.quantized_weights(u)
+    pos = ctd.sample_columns(w, W, s, seed=seed)
+    r = ctd.ctd_s_given(u, pos, w=w, W=W, s=s, residual="literal")
+    R0 = _cols(u, pos)                     # with duplicates, in draw order
+    e_ls = ctd.lstsq_error(R0, u)
+    assert r.err2 == pytest.approx(e_ls, rel=1e-9, abs=1e-12 * u.norm2)
+    rp = ctd.ctd_s_given(u, pos, w=w, W=W, s=s)
+    assert rp.err2 == pytest.approx(e_ls, rel=1e-9, abs=1e-12 * u.norm2)
+
+
+@pytest.mark.parametrize("dims,nnz,s", [((50, 40, 10), 3000, 80), ((300, 40, 10), 3000, 80)])
+def test_U_is_inverse_gram_and_R_holds_actual_fibers(dims, nnz, s):
+    t = synth.power_law_tensor(dims, nnz, 23, zipf_a=1.2)
+    r = ctd.ctd_s(t.dims, t.idx, t.val, 0, s, seed=5)
+    k = r.R.shape[1]
+    assert k <= dims[0]
+    assert np.linalg.matrix_rank(r.R) == k
+    G = r.R.T @ r.R
+    cond = np.linalg.cond(G)
+    assert np.linalg.norm(r.U @ G - np.eye(k)) <= 1e-13 * cond * k
+    u = r.unfolding
+    pos = np.searchsorted(u.fids, r.accepted)
+    assert np.array_equal(r.R, _cols(u, pos))
+    # the CTD-S error is the least-squares error (Lemma 2) in this regime as well
+    e_lit = ctd.error_literal(r.R, r.U, ctd.core_matrix(r.R, u), u)
+    assert e_lit == pytest.approx(r.err2, rel=1e-6, abs=1e-10 * u.norm2)
+
+
+def test_accepted_set_matches_greedy_rank_scan():
+    """Brute force: keep a candidate iff it raises the rank of the kept set."""
+    for seed in range(6):
+        t = synth.uniform_tensor((8, 5, 4), 30, 40 + seed)
+        u = ctd.unfold(t.dims, t.idx, t.val, 0)
+        w, W = ctd.quantized_weights(u)
+        pos = ctd.sample_columns(w, W, 15, seed=seed)
+        r = ctd.ctd_s_given(u, pos, w=w, W=W, s=15)
+        kept = []
+        for j in np.unique(pos).tolist():
+            M = _cols(u, kept + [j])
+            if np.linalg.matrix_rank(M, tol=1e-9) == len(kept) + 1:
+                kept.append(j)
+        assert np.array_equal(u.fids[kept], r.accepted)
+
+
+def test_residual_zero_when_all_fibers_drawn():
+    t = _small(seed=31, dims=(20, 15, 6), nnz=300)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    r = ctd.ctd_s_given(u, np.arange(u.n_f), s=u.n_f, residual="literal")
+    assert r.rel_err <= 1e-13
+    assert r.R.shape[1] == np.linalg.matrix_rank(u.mat.toarray())
+
+
+def test_planted_rank_is_recovered_exactly():
+    noisy, clean = synth.planted_low_rank(dims=(60, 50, 20), rank=5, seed=3,
+                                          factor_nnz=(12, 10, 4))
+    r = ctd.ctd_s(clean.dims, clean.idx, clean.val, 0, 200, seed=0)
+    assert r.R.shape[1] == 5
+    assert r.rel_err <= 1e-12
+    rn = ctd.ctd_s(noisy.dims, noisy.idx, noisy.val, 0, 200, seed=0)
+    # the noise floor: the projection can remove at most all of the signal
+    assert rn.rel_err <= 1.5 * 1e-4 * 1.01 + 0.5
+
+
+def test_figure2_example():
+    g = json.load(open(os.path.join(GOLDEN, "figure_examples.json")))["ctd_s"]
+    I, J, K = g["dims"]
+    idx, val = [], []
+    for name, col in g["column_of"].items():
+        for i, v in enumerate(g["fibers"][name]):
+            if v:
+                idx.append((i, col, 0))
+                val.append(v)
+    idx = np.array(idx).T.astype(np.int32)
+    u = ctd.unfold((I, J, K), idx, np.array(val), 0)
+    pos = [g["column_of"][n] for n in g["draws"]]
+    r = ctd.ctd_s_given(u, pos, s=len(pos))
+    assert r.uniq.tolist() == [g["column_of"][n] for n in g["expect_unique"]]
+    assert r.counts.tolist() == g["expect_counts"]
+    assert r.accepted.tolist() == [g["column_of"][n] for n in g["expect_kept"]]
+    assert r.rel_err == pytest.approx(g["expect_rel_err"], abs=1e-15)
+
+
+def test_draws_use_documented_counter_layout():
+    """Draw j of seed S at step t uses counter (j, j>>32, t, tensor) and key (S, S>>32)."""
+    from oracle.philox import philox4x32_10
+    seed = (7 << 32) | 99
+    x = philox4x32_10((5, 0, 3, 2), (99, 7))
+    assert draw_u128(seed, 5, 3, 2) == x[0] | (x[1] << 32) | (x[2] << 64) | (x[3] << 96)
