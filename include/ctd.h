@@ -1,0 +1,160 @@
+/*
+ * ctd.h — C ABI of the MI355X (gfx950) CTD library.
+ *
+ * CTD ("Compact Tensor Decomposition") approximates a sparse tensor X by a
+ * mode-alpha LR decomposition X ~ C x_alpha (R U) whose factor R holds
+ * actual, linearly independent mode-alpha fibers of X (Section 3 of the
+ * paper).  CTD-S (Section 3.1, Algorithm 1) decomposes a static tensor;
+ * CTD-D (Section 3.2, Algorithm 2) extends the factors with each arriving
+ * time slice.  This library runs the data-parallel path of both on one GPU:
+ * fiber keying, squared fiber norms, weighted sampling with replacement,
+ * unique selection, the independence filter, the projection of X_(alpha)
+ * onto span(R) and the Frobenius residual of Eq. 14.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Modes are 0-based: the paper's alpha = 1 is mode 0.
+ *  - Tensors arrive as COO ("sparse-unordered" storage, Section 2.1): a
+ *    device array of int32 indices laid out mode-major ([order][nnz]) and a
+ *    device array of nnz values, float64 or float32.  Coordinates must be
+ *    distinct and inside `dims`; values must be finite.
+ *  - Columns of X_(alpha) are numbered column-major over the other modes in
+ *    increasing mode order (fiber id f = sum_{m != alpha} i_m prod_{l<m,
+ *    l != alpha} I_l), so a new last-mode (time) slice appends trailing
+ *    columns.  The product of all mode lengths must stay below 2^62.
+ *  - Every call is asynchronous on the stream given to ctd_create.  Inputs
+ *    are borrowed: they must stay valid until the stream passes the call.
+ *    Results live in the handle until the next decompose/update/destroy.
+ *  - Arguments the host can check are checked at once (CTD_ERR_INVALID_ARG,
+ *    CTD_ERR_STATE).  Errors found by kernels (index out of range,
+ *    duplicate coordinate, non-finite value, zero norm) are latched on the
+ *    device and returned by ctd_sync / ctd_get_result.  After any error the
+ *    handle only accepts ctd_decompose, ctd_get_result, ctd_last_error and
+ *    ctd_destroy.
+ *  - Random draws are reproducible: draw j of a call uses Philox4x32-10
+ *    (Salmon et al., SC'11) with key (seed mod 2^32, seed >> 32) and counter
+ *    (j mod 2^32, j >> 32, step, tensor); step is 0 for ctd_decompose and t
+ *    for the t-th ctd_update after it; tensor is 0.
+ */
+#ifndef CTD_H_
+#define CTD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CTD_OK = 0,
+  CTD_ERR_INVALID_ARG = 1,  /* bad scalar argument (mode, sample size, order, dims, dtype) */
+  CTD_ERR_EMPTY = 2,        /* ||X||_F = 0: the column distribution of Algorithm 1 line 2 is undefined */
+  CTD_ERR_INDEX_OOB = 3,    /* a coordinate lies outside dims */
+  CTD_ERR_DUPLICATE = 4,    /* two nonzeros share a coordinate */
+  CTD_ERR_NONFINITE = 5,    /* a value is NaN or infinite */
+  CTD_ERR_OOM = 6,          /* device allocation failed */
+  CTD_ERR_HIP = 7,          /* a HIP runtime call failed */
+  CTD_ERR_STATE = 8,        /* call not valid in the handle's state (update before decompose, shape mismatch) */
+  CTD_ERR_CAPACITY = 9      /* a size exceeds a documented limit of this build */
+} ctd_status;
+
+enum { CTD_F64 = 0, CTD_F32 = 1 };                 /* value dtype of a ctd_coo */
+enum { CTD_PREC_FP64 = 0, CTD_PREC_MIXED = 1 };    /* arithmetic of the projection */
+
+/* A sparse tensor in COO form.  `dims` is a host array; `idx` and `val`
+ * are device arrays owned by the caller. */
+typedef struct {
+  int32_t order;            /* N, 2 <= N <= 8 */
+  const int64_t* dims;      /* host [order]: I_1 .. I_N, each >= 1 */
+  int64_t nnz;              /* number of stored entries, 0 <= nnz < 2^31 */
+  const int32_t* idx;       /* device [order * nnz]: idx[m * nnz + e] is the mode-m index of entry e */
+  const void* val;          /* device [nnz], float64 or float32 per val_dtype */
+  int32_t val_dtype;        /* CTD_F64 or CTD_F32 */
+} ctd_coo;
+
+typedef struct {
+  int32_t precision;        /* CTD_PREC_FP64 (all float64) or CTD_PREC_MIXED (float32 projection) */
+  double eps;               /* tolerance of the independence test, Algorithm 1 line 8 (the paper uses 1e-6) */
+  int32_t want_C;           /* CTD-S: also write C_(alpha) = R^T X_(alpha) (dense s~ x n_f) */
+  int32_t want_fiber_stats; /* also keep per-fiber ||x_f||^2 - ||P x_f||^2 */
+} ctd_options;
+
+/* Results of the last call.  Scalars are copies; pointers are device
+ * memory owned by the handle (valid until the next decompose/update/destroy). */
+typedef struct {
+  int64_t s;                /* number of draws of the last call */
+  int64_t s_unique;         /* s': unique drawn fibers */
+  int64_t s_tilde;          /* accepted fibers held in R (CTD-D: all steps) */
+  int64_t n_f;              /* non-empty fibers of the last input (CTD-D: of the slice) */
+  int64_t n_rows;           /* I_alpha */
+  int64_t step;             /* 0 after ctd_decompose, t after the t-th ctd_update */
+  uint64_t weight_total;    /* W, total integer sampling weight of the last input */
+  double norm2;             /* ||X||_F^2 (CTD-D: of all data seen) */
+  double err2;              /* ||X - X~||_F^2, Eq. 14 numerator */
+  double rel_err;           /* err2 / norm2, Eq. 14 */
+  double slice_err2;        /* CTD-D: ||dX - P dX||_F^2 of the last slice */
+  int32_t status;           /* latched device status (ctd_status) */
+  /* device arrays */
+  const uint64_t* draws;    /* [s] fiber ids in draw order */
+  const uint64_t* unique;   /* [s'] ascending unique fiber ids */
+  const int32_t* counts;    /* [s'] multiplicity of each unique fiber */
+  const double* prob;       /* [s'] quantized sampling probability w/W */
+  const double* scale;      /* [s'] duplicate-merge scale sqrt(k / (s p)) */
+  const uint64_t* accepted; /* [s~] fiber ids kept in R, in order of acceptance */
+  const double* Q;          /* [I_alpha x ldq] row-major orthonormal basis R L^{-T} */
+  int64_t ldq;
+  const double* Linv_t;     /* [s~ x ldx] row-major upper M with Q = R M: U = (R^T R)^{-1} = M M^T */
+  int64_t ldx;
+  const double* R;          /* [I_alpha x ldr] row-major kept fibers (the paper's R) */
+  int64_t ldr;
+  const double* C;          /* column-major C_(alpha), ldc rows per column: CTD-S n_f columns if
+                               want_C; CTD-D one column per non-empty fiber seen (n_cols) */
+  int64_t ldc;
+  int64_t n_cols;           /* columns of C */
+  const uint64_t* col_ids;  /* [n_cols] fiber id of each column of C */
+  const uint64_t* fiber_ids;/* [n_f] ascending non-empty fiber ids of the last input */
+  const double* fiber_resid;/* [n_f] ||x_f||^2 - ||P x_f||^2 if want_fiber_stats */
+} ctd_result;
+
+typedef struct ctd_handle ctd_handle;
+
+/* Create a handle bound to a HIP stream (NULL = default stream).  Options may
+ * be NULL (float64, eps 1e-6, no C).  Allocates device memory lazily. */
+ctd_status ctd_create(ctd_handle** out, const ctd_options* opt, void* hip_stream);
+
+/* CTD-S, Algorithm 1 (Section 3.1) on tensor X for mode `mode` with s draws
+ * (1 <= s <= N_alpha, the REQUIRE clause of Algorithm 1) and Philox seed
+ * `seed`.  Also starts a CTD-D stream whose time mode is the last mode. */
+ctd_status ctd_decompose(ctd_handle* h, const ctd_coo* X, int32_t mode, int64_t s, uint64_t seed);
+
+/* CTD-S from given draws instead of sampling (Lemma 2's "given R_0"):
+ * `draws` is a host array of s fiber ids of X_(alpha), repeats allowed;
+ * every id must name a non-empty fiber (else CTD_ERR_INVALID_ARG at sync). */
+ctd_status ctd_decompose_given(ctd_handle* h, const ctd_coo* X, int32_t mode,
+                               const uint64_t* draws, int64_t s);
+
+/* CTD-D, Algorithm 2 (Section 3.2): one time slice dX whose dims equal the
+ * stream's first N-1 dims with a last dim of 1, d draws (1 <= d <= dN_alpha).
+ * Requires a prior ctd_decompose with want_C set and a non-time mode. */
+ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d);
+
+/* Wait for the stream and return the latched device status. */
+ctd_status ctd_sync(ctd_handle* h);
+
+/* Wait for the stream and fill `out` (see ctd_result). */
+ctd_status ctd_get_result(ctd_handle* h, ctd_result* out);
+
+/* Message for the last error on this handle ("" if none). */
+const char* ctd_last_error(const ctd_handle* h);
+
+void ctd_destroy(ctd_handle* h);
+
+/* Limits of this build. */
+#define CTD_MAX_ORDER 8
+#define CTD_MAX_DRAWS 16384
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTD_H_ */

@@ -1,0 +1,440 @@
+// C ABI of the CTD library: argument checks, workspace, and the order in
+// which the kernels of one CTD-S decomposition (Algorithm 1) or one CTD-D
+// step (Algorithm 2) are enqueued.  Nothing here synchronizes except
+// ctd_sync / ctd_get_result; sizes known only on the device are bounded on
+// the host (s' <= s, s~ <= min(s', I_alpha), n_f <= nnz).
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "state.h"
+
+using namespace ctd;
+
+namespace ctd {
+
+void Arena::reset() { off = 0; }
+
+void* Arena::take(size_t bytes) {
+  const size_t a = (off + 255) & ~size_t(255);
+  off = a + ((bytes + 255) & ~size_t(255));
+  return (void*)a;  // offset, rebased in commit()
+}
+
+}  // namespace ctd
+
+namespace ctd {
+int bits_for(uint64_t n) {  // ceil(log2(n)) for n >= 1
+  return n <= 1 ? 0 : 64 - __builtin_clzll(n - 1);
+}
+// Host-side argument errors leave the handle usable; runtime, allocation and
+// device-detected errors put it into the failed state.
+ctd_status fail(ctd_handle* h, ctd_status st, const std::string& msg) {
+  if (h) {
+    h->last_error = msg;
+    if (st == CTD_ERR_HIP || st == CTD_ERR_OOM || st == CTD_ERR_INDEX_OOB ||
+        st == CTD_ERR_DUPLICATE || st == CTD_ERR_NONFINITE || st == CTD_ERR_EMPTY)
+      h->failed = true;
+  }
+  return st;
+}
+}  // namespace ctd
+
+namespace {
+
+#define HIP_TRY(h, expr)                                                         \
+  do {                                                                           \
+    hipError_t _e = (expr);                                                      \
+    if (_e != hipSuccess)                                                        \
+      return fail(h, CTD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+
+}  // namespace
+
+namespace ctd {
+__global__ void k_fill_u8(uint8_t* p, int64_t n_max, const DevScalars* sc) {
+  const int64_t n = std::min<int64_t>(n_max, sc->n_f);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout* lay,
+                     uint64_t* n_cols_total) {
+  if (!X) return fail(h, CTD_ERR_INVALID_ARG, "tensor is NULL");
+  if (X->order < 2 || X->order > CTD_MAX_ORDER)
+    return fail(h, CTD_ERR_INVALID_ARG, "order must be in [2, 8]");
+  if (!X->dims) return fail(h, CTD_ERR_INVALID_ARG, "dims is NULL");
+  if (mode < 0 || mode >= X->order) return fail(h, CTD_ERR_INVALID_ARG, "mode out of range");
+  if (X->nnz < 0 || X->nnz >= (int64_t)INT32_MAX)
+    return fail(h, CTD_ERR_INVALID_ARG, "nnz must be in [0, 2^31 - 1)");
+  if (X->nnz > 0 && (!X->idx || !X->val))
+    return fail(h, CTD_ERR_INVALID_ARG, "idx/val is NULL");
+  if (X->val_dtype != CTD_F64 && X->val_dtype != CTD_F32)
+    return fail(h, CTD_ERR_INVALID_ARG, "val_dtype must be CTD_F64 or CTD_F32");
+  unsigned __int128 total = 1;
+  uint64_t ncols = 1;
+  lay->order = X->order;
+  lay->mode = mode;
+  for (int m = 0; m < X->order; ++m) {
+    const int64_t d = X->dims[m];
+    if (d < 1 || d > (int64_t)INT32_MAX)
+      return fail(h, CTD_ERR_INVALID_ARG, "dims must be in [1, 2^31 - 1]");
+    total *= (unsigned __int128)d;
+    if (total >= ((unsigned __int128)1 << 62))
+      return fail(h, CTD_ERR_INVALID_ARG, "product of dims must stay below 2^62");
+    lay->dims[m] = d;
+  }
+  for (int m = 0; m < X->order; ++m) {
+    if (m == mode) {
+      lay->stride[m] = 0;
+      continue;
+    }
+    lay->stride[m] = (int64_t)ncols;
+    ncols *= (uint64_t)X->dims[m];
+  }
+  lay->n_rows = X->dims[mode];
+  lay->rbits = bits_for((uint64_t)X->dims[mode]);
+  *n_cols_total = ncols;
+  return CTD_OK;
+}
+
+int64_t round4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+// Plan the workspace of one CTD-S call (or one CTD-D slice) and bind pointers.
+ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
+                       bool want_C, StaticBufs* b) {
+  Arena& A = h->arena;
+  A.reset();
+  const int64_t n = std::max<int64_t>(nnz, 1);
+  const int64_t ld = round4(s);
+  const int64_t nb = (int64_t)segment_blocks(nnz);
+  struct Item { void** p; size_t bytes; };
+  std::vector<Item> items;
+  auto add = [&](void* pp, size_t bytes) { items.push_back({(void**)pp, bytes}); };
+  add(&b->keys, 2 * n * 8);
+  add(&b->perm, 2 * n * 4);
+  add(&b->hist, radix_sort_hist_elems(n) * 4);
+  add(&b->row, n * 4);
+  add(&b->val, n * 8);
+  add(&b->val32, mixed ? n * 4 : 4);
+  add(&b->qpref, n * 8);
+  add(&b->fptr, (n + 1) * 4);
+  add(&b->fid, n * 8);
+  add(&b->blk_cnt, (nb + 1) * 4);
+  add(&b->blk_q, (nb + 1) * 8);
+  add(&b->blk_v2, (nb + 1) * 8);
+  add(&b->draw_fi, s * 4);
+  add(&b->draw_fid, s * 8);
+  add(&b->uniq_fi, s * 4);
+  add(&b->uniq_fid, s * 8);
+  add(&b->counts, s * 4);
+  add(&b->prob, s * 8);
+  add(&b->scale, s * 8);
+  add(&b->P, n_rows * ld * 8);
+  add(&b->accept, s * 4);
+  add(&b->acc_fid, s * 8);
+  add(&b->M, s * ld * 8);
+  add(&b->scratch, basis_scratch_doubles(n_rows, ld) * 8);
+  add(&b->Q, n_rows * ld * 8);
+  add(&b->Qf, mixed ? n_rows * ld * 4 : 4);
+  add(&b->lev, n_rows * 8);
+  add(&b->fiber_mark, n);
+  add(&b->resid, n * 8);
+  add(&b->multi, n * 4);
+  add(&b->partial, ((n + 8191) / 8192 + 1) * 8);
+  add(&b->Rs, n_rows * ld * 8);
+  add(&b->C, want_C ? (size_t)ld * n * 8 : 8);
+  std::vector<size_t> offs;
+  for (auto& it : items) offs.push_back((size_t)A.take(it.bytes));
+  if (A.off > A.cap) {
+    if (A.base) {
+      (void)hipStreamSynchronize(h->stream);
+      (void)hipFree(A.base);
+      A.base = nullptr;
+      A.cap = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, A.off) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, CTD_ERR_OOM, "workspace allocation of " + std::to_string(A.off) + " bytes failed");
+    }
+    A.base = (char*)p;
+    A.cap = A.off;
+  }
+  for (size_t i = 0; i < items.size(); ++i) *items[i].p = (void*)(A.base + offs[i]);
+  b->ld = ld;
+  b->s_max = s;
+  return CTD_OK;
+}
+
+}  // namespace ctd
+
+namespace ctd {
+
+// A0-A3 on one COO input: keys, fiber-major layout, weights, draws (sampled
+// with Philox counter word `step`, or given) and the unique candidates.
+ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
+                         uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b) {
+  hipStream_t st = h->stream;
+  const bool mixed = h->opt.precision == CTD_PREC_MIXED;
+  const int64_t nnz = X->nnz;
+  DevScalars* sc = h->d_sc;
+  // A0: keys and fiber-major order
+  launch_build_keys(st, lay, X->idx, X->val, X->val_dtype, nnz, b.keys, b.perm, sc);
+  uint64_t n_cols = 1;
+  for (int m = 0; m < lay.order; ++m)
+    if (m != lay.mode) n_cols *= (uint64_t)lay.dims[m];
+  const int nbits = lay.rbits + bits_for(n_cols);
+  const int64_t n1 = std::max<int64_t>(nnz, 1);
+  const bool alt = radix_sort(st, b.keys, b.perm, b.keys + n1, b.perm + n1, nnz, nullptr, nbits,
+                              b.hist);
+  SegmentBuffers sb{};
+  sb.keys = alt ? b.keys + n1 : b.keys;
+  sb.perm = alt ? b.perm + n1 : b.perm;
+  sb.val_in = X->val;
+  sb.val_dtype = X->val_dtype;
+  sb.row = b.row;
+  sb.val = b.val;
+  sb.val32 = mixed ? b.val32 : nullptr;
+  sb.qpref = b.qpref;
+  sb.fptr = b.fptr;
+  sb.fid = b.fid;
+  sb.blk_cnt = b.blk_cnt;
+  sb.blk_q = b.blk_q;
+  sb.blk_v2 = b.blk_v2;
+  // A1: weights, norms; A2: prefix
+  launch_segment(st, sb, nnz, lay.rbits, sc);
+  hipLaunchKernelGGL(k_fill_u8, dim3(std::max(1, std::min(4096, div_up(nnz, 256)))), dim3(256), 0,
+                     st, b.fiber_mark, n1, sc);
+  // A2: draws
+  if (given) {
+    HIP_TRY(h, hipMemcpyAsync(b.draw_fid, given, s * 8, hipMemcpyHostToDevice, st));
+    launch_locate_given(st, b.fid, s, b.draw_fid, b.draw_fi, sc);
+  } else {
+    launch_draws(st, b.qpref, b.fptr, b.fid, nnz, s, seed, step, 0u, b.draw_fi, b.draw_fid, sc);
+  }
+  // A3: unique
+  launch_unique(st, b.draw_fi, s, b.qpref, b.fptr, b.fid, b.uniq_fi, b.uniq_fid, b.counts, b.prob,
+                b.scale, sc);
+  return CTD_OK;
+}
+
+int key_bits(const FiberLayout& lay) {
+  uint64_t n_cols = 1;
+  for (int m = 0; m < lay.order; ++m)
+    if (m != lay.mode) n_cols *= (uint64_t)lay.dims[m];
+  return lay.rbits + bits_for(n_cols);
+}
+
+ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const float* Qf,
+                         int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max) {
+  const bool mixed = h->opt.precision == CTD_PREC_MIXED;
+  ProjectArgs pa{};
+  pa.fptr = b.fptr;
+  pa.row = b.row;
+  pa.val = b.val;
+  pa.val32 = mixed ? b.val32 : nullptr;
+  pa.Q = Q;
+  pa.Qf = mixed ? Qf : nullptr;
+  pa.ldq = ldq;
+  pa.lev = lev;
+  pa.fiber_mark = b.fiber_mark;
+  pa.d_ncols = d_ncols;
+  pa.ncols_max = ncols_max;
+  pa.resid = b.resid;
+  pa.multi = b.multi;
+  pa.partial = b.partial;
+  pa.mixed = mixed;
+  return pa;
+}
+
+}  // namespace ctd
+
+namespace {
+
+// Enqueue CTD-S on `lay`/`X`; draws either sampled (given == nullptr) or given.
+ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
+                      uint64_t seed, const uint64_t* given) {
+  hipStream_t st = h->stream;
+  const bool mixed = h->opt.precision == CTD_PREC_MIXED;
+  const bool want_C = h->opt.want_C != 0;
+  const int64_t nnz = X->nnz;
+  const int64_t n_rows = lay.n_rows;
+  StaticBufs& b = h->sb;
+  ctd_status rc = plan_static(h, nnz, s, n_rows, mixed, want_C, &b);
+  if (rc != CTD_OK) return rc;
+  DevScalars* sc = h->d_sc;
+  launch_reset_scalars(st, sc, false);
+  rc = enqueue_input(h, X, lay, s, seed, 0u, given, b);
+  if (rc != CTD_OK) return rc;
+  // A4: candidate panel
+  launch_panel(st, b.uniq_fi, s, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
+  // A5-A7: independence filter and orthonormal basis, block by block
+  BasisArgs ba{};
+  ba.P = b.P;
+  ba.ldp = b.ld;
+  ba.n_rows = n_rows;
+  ba.s_max = s;
+  ba.uniq_fi = b.uniq_fi;
+  ba.uniq_fid = b.uniq_fid;
+  ba.fptr = b.fptr;
+  ba.row = b.row;
+  ba.val = b.val;
+  ba.Q = b.Q;
+  ba.ldq = b.ld;
+  ba.Qf = mixed ? b.Qf : nullptr;
+  ba.R = b.Rs;
+  ba.ldr = b.ld;
+  ba.M = b.M;
+  ba.ldm = b.ld;
+  ba.lev = b.lev;
+  ba.lev_accumulate = false;
+  ba.eps2 = h->opt.eps * h->opt.eps;
+  ba.accept = b.accept;
+  ba.acc_fid = b.acc_fid;
+  ba.acc_fi_local = nullptr;
+  ba.fiber_mark = b.fiber_mark;
+  ba.id_offset = 0;
+  ba.Wacc = nullptr;
+  ba.ldwa = 0;
+  ba.scratch = b.scratch;
+  ba.cap = b.ld;
+  launch_basis(st, ba, sc);
+  // A8: projection and residual
+  ProjectArgs pa = project_args(h, b, b.Q, b.Qf, b.ld, b.lev, &sc->s_tilde, s);
+  launch_project(st, pa, nnz, sc);
+  if (want_C) launch_core_static(st, b, n_rows, nnz, sc);
+  launch_static_totals(st, sc);
+  HIP_TRY(h, hipGetLastError());
+  h->s = s;
+  h->n_rows = n_rows;
+  h->step = 0;
+  h->has_static = true;
+  h->last_was_update = false;
+  h->mode = lay.mode;
+  h->layout = lay;
+  return CTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ctd_status ctd_create(ctd_handle** out, const ctd_options* opt, void* hip_stream) {
+  if (!out) return CTD_ERR_INVALID_ARG;
+  ctd_handle* h = new ctd_handle();
+  h->stream = (hipStream_t)hip_stream;
+  h->opt.precision = CTD_PREC_FP64;
+  h->opt.eps = 1e-6;
+  h->opt.want_C = 0;
+  h->opt.want_fiber_stats = 0;
+  if (opt) {
+    if (opt->precision != CTD_PREC_FP64 && opt->precision != CTD_PREC_MIXED) {
+      delete h;
+      return CTD_ERR_INVALID_ARG;
+    }
+    if (!(opt->eps >= 0.0) || opt->eps >= 1.0) {
+      delete h;
+      return CTD_ERR_INVALID_ARG;
+    }
+    h->opt = *opt;
+  }
+  if (hipMalloc(&h->d_sc, sizeof(DevScalars)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    return CTD_ERR_OOM;
+  }
+  (void)hipMemsetAsync(h->d_sc, 0, sizeof(DevScalars), h->stream);
+  *out = h;
+  return CTD_OK;
+}
+
+ctd_status ctd_decompose(ctd_handle* h, const ctd_coo* X, int32_t mode, int64_t s, uint64_t seed) {
+  if (!h) return CTD_ERR_INVALID_ARG;
+  h->last_error.clear();
+  (void)hipGetLastError();
+  FiberLayout lay{};
+  uint64_t ncols = 0;
+  ctd_status rc = check_coo(h, X, mode, &lay, &ncols);
+  if (rc != CTD_OK) return rc;
+  if (s < 1 || (uint64_t)s > ncols)
+    return fail(h, CTD_ERR_INVALID_ARG, "sample size must be in [1, N_alpha]");
+  if (s > CTD_MAX_DRAWS)
+    return fail(h, CTD_ERR_CAPACITY, "sample size above CTD_MAX_DRAWS");
+  if (X->nnz == 0) return fail(h, CTD_ERR_EMPTY, "tensor has no nonzeros");
+  h->failed = false;
+  h->has_static = false;
+  h->dyn_ready = false;
+  h->seed = seed;
+  rc = run_static(h, X, lay, s, seed, nullptr);
+  if (rc == CTD_OK && h->opt.want_C) rc = dyn_begin(h, X);
+  return rc;
+}
+
+ctd_status ctd_decompose_given(ctd_handle* h, const ctd_coo* X, int32_t mode,
+                               const uint64_t* draws, int64_t s) {
+  if (!h) return CTD_ERR_INVALID_ARG;
+  h->last_error.clear();
+  (void)hipGetLastError();
+  FiberLayout lay{};
+  uint64_t ncols = 0;
+  ctd_status rc = check_coo(h, X, mode, &lay, &ncols);
+  if (rc != CTD_OK) return rc;
+  if (!draws || s < 1) return fail(h, CTD_ERR_INVALID_ARG, "draws must be a non-empty host array");
+  if (s > CTD_MAX_DRAWS) return fail(h, CTD_ERR_CAPACITY, "sample size above CTD_MAX_DRAWS");
+  for (int64_t j = 0; j < s; ++j)
+    if (draws[j] >= ncols) return fail(h, CTD_ERR_INVALID_ARG, "draw outside [0, N_alpha)");
+  if (X->nnz == 0) return fail(h, CTD_ERR_EMPTY, "tensor has no nonzeros");
+  h->failed = false;
+  h->has_static = false;
+  h->dyn_ready = false;
+  h->given.assign(draws, draws + s);
+  h->seed = 0;
+  rc = run_static(h, X, lay, s, 0, h->given.data());
+  if (rc == CTD_OK && h->opt.want_C) rc = dyn_begin(h, X);
+  return rc;
+}
+
+ctd_status ctd_sync(ctd_handle* h) {
+  if (!h) return CTD_ERR_INVALID_ARG;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  DevScalars sc{};
+  HIP_TRY(h, hipMemcpy(&sc, h->d_sc, sizeof(sc), hipMemcpyDeviceToHost));
+  if (sc.status != 0) {
+    h->failed = true;
+    if (h->last_error.empty()) h->last_error = "device reported status " + std::to_string(sc.status);
+    return (ctd_status)sc.status;
+  }
+  return CTD_OK;
+}
+
+ctd_status ctd_get_result(ctd_handle* h, ctd_result* out) {
+  if (!h || !out) return CTD_ERR_INVALID_ARG;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  DevScalars sc{};
+  HIP_TRY(h, hipMemcpy(&sc, h->d_sc, sizeof(sc), hipMemcpyDeviceToHost));
+  memset(out, 0, sizeof(*out));
+  fill_result(h, sc, out);
+  if (sc.status != 0) {
+    h->failed = true;
+    return (ctd_status)sc.status;
+  }
+  return CTD_OK;
+}
+
+const char* ctd_last_error(const ctd_handle* h) { return h ? h->last_error.c_str() : "null handle"; }
+
+void ctd_destroy(ctd_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  dyn_free(h);
+  if (h->arena.base) (void)hipFree(h->arena.base);
+  if (h->d_sc) (void)hipFree(h->d_sc);
+  delete h;
+}
+
+}  // extern "C"

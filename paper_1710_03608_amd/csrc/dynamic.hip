@@ -1,0 +1,507 @@
+// CTD-D (Section 3.2, Algorithm 2) and the core tensor C of CTD-S
+// (Algorithm 1 line 16).
+//
+// State kept between slices (all device memory):
+//   Rs  n_rows x capD  the kept fibers (the paper's R), row-major
+//   Q   n_rows x capD  orthonormal basis of span(R)
+//   Xt  capD x capD    upper triangular M with Q = R M, so U = (R^T R)^{-1} = M M^T
+//   C   capD x capN    C_(alpha) = R^T X_(alpha), column-major, one column per
+//                      non-empty fiber seen so far (tensor then slices)
+// One slice dX with d draws:
+//   1. fibers, weights, draws (Philox counter word = step t), unique
+//      candidates: the same kernels as CTD-S (Algorithm 2 lines 1-4);
+//   2. the candidates are tested against R^(t) and each other and the kept
+//      ones extend R, Q and M: the same block filter as CTD-S, started from
+//      the d~_t columns already held (lines 5-16);
+//   3. C (lines 17-21, Eq. 13): rows for the kept fibers over the earlier
+//      columns are ((dR^T R^(t)) U^(t)) C^(t), parenthesized from the left as
+//      the paper prescribes; with w = Q^(t)T x the row vector dR^T R^(t) U^(t)
+//      equals (M^(t) w)^T, so one pass over C^(t) applies them; the new
+//      columns are R^(t+1)T dX;
+//   4. error: earlier columns keep their reconstruction (span(R) only grows),
+//      so ||X^(t+1) - X~^(t+1)||^2 = E^(t) + ||dX - P_{t+1} dX||^2, the slice
+//      term computed by the CTD-S projection kernels with the grown Q.
+#include <string.h>
+
+#include <string>
+
+#include "state.h"
+
+namespace ctd {
+
+namespace {
+constexpr int kBlock = 256;
+
+__global__ void k_reset(DevScalars* sc, bool keep_stream) {
+  if (threadIdx.x != 0) return;
+  DevScalars old = *sc;
+  *sc = DevScalars{};
+  if (keep_stream) {
+    sc->total_norm2 = old.total_norm2;
+    sc->total_err2 = old.total_err2;
+    sc->n_accept_total = old.n_accept_total;
+    sc->n_cols_total = old.n_cols_total;
+    sc->allow_empty = 1;
+  }
+}
+
+__global__ void k_static_totals(DevScalars* sc) {
+  sc->total_norm2 = sc->norm2;
+  sc->total_err2 = sc->err2;
+  sc->n_accept_total = sc->s_tilde;
+  sc->n_cols_total = sc->n_f;
+}
+
+// One wave per fiber f < n_f: out[(col0 + f) * ldo + k] = sum_e v_e M[r_e][k], k < ncols.
+__global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict__ fptr,
+                                                      const int32_t* __restrict__ row,
+                                                      const double* __restrict__ val,
+                                                      const DevScalars* sc,
+                                                      const double* __restrict__ M, int64_t ldm,
+                                                      const int32_t* d_ncols,
+                                                      double* __restrict__ out, int64_t ldo,
+                                                      const int64_t* d_col0) {
+  const int64_t n_f = sc->status == 0 ? sc->n_f : 0;
+  const int64_t ncols = *d_ncols;
+  const int64_t col0 = d_col0 ? *d_col0 : 0;
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t f = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; f < n_f; f += nwaves) {
+    const int32_t e0 = fptr[f], e1 = fptr[f + 1];
+    double* o = out + (col0 + f) * ldo;
+    for (int64_t c0 = 0; c0 < ncols; c0 += 4 * kWave) {
+      const int64_t c = c0 + 4 * lane;
+      double a[4] = {0, 0, 0, 0};
+      if (c < ncols) {
+        for (int32_t e = e0; e < e1; ++e) {
+          const double v = val[e];
+          const double* mr = M + (int64_t)row[e] * ldm + c;
+          const double2 x = *(const double2*)mr;
+          const double2 y = *(const double2*)(mr + 2);
+          a[0] += v * x.x;
+          a[1] += v * x.y;
+          a[2] += v * y.x;
+          a[3] += v * y.y;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (c + k < ncols) o[c + k] = a[k];
+    }
+  }
+}
+
+// Rows of ((dR^T R^(t)) U^(t)): Y[a][c] = sum_{c <= j < d} M[c][j] Wacc[a][j]
+// for c < d = d~_t (columns held before the slice); one wave per row c of M.
+__global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict__ M, int64_t ldm,
+                                                       const double* __restrict__ Wacc,
+                                                       int64_t ldw, double* __restrict__ Y,
+                                                       int64_t ldy, const DevScalars* sc) {
+  const int64_t d = sc->base_accept;
+  const int64_t na = sc->s_tilde;
+  const int lane = lane_id();
+  const int64_t c = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  if (c >= d) return;
+  const double* mr = M + c * ldm;
+  for (int64_t a = 0; a < na; ++a) {
+    const double* w = Wacc + a * ldw;
+    double s = 0.0;
+    for (int64_t j = c + lane; j < d; j += kWave) s += mr[j] * w[j];
+    s = wave_sum(s);
+    if (lane == 0) Y[a * ldy + c] = s;
+  }
+}
+
+// Cross term: C[d + a][f] = sum_{k<d} Y[a][k] C[k][f] for the columns held
+// before this slice; one wave per column, up to 8 new rows per pass.
+__global__ __launch_bounds__(kBlock) void k_cross_term(double* __restrict__ C, int64_t ldc,
+                                                       const double* __restrict__ Y, int64_t ldy,
+                                                       const DevScalars* sc) {
+  const int64_t d = sc->base_accept;
+  const int64_t na = sc->s_tilde;
+  const int64_t ncols = sc->n_cols_total;
+  if (na == 0) return;
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t f = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; f < ncols; f += nwaves) {
+    double* col = C + f * ldc;
+    for (int64_t a0 = 0; a0 < na; a0 += 8) {
+      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int64_t k = lane; k < d; k += kWave) {
+        const double cv = col[k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (a0 + u < na) acc[u] += Y[(a0 + u) * ldy + k] * cv;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double s = wave_sum(acc[u]);
+        if (lane == 0 && a0 + u < na) col[d + a0 + u] = s;
+      }
+    }
+  }
+}
+
+__global__ void k_append_ids(const uint64_t* __restrict__ src, const int32_t* d_count,
+                             uint64_t* __restrict__ dst, const int32_t* d_off32,
+                             const int64_t* d_off64, uint64_t add) {
+  const int64_t n = *d_count;
+  const int64_t off = d_off32 ? (int64_t)*d_off32 : *d_off64;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[off + i] = src[i] + add;
+}
+
+__global__ void k_finish_slice(DevScalars* sc) {
+  sc->total_norm2 += sc->norm2;
+  sc->total_err2 += sc->err2;
+  sc->n_cols_total += sc->n_f;
+}
+
+int grid_for(int64_t work, int per = kBlock) {
+  return std::max(1, std::min(8192, div_up(std::max<int64_t>(work, 1), per)));
+}
+
+#define HIP_CHECK(h, expr)                                                            \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess)                                                             \
+      return fail(h, CTD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// (Re)allocate the CTD-D state with the given capacities, keeping contents.
+ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
+  DynState& S = h->dyn;
+  const int64_t n_rows = h->n_rows;
+  const bool mixed = h->opt.precision == CTD_PREC_MIXED;
+  capD = std::min<int64_t>(round4(capD), round4(n_rows));
+  if (capD <= S.capD && capN <= S.capN) return CTD_OK;
+  capD = std::max(capD, S.capD);
+  capN = std::max(capN, S.capN);
+  HIP_CHECK(h, hipStreamSynchronize(h->stream));
+  DynState N = S;
+  N.capD = capD;
+  N.capN = capN;
+  auto alloc = [&](void** p, size_t bytes) -> bool {
+    if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
+  };
+  bool ok = true;
+  ok = ok && alloc((void**)&N.Rs, n_rows * capD * 8);
+  ok = ok && alloc((void**)&N.Q, n_rows * capD * 8);
+  if (mixed) ok = ok && alloc((void**)&N.Qf, n_rows * capD * 4);
+  ok = ok && alloc((void**)&N.Xt, capD * capD * 8);
+  ok = ok && alloc((void**)&N.C, (size_t)capD * capN * 8);
+  ok = ok && alloc((void**)&N.acc_fid, capD * 8);
+  ok = ok && alloc((void**)&N.col_fid, capN * 8);
+  if (!S.lev) ok = ok && alloc((void**)&N.lev, n_rows * 8);
+  if (!ok) {
+    (void)hipFree(N.Rs);
+    (void)hipFree(N.Q);
+    if (mixed) (void)hipFree(N.Qf);
+    (void)hipFree(N.Xt);
+    (void)hipFree(N.C);
+    (void)hipFree(N.acc_fid);
+    (void)hipFree(N.col_fid);
+    if (!S.lev) (void)hipFree(N.lev);
+    return fail(h, CTD_ERR_OOM, "CTD-D state allocation failed");
+  }
+  if (S.capD) {
+    const int64_t dr = S.d_tilde, nc = S.n_cols;
+    HIP_CHECK(h, hipMemcpy2DAsync(N.Rs, capD * 8, S.Rs, S.capD * 8, dr * 8, n_rows,
+                                  hipMemcpyDeviceToDevice, h->stream));
+    HIP_CHECK(h, hipMemcpy2DAsync(N.Q, capD * 8, S.Q, S.capD * 8, dr * 8, n_rows,
+                                  hipMemcpyDeviceToDevice, h->stream));
+    if (mixed)
+      HIP_CHECK(h, hipMemcpy2DAsync(N.Qf, capD * 4, S.Qf, S.capD * 4, dr * 4, n_rows,
+                                    hipMemcpyDeviceToDevice, h->stream));
+    HIP_CHECK(h, hipMemcpy2DAsync(N.Xt, capD * 8, S.Xt, S.capD * 8, dr * 8, dr,
+                                  hipMemcpyDeviceToDevice, h->stream));
+    if (nc > 0)
+      HIP_CHECK(h, hipMemcpy2DAsync(N.C, capD * 8, S.C, S.capD * 8, dr * 8, nc,
+                                    hipMemcpyDeviceToDevice, h->stream));
+    HIP_CHECK(h, hipMemcpyAsync(N.acc_fid, S.acc_fid, dr * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (nc > 0)
+      HIP_CHECK(h, hipMemcpyAsync(N.col_fid, S.col_fid, nc * 8, hipMemcpyDeviceToDevice, h->stream));
+    HIP_CHECK(h, hipStreamSynchronize(h->stream));
+    (void)hipFree(S.Rs);
+    (void)hipFree(S.Q);
+    if (S.Qf) (void)hipFree(S.Qf);
+    (void)hipFree(S.Xt);
+    (void)hipFree(S.C);
+    (void)hipFree(S.acc_fid);
+    (void)hipFree(S.col_fid);
+  }
+  S = N;
+  return CTD_OK;
+}
+
+ctd_status dyn_sync_sizes(ctd_handle* h) {
+  DevScalars sc{};
+  HIP_CHECK(h, hipStreamSynchronize(h->stream));
+  HIP_CHECK(h, hipMemcpy(&sc, h->d_sc, sizeof(sc), hipMemcpyDeviceToHost));
+  if (sc.status != 0) return fail(h, (ctd_status)sc.status, "device reported an error");
+  h->dyn.d_tilde = sc.n_accept_total;
+  h->dyn.n_cols = sc.n_cols_total;
+  h->dyn.d_ub = sc.n_accept_total;
+  h->dyn.n_cols_ub = sc.n_cols_total;
+  return CTD_OK;
+}
+
+}  // namespace
+
+void launch_reset_scalars(hipStream_t st, DevScalars* sc, bool keep_stream) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, sc, keep_stream);
+}
+
+void launch_static_totals(hipStream_t st, DevScalars* sc) {
+  hipLaunchKernelGGL(k_static_totals, dim3(1), dim3(1), 0, st, sc);
+}
+
+// C = R_S^T X_(alpha) for CTD-S (column-major, ld = b.ld).
+void launch_core_static(hipStream_t st, StaticBufs& b, int64_t n_rows, int64_t nnz_max,
+                        DevScalars* sc) {
+  (void)n_rows;
+  hipLaunchKernelGGL(k_spmm_cols, dim3(grid_for(nnz_max * kWave)), dim3(kBlock), 0, st, b.fptr,
+                     b.row, b.val, sc, b.Rs, b.ld, &sc->s_tilde, b.C, b.ld, nullptr);
+}
+
+ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X) {
+  const FiberLayout& lay = h->layout;
+  if (lay.mode == lay.order - 1) return CTD_OK;  // no time mode left for CTD-D
+  StaticBufs& b = h->sb;
+  DevScalars sc{};
+  HIP_CHECK(h, hipStreamSynchronize(h->stream));
+  HIP_CHECK(h, hipMemcpy(&sc, h->d_sc, sizeof(sc), hipMemcpyDeviceToHost));
+  if (sc.status != 0) return fail(h, (ctd_status)sc.status, "device reported an error");
+  const int64_t st = sc.s_tilde, nf = sc.n_f;
+  DynState& S = h->dyn;
+  dyn_free(h);
+  S = DynState{};
+  const int64_t capD = std::max<int64_t>(2 * h->s + 256, st + 64);
+  const int64_t capN = nf + std::max<int64_t>(nf, 1 << 16);
+  ctd_status rc = dyn_reserve(h, capD, capN);
+  if (rc != CTD_OK) return rc;
+  const bool mixed = h->opt.precision == CTD_PREC_MIXED;
+  const int64_t n_rows = h->n_rows;
+  HIP_CHECK(h, hipMemcpy2DAsync(S.Rs, S.capD * 8, b.Rs, b.ld * 8, st * 8, n_rows,
+                                hipMemcpyDeviceToDevice, h->stream));
+  HIP_CHECK(h, hipMemcpy2DAsync(S.Q, S.capD * 8, b.Q, b.ld * 8, st * 8, n_rows,
+                                hipMemcpyDeviceToDevice, h->stream));
+  if (mixed)
+    HIP_CHECK(h, hipMemcpy2DAsync(S.Qf, S.capD * 4, b.Qf, b.ld * 4, st * 4, n_rows,
+                                  hipMemcpyDeviceToDevice, h->stream));
+  HIP_CHECK(h, hipMemcpy2DAsync(S.Xt, S.capD * 8, b.M, b.ld * 8, st * 8, st,
+                                hipMemcpyDeviceToDevice, h->stream));
+  HIP_CHECK(h, hipMemcpy2DAsync(S.C, S.capD * 8, b.C, b.ld * 8, st * 8, nf,
+                                hipMemcpyDeviceToDevice, h->stream));
+  HIP_CHECK(h, hipMemcpyAsync(S.lev, b.lev, n_rows * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_CHECK(h, hipMemcpyAsync(S.acc_fid, b.acc_fid, st * 8, hipMemcpyDeviceToDevice, h->stream));
+  HIP_CHECK(h, hipMemcpyAsync(S.col_fid, b.fid, nf * 8, hipMemcpyDeviceToDevice, h->stream));
+  S.d_tilde = S.d_ub = st;
+  S.n_cols = S.n_cols_ub = nf;
+  S.T = lay.dims[lay.order - 1];
+  int64_t dN = 1;
+  for (int m = 0; m < lay.order - 1; ++m)
+    if (m != lay.mode) dN *= lay.dims[m];
+  S.dN = dN;
+  h->dyn_ready = true;
+  (void)X;
+  return CTD_OK;
+}
+
+void dyn_free(ctd_handle* h) {
+  DynState& S = h->dyn;
+  if (S.Rs) (void)hipFree(S.Rs);
+  if (S.Q) (void)hipFree(S.Q);
+  if (S.Qf) (void)hipFree(S.Qf);
+  if (S.Xt) (void)hipFree(S.Xt);
+  if (S.C) (void)hipFree(S.C);
+  if (S.lev) (void)hipFree(S.lev);
+  if (S.acc_fid) (void)hipFree(S.acc_fid);
+  if (S.col_fid) (void)hipFree(S.col_fid);
+  if (S.ws) (void)hipFree(S.ws);
+  S = DynState{};
+  h->dyn_ready = false;
+}
+
+void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out) {
+  const StaticBufs& b = h->sb;
+  out->s = h->s;
+  out->s_unique = sc.s_unique;
+  out->n_f = sc.n_f;
+  out->n_rows = h->n_rows;
+  out->step = h->step;
+  out->weight_total = sc.W;
+  out->norm2 = sc.total_norm2;
+  out->err2 = sc.total_err2;
+  out->rel_err = sc.total_norm2 > 0 ? sc.total_err2 / sc.total_norm2 : 0.0;
+  out->slice_err2 = sc.err2;
+  out->status = sc.status;
+  out->draws = b.draw_fid;
+  out->unique = b.uniq_fid;
+  out->counts = b.counts;
+  out->prob = b.prob;
+  out->scale = b.scale;
+  out->fiber_ids = b.fid;
+  out->fiber_resid = h->opt.want_fiber_stats ? b.resid : nullptr;
+  if (h->last_was_update && h->dyn_ready) {
+    const DynState& S = h->dyn;
+    out->s_tilde = sc.n_accept_total;
+    out->accepted = S.acc_fid;
+    out->Q = S.Q;
+    out->ldq = S.capD;
+    out->Linv_t = S.Xt;
+    out->ldx = S.capD;
+    out->R = S.Rs;
+    out->ldr = S.capD;
+    out->C = S.C;
+    out->ldc = S.capD;
+    out->n_cols = sc.n_cols_total;
+    out->col_ids = S.col_fid;
+  } else {
+    out->s_tilde = sc.s_tilde;
+    out->accepted = b.acc_fid;
+    out->Q = b.Q;
+    out->ldq = b.ld;
+    out->Linv_t = b.M;
+    out->ldx = b.ld;
+    out->R = b.Rs;
+    out->ldr = b.ld;
+    out->C = h->opt.want_C ? b.C : nullptr;
+    out->ldc = b.ld;
+    out->n_cols = sc.n_f;
+    out->col_ids = b.fid;
+  }
+}
+
+}  // namespace ctd
+
+using namespace ctd;
+
+extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d) {
+  if (!h) return CTD_ERR_INVALID_ARG;
+  h->last_error.clear();
+  (void)hipGetLastError();
+  if (h->failed) return fail(h, CTD_ERR_STATE, "handle is in a failed state; call ctd_decompose");
+  if (!h->dyn_ready)
+    return fail(h, CTD_ERR_STATE, "ctd_update needs a prior ctd_decompose with want_C on a non-time mode");
+  const FiberLayout& full = h->layout;
+  if (!slice || slice->order != full.order)
+    return fail(h, CTD_ERR_STATE, "slice order differs from the stream's");
+  for (int m = 0; m < full.order - 1; ++m)
+    if (slice->dims[m] != full.dims[m]) return fail(h, CTD_ERR_STATE, "slice dims differ from the stream's");
+  if (slice->dims[full.order - 1] != 1) return fail(h, CTD_ERR_STATE, "slice time dim must be 1");
+  FiberLayout lay{};
+  uint64_t ncols = 0;
+  ctd_status rc = check_coo(h, slice, full.mode, &lay, &ncols);
+  if (rc != CTD_OK) return rc;
+  if (d < 1 || (uint64_t)d > ncols) return fail(h, CTD_ERR_INVALID_ARG, "d must be in [1, dN_alpha]");
+  if (d > CTD_MAX_DRAWS) return fail(h, CTD_ERR_CAPACITY, "d above CTD_MAX_DRAWS");
+  hipStream_t st = h->stream;
+  DynState& S = h->dyn;
+  const int64_t nnz = slice->nnz;
+  const int64_t n_rows = h->n_rows;
+  const bool mixed = h->opt.precision == CTD_PREC_MIXED;
+  const uint32_t step = (uint32_t)(h->step + 1);
+  DevScalars* sc = h->d_sc;
+  // capacities (host upper bounds; exact sizes only at a sync)
+  const int64_t need_d = std::min<int64_t>(n_rows, S.d_ub + d);
+  const int64_t need_n = S.n_cols_ub + nnz;
+  if (need_d > S.capD || need_n > S.capN) {
+    rc = dyn_sync_sizes(h);
+    if (rc != CTD_OK) return rc;
+    const int64_t nd = std::min<int64_t>(n_rows, S.d_tilde + d);
+    const int64_t nn = S.n_cols + nnz;
+    if (nd > S.capD || nn > S.capN) {
+      rc = dyn_reserve(h, nd > S.capD ? std::max(nd, 2 * S.capD) : S.capD,
+                       nn > S.capN ? std::max(nn, S.capN + S.capN / 2) : S.capN);
+      if (rc != CTD_OK) return rc;
+    }
+  }
+  StaticBufs& b = h->sb;
+  rc = plan_static(h, nnz, d, n_rows, mixed, false, &b);
+  if (rc != CTD_OK) return rc;
+  // per-slice workspace: block-filter scratch, kept W rows, cross rows
+  const size_t ws_doubles = basis_scratch_doubles(n_rows, S.capD) + (size_t)2 * d * S.capD + 64;
+  if (ws_doubles * 8 > S.ws_bytes) {
+    if (S.ws) {
+      HIP_CHECK(h, hipStreamSynchronize(st));
+      (void)hipFree(S.ws);
+      S.ws = nullptr;
+    }
+    if (hipMalloc(&S.ws, ws_doubles * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      S.ws_bytes = 0;
+      return fail(h, CTD_ERR_OOM, "CTD-D workspace allocation failed");
+    }
+    S.ws_bytes = ws_doubles * 8;
+  }
+  double* scratch = (double*)S.ws;
+  double* Wacc = scratch + basis_scratch_doubles(n_rows, S.capD);
+  double* Y = Wacc + (size_t)d * S.capD;
+
+  launch_reset_scalars(st, sc, true);
+  const uint64_t t_off = (uint64_t)S.T * (uint64_t)S.dN;
+  if (nnz > 0) {
+    rc = enqueue_input(h, slice, lay, d, h->seed, step, nullptr, b);
+    if (rc != CTD_OK) return rc;
+    // candidates against R^(t) and each other; kept ones extend R, Q, M (lines 5-16)
+    launch_panel(st, b.uniq_fi, d, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
+    BasisArgs ba{};
+    ba.P = b.P;
+    ba.ldp = b.ld;
+    ba.n_rows = n_rows;
+    ba.s_max = d;
+    ba.uniq_fi = b.uniq_fi;
+    ba.uniq_fid = b.uniq_fid;
+    ba.fptr = b.fptr;
+    ba.row = b.row;
+    ba.val = b.val;
+    ba.Q = S.Q;
+    ba.ldq = S.capD;
+    ba.Qf = mixed ? S.Qf : nullptr;
+    ba.R = S.Rs;
+    ba.ldr = S.capD;
+    ba.M = S.Xt;
+    ba.ldm = S.capD;
+    ba.lev = S.lev;
+    ba.lev_accumulate = true;
+    ba.eps2 = h->opt.eps * h->opt.eps;
+    ba.accept = b.accept;
+    ba.acc_fid = S.acc_fid;
+    ba.acc_fi_local = nullptr;
+    ba.fiber_mark = b.fiber_mark;
+    ba.id_offset = t_off;
+    ba.Wacc = Wacc;
+    ba.ldwa = S.capD;
+    ba.scratch = scratch;
+    ba.cap = S.capD;
+    launch_basis(st, ba, sc);
+    // C: cross term over the columns held (Eq. 13), then the new columns R^(t+1)T dX
+    hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave)), dim3(kBlock), 0, st, S.Xt,
+                       S.capD, Wacc, S.capD, Y, S.capD, sc);
+    hipLaunchKernelGGL(k_cross_term, dim3(grid_for(S.n_cols_ub * kWave)), dim3(kBlock), 0, st,
+                       S.C, S.capD, Y, S.capD, sc);
+    hipLaunchKernelGGL(k_spmm_cols, dim3(grid_for(nnz * kWave)), dim3(kBlock), 0, st, b.fptr,
+                       b.row, b.val, sc, S.Rs, S.capD, &sc->n_accept_total, S.C, S.capD,
+                       &sc->n_cols_total);
+    hipLaunchKernelGGL(k_append_ids, dim3(grid_for(nnz)), dim3(kBlock), 0, st, b.fid, &sc->n_f,
+                       S.col_fid, nullptr, &sc->n_cols_total, t_off);
+    // slice residual against the grown basis
+    ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total, S.capD);
+    launch_project(st, pa, nnz, sc);
+  }
+  hipLaunchKernelGGL(k_finish_slice, dim3(1), dim3(1), 0, st, sc);
+  HIP_CHECK(h, hipGetLastError());
+  h->s = d;
+  h->step += 1;
+  h->last_was_update = true;
+  S.T += 1;
+  S.d_ub = std::min<int64_t>(n_rows, S.d_ub + d);
+  S.n_cols_ub += nnz;
+  return CTD_OK;
+}

@@ -1,0 +1,136 @@
+// Host-side launch wrappers of the CTD kernels.  Every wrapper enqueues on
+// `st` and never synchronizes.  Sizes that are known only on the device are
+// passed as pointers into DevScalars; host arguments give upper bounds.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace ctd {
+
+// ---- sort.hip --------------------------------------------------------------
+// Stable LSD radix sort of (key, payload) pairs on the low `nbits` bits of the
+// keys.  The element count is *d_n if d_n != nullptr, else n_max.  Returns
+// true if the sorted data ended in the *_alt buffers.
+size_t radix_sort_hist_elems(int64_t n_max);
+bool radix_sort(hipStream_t st, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                uint32_t* vals_alt, int64_t n_max, const int32_t* d_n, int nbits,
+                uint32_t* hist_ws);
+
+// ---- fibers.hip ------------------------------------------------------------
+struct FiberLayout {
+  int order;
+  int mode;
+  int rbits;              // bits of the row (mode-alpha) index
+  int64_t n_rows;         // I_alpha
+  int64_t dims[CTD_MAX_ORDER];
+  int64_t stride[CTD_MAX_ORDER];  // fiber-id stride of each mode (0 for alpha)
+};
+
+// A0: validate, build keys (fid << rbits | row) and the identity payload, track
+// max v^2.  val_dtype selects float64/float32 input.
+void launch_build_keys(hipStream_t st, const FiberLayout& lay, const int32_t* idx,
+                       const void* val, int val_dtype, int64_t nnz, uint64_t* keys,
+                       uint32_t* perm, DevScalars* sc);
+// A0/A1/A2: segment the sorted keys into fibers, gather values, quantized
+// weights, inclusive weight prefix, ||X||^2.
+struct SegmentBuffers {
+  const uint64_t* keys;   // sorted
+  const uint32_t* perm;   // sorted payload (original positions)
+  const void* val_in;
+  int val_dtype;
+  int32_t* row;           // [nnz] out
+  double* val;            // [nnz] out (float64 copy in fiber order)
+  float* val32;           // [nnz] out (float32 copy) or nullptr
+  uint64_t* qpref;        // [nnz] out inclusive prefix of quantized weights
+  int32_t* fptr;          // [nnz+1] out fiber starts
+  uint64_t* fid;          // [nnz] out fiber ids
+  uint32_t* blk_cnt;      // workspace [nblocks+1]
+  uint64_t* blk_q;        // workspace [nblocks+1]
+  double* blk_v2;         // workspace [nblocks]
+};
+size_t segment_blocks(int64_t nnz);
+void launch_segment(hipStream_t st, const SegmentBuffers& b, int64_t nnz, int rbits,
+                    DevScalars* sc);
+
+// ---- sample.hip ------------------------------------------------------------
+// A2: s Philox draws -> fiber index and fiber id per draw.
+void launch_draws(hipStream_t st, const uint64_t* qpref, const int32_t* fptr,
+                  const uint64_t* fid, int64_t nnz, int64_t s, uint64_t seed, uint32_t step,
+                  uint32_t tensor, int32_t* draw_fi, uint64_t* draw_fid, DevScalars* sc);
+// Given draws (fiber ids, device) -> fiber index per draw (binary search).
+void launch_locate_given(hipStream_t st, const uint64_t* fid, int64_t s,
+                         const uint64_t* draw_fid, int32_t* draw_fi, DevScalars* sc);
+// A3: sort the s draws, unique, multiplicities, probabilities, merge scales.
+void launch_unique(hipStream_t st, const int32_t* draw_fi, int64_t s, const uint64_t* qpref,
+                   const int32_t* fptr, const uint64_t* fid, int32_t* uniq_fi,
+                   uint64_t* uniq_fid, int32_t* counts, double* prob, double* scale,
+                   DevScalars* sc);
+
+// ---- factor.hip ------------------------------------------------------------
+// A4: dense row-major panel P (n_rows x ldp) of the s' candidate fibers.
+void launch_panel(hipStream_t st, const int32_t* uniq_fi, int64_t s_max, const int32_t* fptr,
+                  const int32_t* row, const double* val, int64_t n_rows, double* P, int64_t ldp,
+                  DevScalars* sc);
+
+// ---- basis.hip -------------------------------------------------------------
+// A5-A7: independence filter over the s' candidates in blocks of 64, growing
+// an orthonormal basis Q of span(R), R itself and M (Q = R M, U = M M^T).
+// Starts from the sc->n_accept_total columns already held (0 for CTD-S).
+struct BasisArgs {
+  const double* P;           // candidate panel, n_rows x ldp
+  int64_t ldp;
+  int64_t n_rows;
+  int64_t s_max;             // host bound of s'
+  const int32_t* uniq_fi;    // candidate fiber positions (ascending)
+  const uint64_t* uniq_fid;  // candidate fiber ids
+  const int32_t* fptr;
+  const int32_t* row;
+  const double* val;
+  double* Q;                 // n_rows x ldq
+  int64_t ldq;
+  float* Qf;                 // optional float copy of Q (same ld)
+  double* R;                 // n_rows x ldr kept fibers (optional)
+  int64_t ldr;
+  double* M;                 // ldm x ldm upper triangular
+  int64_t ldm;
+  double* lev;               // n_rows: ||Q_i||^2
+  bool lev_accumulate;       // add the new columns only
+  double eps2;
+  int32_t* accept;           // optional [s'] 0/1 per candidate
+  uint64_t* acc_fid;         // kept fiber ids, indexed by global column
+  int32_t* acc_fi_local;     // optional: kept fiber positions, indexed within this call
+  uint8_t* fiber_mark;       // optional: 1 for kept fibers of this input
+  uint64_t id_offset;        // added to fiber ids written to acc_fid
+  double* Wacc;              // optional: Q^T x rows of the kept fibers (this call)
+  int64_t ldwa;
+  double* scratch;           // basis_scratch_doubles(n_rows, cap)
+  int64_t cap;               // column capacity of Q, M, W (>= final k + 64)
+};
+size_t basis_scratch_doubles(int64_t n_rows, int64_t cap);
+void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc);
+
+// ---- project.hip -----------------------------------------------------------
+// A8: per-fiber residual ||x_f||^2 - ||Q^T x_f||^2 (0 for marked fibers) and
+// its deterministic sum into sc->err2.
+struct ProjectArgs {
+  const int32_t* fptr;
+  const int32_t* row;
+  const double* val;
+  const float* val32;      // mixed precision
+  const double* Q;
+  const float* Qf;         // mixed precision
+  int64_t ldq;
+  const double* lev;
+  const uint8_t* fiber_mark;
+  const int32_t* d_ncols;  // device count of columns of Q
+  int64_t ncols_max;
+  double* resid;           // [n_f] out
+  int32_t* multi;          // [n_f] workspace: fibers with >= 2 nonzeros
+  double* partial;         // workspace
+  bool mixed;
+};
+void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc);
+
+}  // namespace ctd

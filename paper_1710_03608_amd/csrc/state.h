@@ -1,0 +1,126 @@
+// Host-side handle of the CTD library.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace ctd {
+
+// Bump allocator over one device buffer; `take` returns offsets that are
+// rebased onto `base` once the total is known.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  void reset();
+  void* take(size_t bytes);
+};
+
+// Workspace of one CTD-S call (all device pointers into the arena).
+struct StaticBufs {
+  uint64_t* keys;
+  uint32_t* perm;
+  uint32_t* hist;
+  int32_t* row;
+  double* val;
+  float* val32;
+  uint64_t* qpref;
+  int32_t* fptr;
+  uint64_t* fid;
+  uint32_t* blk_cnt;
+  uint64_t* blk_q;
+  double* blk_v2;
+  int32_t* draw_fi;
+  uint64_t* draw_fid;
+  int32_t* uniq_fi;
+  uint64_t* uniq_fid;
+  int32_t* counts;
+  double* prob;
+  double* scale;
+  double* P;
+  int32_t* accept;
+  uint64_t* acc_fid;
+  double* M;
+  double* scratch;
+  double* Q;
+  float* Qf;
+  double* lev;
+  uint8_t* fiber_mark;
+  double* resid;
+  int32_t* multi;
+  double* partial;
+  double* Rs;
+  double* C;
+  int64_t ld;
+  int64_t s_max;
+};
+
+// CTD-D state: factors of step t, kept on the device between calls.
+struct DynState {
+  int64_t capD = 0;        // row capacity of C / column capacity of R, Q, Xt
+  int64_t capN = 0;        // column capacity of C
+  int64_t d_tilde = 0;     // accepted fibers held (host copy, updated at sync points)
+  int64_t n_cols = 0;      // columns of C held (non-empty fibers seen)
+  int64_t d_ub = 0;        // host upper bound of d_tilde between syncs
+  int64_t n_cols_ub = 0;   // host upper bound of n_cols between syncs
+  int64_t T = 0;           // time steps held
+  int64_t dN = 0;          // columns per time step (N_alpha of a slice)
+  double* Rs = nullptr;    // n_rows x capD row-major: kept fibers
+  double* Q = nullptr;     // n_rows x capD row-major: orthonormal basis
+  float* Qf = nullptr;     // mixed precision copy of Q
+  double* Xt = nullptr;    // capD x capD row-major: (L^{-1})^T
+  double* lev = nullptr;   // n_rows: ||Q_i||^2
+  double* C = nullptr;     // capD x capN column-major
+  uint64_t* acc_fid = nullptr;  // capD kept fiber ids
+  uint64_t* col_fid = nullptr;  // capN fiber ids of C's columns
+  void* ws = nullptr;      // per-slice workspace
+  size_t ws_bytes = 0;
+};
+
+}  // namespace ctd
+
+struct ctd_handle {
+  hipStream_t stream = nullptr;
+  ctd_options opt{};
+  ctd::DevScalars* d_sc = nullptr;
+  ctd::Arena arena;
+  ctd::StaticBufs sb{};
+  ctd::DynState dyn;
+  ctd::FiberLayout layout{};
+  std::vector<uint64_t> given;
+  std::string last_error;
+  int64_t s = 0;
+  uint64_t seed = 0;
+  int64_t n_rows = 0;
+  int64_t step = 0;
+  int32_t mode = 0;
+  bool failed = false;
+  bool has_static = false;
+  bool dyn_ready = false;
+  bool last_was_update = false;
+};
+
+namespace ctd {
+int bits_for(uint64_t n);
+int64_t round4(int64_t x);
+ctd_status fail(ctd_handle* h, ctd_status st, const std::string& msg);
+ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout* lay,
+                     uint64_t* n_cols_total);
+ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
+                       bool want_C, StaticBufs* b);
+ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
+                         uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b);
+int key_bits(const FiberLayout& lay);
+ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const float* Qf,
+                         int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max);
+void launch_reset_scalars(hipStream_t st, DevScalars* sc, bool keep_stream);
+void launch_static_totals(hipStream_t st, DevScalars* sc);
+void launch_core_static(hipStream_t st, StaticBufs& b, int64_t n_rows, int64_t nnz_max,
+                        DevScalars* sc);
+ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X);
+void dyn_free(ctd_handle* h);
+void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out);
+}  // namespace ctd

@@ -1,0 +1,121 @@
+"""CTD-D on the GPU (through the C ABI) against the CPU float64 oracle (Algorithm 2)."""
+import numpy as np
+import pytest
+
+from oracle import ctd as ora
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_1710_03608_amd as ctd
+    assert torch.cuda.is_available()
+    ctd.load_library()
+    return ctd
+
+
+def _stream(seed, dims=(60, 50, 12), nnz0=2500, n_slices=8, slice_nnz=(60, 400)):
+    return synth.traffic_stream(dims=dims, nnz0=nnz0, n_slices=n_slices, slice_nnz=slice_nnz,
+                                zipf_a=1.1, n_anomalies=1, block=6, seed=seed)
+
+
+def reference_core(st, o):
+    """C_(alpha) from its definition: column f holds R^T P_{t_f} x_f, P_{t_f} the
+    projector onto span(R) at the step where fiber f arrived (Eqs. 8-13 unrolled)."""
+    R = o.R
+    k_at = [len(o.static.accepted)] + [h["d_tilde"] for h in o.history]
+    inputs = [st.initial] + list(st.slices)
+    cols = []
+    for t, X in enumerate(inputs):
+        u = ora.unfold(X.dims, X.idx, X.val, 0)
+        Qt, _ = np.linalg.qr(R[:, :k_at[t]])
+        Xd = u.mat.toarray()
+        cols.append(R.T @ (Qt @ (Qt.T @ Xd)))
+    return np.hstack(cols)
+
+
+def _run(lib, st, s, d, seed, precision="fp64"):
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(precision=precision, want_C=True)
+    h.decompose(dims, idx, val, 0, s, seed)
+    steps = [h.result()]
+    for sl in st.slices:
+        sd, si, sv = lib.to_device(sl, "cuda")
+        h.update(sd, si, sv, d)
+        steps.append(h.result(factors=False))
+    final = h.result(factors=True)
+    h.close()
+    return steps, final
+
+
+@pytest.mark.parametrize("seed,s,d,J", [(3, 30, 4, 50), (5, 50, 8, 50), (7, 20, 100, 200)])
+def test_stream_matches_oracle(lib, seed, s, d, J):
+    st = _stream(seed, dims=(60, J, 12))
+    o = ora.Dynamic(st.initial.dims, st.initial.idx, st.initial.val, 0, s, seed)
+    steps, final = _run(lib, st, s, d, seed)
+    T0, J = st.initial.dims[2], st.initial.dims[1]
+    assert np.array_equal(steps[0]["accepted"], o.static.accepted.astype(np.uint64))
+    for t, sl in enumerate(st.slices):
+        info = o.update(sl.dims, sl.idx, sl.val, d)
+        g = steps[t + 1]
+        off = (T0 + t) * J
+        assert np.array_equal(g["draws"] + np.uint64(off), info["draws"].astype(np.uint64)), t
+        assert g["s_tilde"] == info["d_tilde"], t
+        assert g["step"] == t + 1
+        assert abs(g["rel_err"] - o.rel_err) <= 1e-6 * o.rel_err + 1e-12, (t, g["rel_err"], o.rel_err)
+        assert g["norm2"] == pytest.approx(o.norm2, rel=1e-13)
+    assert np.array_equal(np.sort(final["accepted"]), np.sort(np.array(o.accepted, dtype=np.uint64)))
+    assert np.array_equal(final["col_ids"], o.col_fids.astype(np.uint64))
+    R = final["R"]
+    assert np.array_equal(R, o.R)
+    C = final["C"]
+    assert C.shape == o.C.shape
+    ref = reference_core(st, o)
+    scale = np.abs(ref).max()
+    err = np.abs(C - ref).max() / scale
+    cond = np.linalg.cond(R)
+    # the cross rows multiply U = (R^T R)^{-1}-sized factors into C: error ~ u cond(R)^2
+    assert err <= max(1e-12, 1e-15 * cond ** 2), (err, cond)
+
+
+def test_empty_and_zero_slices(lib):
+    import torch
+    st = _stream(9, n_slices=2)
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(want_C=True)
+    h.decompose(dims, idx, val, 0, 20, 1)
+    r0 = h.result()
+    sd = st.slices[0].dims
+    h.update(sd, torch.zeros((3, 0), dtype=torch.int32, device="cuda"),
+             torch.zeros(0, dtype=torch.float64, device="cuda"), 2)
+    r1 = h.result()
+    assert r1["err2"] == r0["err2"] and r1["s_tilde"] == r0["s_tilde"] and r1["step"] == 1
+    _, si, sv = lib.to_device(st.slices[1], "cuda")
+    h.update(sd, si, torch.zeros_like(sv), 2)
+    r2 = h.result()
+    assert r2["err2"] == r0["err2"] and r2["s_tilde"] == r0["s_tilde"] and r2["step"] == 2
+    h.close()
+
+
+def test_update_argument_checks(lib):
+    st = _stream(11, n_slices=1)
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(want_C=True)
+    h.decompose(dims, idx, val, 0, 20, 1)
+    sd, si, sv = lib.to_device(st.slices[0], "cuda")
+    for bad_dims, d, code in (((sd[0], sd[1], 2), 2, "CTD_ERR_STATE"),
+                              ((sd[0] + 1, sd[1], 1), 2, "CTD_ERR_STATE"),
+                              (sd, 0, "CTD_ERR_INVALID_ARG")):
+        with pytest.raises(lib.CtdError) as ei:
+            h.update(bad_dims, si, sv, d)
+        assert ei.value.name == code
+    h.close()
+    h2 = lib.Ctd(want_C=False)
+    h2.decompose(dims, idx, val, 0, 20, 1)
+    with pytest.raises(lib.CtdError) as ei:
+        h2.update(sd, si, sv, 2)
+    assert ei.value.name == "CTD_ERR_STATE"
+    h2.close()

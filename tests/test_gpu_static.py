@@ -1,0 +1,183 @@
+"""CTD-S on the GPU (through the C ABI) against the CPU float64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ctd as ora
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL_FP64 = 1e-6      # relative-error parity in float64 mode
+ATOL_FP64 = 1e-12
+RTOL_MIXED = 1e-4     # float32 projection
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_1710_03608_amd as ctd
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctd.load_library()
+    return ctd
+
+
+def run_gpu(lib, X, mode, s, seed, precision="fp64", val_dtype="f64", **kw):
+    dims, idx, val = lib.to_device(X, "cuda", val_dtype=val_dtype)
+    h = lib.Ctd(precision=precision, **kw)
+    try:
+        h.decompose(dims, idx, val, mode, s, seed)
+        return h.result(factors=kw.get("want_C", False))
+    finally:
+        h.close()
+
+
+def check_parity(g, o, rtol=RTOL_FP64, atol=ATOL_FP64):
+    assert np.array_equal(g["draws"], o.draws.astype(np.uint64))
+    assert np.array_equal(g["unique"], o.uniq.astype(np.uint64))
+    assert np.array_equal(g["counts"], o.counts.astype(np.int32))
+    assert np.allclose(g["prob"], o.p, rtol=1e-14, atol=0)
+    assert np.allclose(g["scale"], o.omega, rtol=1e-13, atol=0)
+    if not np.array_equal(g["accepted"], o.accepted.astype(np.uint64)):
+        ga, oa = set(g["accepted"].tolist()), set(o.accepted.tolist())
+        rho = dict(zip(o.uniq.tolist(), np.asarray(o.rho).tolist()))
+        extra = {f: rho.get(f) for f in sorted(ga - oa)}
+        missing = {f: rho.get(f) for f in sorted(oa - ga)}
+        raise AssertionError(f"kept sets differ: gpu-only {extra} oracle-only {missing} "
+                             f"(sizes {len(ga)} vs {len(oa)})")
+    assert g["norm2"] == pytest.approx(o.norm2, rel=1e-13)
+    assert abs(g["rel_err"] - o.rel_err) <= rtol * o.rel_err + atol, (g["rel_err"], o.rel_err)
+
+
+def borderline(o, eps=1e-6, band=1e3):
+    """Candidates whose residual ratio sits within rounding of the threshold."""
+    r = np.asarray(o.rho[1:])
+    return np.any((r > eps * eps / band) & (r < eps * eps * band))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_tiny_uniform_matches_oracle(lib, seed):
+    X = synth.tiny_uniform()
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 100, seed)
+    g = run_gpu(lib, X, 0, 100, seed)
+    assert not borderline(o)
+    check_parity(g, o)
+
+
+@pytest.mark.parametrize("which", range(5))
+def test_table3_shaped_tensors(lib, which):
+    X = synth.small_shapes()[which]
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 300, 7)
+    g = run_gpu(lib, X, 0, 300, 7)
+    if borderline(o):
+        pytest.skip("candidate within rounding of the threshold")
+    check_parity(g, o)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_other_modes(lib, mode):
+    X = synth.power_law_tensor((90, 70, 40), 6000, 12, zipf_a=1.2)
+    o = ora.ctd_s(X.dims, X.idx, X.val, mode, 150, 3)
+    g = run_gpu(lib, X, mode, 150, 3)
+    check_parity(g, o)
+
+
+def test_float32_values_give_identical_draws(lib):
+    X = synth.tiny_uniform()
+    g64 = run_gpu(lib, X, 0, 100, 5)
+    g32 = run_gpu(lib, X, 0, 100, 5, val_dtype="f32")
+    for k in ("draws", "unique", "counts", "accepted"):
+        assert np.array_equal(g64[k], g32[k])
+    assert g64["err2"] == g32["err2"]
+
+
+def test_runs_are_bit_identical(lib):
+    X = synth.power_law_tensor((300, 200, 60), 40000, 4, zipf_a=1.2)
+    a = run_gpu(lib, X, 0, 400, 9)
+    b = run_gpu(lib, X, 0, 400, 9)
+    assert a["err2"] == b["err2"] and a["norm2"] == b["norm2"]
+    assert np.array_equal(a["accepted"], b["accepted"])
+
+
+def test_all_fibers_drawn_gives_zero_residual(lib):
+    X = synth.uniform_tensor((40, 30, 10), 1500, 5)
+    u = ora.unfold(X.dims, X.idx, X.val, 0)
+    import torch
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd()
+    h.decompose_given(dims, idx, val, 0, u.fids.astype(np.uint64))
+    g = h.result()
+    h.close()
+    assert g["rel_err"] <= 1e-13
+    assert g["s_tilde"] == np.linalg.matrix_rank(u.mat.toarray())
+
+
+def test_planted_rank_recovered(lib):
+    noisy, clean = synth.planted_low_rank(dims=(60, 50, 20), rank=5, seed=3, factor_nnz=(12, 10, 4))
+    g = run_gpu(lib, clean, 0, 200, 0)
+    assert g["s_tilde"] == 5
+    assert g["rel_err"] <= 1e-12
+
+
+def test_factors_match_definitions(lib):
+    X = synth.power_law_tensor((80, 60, 20), 5000, 2, zipf_a=1.2)
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 120, 4, want_C=True)
+    g = run_gpu(lib, X, 0, 120, 4, want_C=True)
+    check_parity(g, o)
+    R, Q, Xt, C = g["R"], g["Q"], g["Linv_t"], g["C"]
+    assert np.array_equal(R, o.R)                       # actual fibers, bit for bit
+    k = R.shape[1]
+    assert np.abs(Q.T @ Q - np.eye(k)).max() <= 1e-9       # orthonormal basis
+    assert np.allclose(Q @ (Q.T @ R), R, atol=1e-12 * np.abs(R).max())
+    assert np.array_equal(Xt, np.triu(Xt))              # Q = R M, M upper triangular
+    cond = np.linalg.cond(R)
+    assert np.linalg.norm(R @ Xt - Q) <= 1e-15 * cond * np.sqrt(k) * 10
+    U = Xt @ Xt.T                                       # (R^T R)^{-1}
+    assert np.linalg.norm(U @ (R.T @ R) - np.eye(k)) <= 1e-15 * cond ** 2 * k * 10
+    assert np.allclose(C, o.C, rtol=1e-12, atol=1e-12 * np.abs(o.C).max())
+
+
+def test_mixed_precision_within_tolerance(lib):
+    X = synth.power_law_tensor((400, 300, 80), 60000, 6, zipf_a=1.2)
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 500, 1)
+    g = run_gpu(lib, X, 0, 500, 1, precision="mixed")
+    assert np.array_equal(g["draws"], o.draws.astype(np.uint64))
+    assert np.array_equal(g["accepted"], o.accepted.astype(np.uint64))
+    assert abs(g["rel_err"] - o.rel_err) <= RTOL_MIXED * o.rel_err + 1e-8
+
+
+def _expect_error(lib, fn, code):
+    with pytest.raises(lib.CtdError) as ei:
+        fn()
+    assert ei.value.name == code
+
+
+def test_error_paths(lib):
+    import torch
+    X = synth.uniform_tensor((20, 10, 5), 200, 3)
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd()
+    try:
+        _expect_error(lib, lambda: h.decompose(dims, idx, val, 3, 10, 0), "CTD_ERR_INVALID_ARG")
+        _expect_error(lib, lambda: h.decompose(dims, idx, val, 0, 0, 0), "CTD_ERR_INVALID_ARG")
+        _expect_error(lib, lambda: h.decompose(dims, idx, val, 0, 51, 0), "CTD_ERR_INVALID_ARG")
+        _expect_error(lib, lambda: h.update(dims, idx, val, 2), "CTD_ERR_STATE")
+        bad = idx.clone()
+        bad[1, 7] = 10
+        h.decompose(dims, bad, val, 0, 10, 0)
+        _expect_error(lib, h.sync, "CTD_ERR_INDEX_OOB")
+        dup = torch.cat([idx, idx[:, :1]], dim=1)
+        h.decompose(dims, dup, torch.cat([val, val[:1]]), 0, 10, 0)
+        _expect_error(lib, h.sync, "CTD_ERR_DUPLICATE")
+        nanv = val.clone()
+        nanv[3] = float("nan")
+        h.decompose(dims, idx, nanv, 0, 10, 0)
+        _expect_error(lib, h.sync, "CTD_ERR_NONFINITE")
+        h.decompose(dims, idx, torch.zeros_like(val), 0, 10, 0)
+        _expect_error(lib, h.sync, "CTD_ERR_EMPTY")
+        # the handle recovers with a fresh decompose
+        h.decompose(dims, idx, val, 0, 10, 0)
+        h.sync()
+    finally:
+        h.close()
