@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the CTD-S hot path on one MI355X.
+
+Workload: the 10,000 x 10,000 x 1,000 source x destination x time traffic
+tensor with 5,000,000 nonzeros (Zipf(1.2) sources and destinations, uniform
+time, lognormal(0,1) values; workloads/synth.traffic_5m, seeded), mode 0,
+s = 2000 draws, Philox seed 0, eps = 1e-6.  One step is one full
+ctd_decompose on the device-resident COO tensor: keys and radix sort,
+weights, draws, unique, candidate panel, independence filter and basis,
+projection of every nonzero and the Frobenius residual.  Both precisions are
+timed; `value` is the float64 path (the one with 1e-6 parity), the mixed
+path is reported beside it.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("nonzeros/sec and HBM GB/s (% roofline) for CTD-S/CTD-D, mixed vs FP64 at stated "
+          "error")
+PEAK_FP64_VALU = 78.6    # TFLOP/s, MI355X vector fp64
+PEAK_FP32_VALU = 157.3   # TFLOP/s, MI355X vector fp32
+PEAK_HBM = 8000.0        # GB/s
+S_DRAWS = 2000
+SEED = 0
+GOLD = os.path.join(ROOT, "tests", "golden", "traffic_5m_s2000_seed0.npz")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload_stats(X):
+    """Fiber statistics of the workload (for the algorithmic flop count)."""
+    import numpy as np
+    f = X.idx[1].astype(np.int64) + X.idx[2].astype(np.int64) * X.dims[1]
+    _, counts = np.unique(f, return_counts=True)
+    single = int((counts == 1).sum())
+    return {"n_f": int(counts.shape[0]), "nnz_multi": int(X.nnz - single), "n_single": single}
+
+
+def time_mode(ctd, dims, idx, val, precision, steps, warmup):
+    import numpy as np
+    import torch
+    h = ctd.Ctd(precision=precision, profile=True)
+    for _ in range(warmup):
+        h.decompose(dims, idx, val, 0, S_DRAWS, SEED)
+        h.sync()
+    stage_sum = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.decompose(dims, idx, val, 0, S_DRAWS, SEED)
+        r = h.result(arrays=False)
+        st = np.array([r["stage_ms"][k] for k in ctd.Ctd.STAGES])
+        stage_sum = st if stage_sum is None else stage_sum + st
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = h.result(arrays=True)
+    h.close()
+    stages = dict(zip(ctd.Ctd.STAGES, (stage_sum / steps).tolist()))
+    return (t1 - t0) * 1000.0 / steps, stages, res
+
+
+def cpu_baseline(X):
+    """The oracle (numpy/scipy float64) on a bounded sample of the same workload."""
+    from oracle import ctd as ora
+    n = 500_000
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    t = time.perf_counter()
+    r = ora.ctd_s(X.dims, X.idx[:, :n], X.val[:n], 0, S_DRAWS, SEED)
+    dt = time.perf_counter() - t
+    return {"value": n / dt, "unit": "nnz/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"first {n} of the 5M nonzeros (a uniform 10% subset: COO order is random), "
+                       f"same dims, mode 0, s={S_DRAWS}, seed {SEED}; oracle CTD-S end to end "
+                       f"(matricize, weights, Philox draws, independence loop, projection "
+                       f"error) in {dt:.1f} s, s~={len(r.accepted)}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--modes", default="fp64,mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the CTD hot path here is built for a single MI355X; "
+              "multi-GPU runs are not part of this build (see the sharding notes in DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1710_03608_amd as ctd
+    from workloads import synth
+
+    log("generating the 5M-nonzero traffic tensor ...")
+    X = synth.traffic_5m()
+    stats = workload_stats(X)
+    torch.cuda.set_device(0)
+    dims, idx, val = ctd.to_device(X, "cuda:0")
+    gold = np.load(GOLD, allow_pickle=False)
+    rel_o = float(gold["rel_err"])
+
+    results = {}
+    for mode in args.modes.split(","):
+        log(f"timing {mode}: {args.warmup} warmup + {args.steps} steps")
+        ms, stages, res = time_mode(ctd, dims, idx, val, mode, args.steps, args.warmup)
+        exact = (np.array_equal(res["draws"], gold["draws"])
+                 and np.array_equal(res["unique"], gold["unique"])
+                 and np.array_equal(res["accepted"], gold["accepted"]))
+        results[mode] = {"ms_per_step": ms, "nnz_per_s": X.nnz / (ms / 1000.0), "stages_ms": stages,
+                         "rel_err": res["rel_err"], "s_unique": res["s_unique"],
+                         "s_tilde": res["s_tilde"],
+                         "rel_err_dev_vs_oracle": abs(res["rel_err"] - rel_o) / rel_o,
+                         "indices_bit_exact": bool(exact)}
+        log(f"  {mode}: {ms:.3f} ms/step, {X.nnz / ms * 1e3:.3e} nnz/s, stages {stages}")
+
+    main_mode = "fp64" if "fp64" in results else next(iter(results))
+    m = results[main_mode]
+    s_t = m["s_tilde"]
+    # dominant kernel: the multi-nonzero fiber SpMM (2 flops per nonzero per basis column)
+    spmm_ms = m["stages_ms"]["spmm"]
+    flops = 2.0 * s_t * stats["nnz_multi"]
+    achieved = flops / (spmm_ms * 1e-3) / 1e12 if spmm_ms > 0 else 0.0
+    peak = PEAK_FP64_VALU if main_mode == "fp64" else PEAK_FP32_VALU
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": "k_proj_multi (A8: z_f = Q^T x_f over fibers with >= 2 nonzeros)",
+                "work": f"2 * s~ ({s_t}) * nnz in multi-nonzero fibers ({stats['nnz_multi']})",
+                "kernel_ms": spmm_ms}
+    # end-to-end algorithmic HBM bytes of one decomposition (float64): COO read
+    # (12 + 8 B/nnz), sort passes, fiber layout, projection stream, Q once
+    nnz = X.nnz
+    e2e_bytes = nnz * (12 + 8) + nnz * (12 + 8) + nnz * (4 + 8) + 10_000 * s_t * 8
+    line = {
+        "metric": METRIC,
+        "value": m["nnz_per_s"],
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_mode == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "ctd_s_traffic_10000x10000x1000_nnz5000000_zipf1.2_s2000",
+                   "mode": 0, "s": S_DRAWS, "seed": SEED, "eps": 1e-6,
+                   "n_f": stats["n_f"], "nnz_multi": stats["nnz_multi"]},
+        "hbm_GBps_end_to_end": e2e_bytes / (m["ms_per_step"] * 1e-3) / 1e9,
+        "roofline": roofline,
+        "modes": results,
+        "oracle_rel_err": rel_o,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        line["cpu_baseline"] = cpu_baseline(X)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

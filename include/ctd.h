@@ -78,7 +78,22 @@ typedef struct {
   double eps;               /* tolerance of the independence test, Algorithm 1 line 8 (the paper uses 1e-6) */
   int32_t want_C;           /* CTD-S: also write C_(alpha) = R^T X_(alpha) (dense s~ x n_f) */
   int32_t want_fiber_stats; /* also keep per-fiber ||x_f||^2 - ||P x_f||^2 */
+  int32_t profile;          /* time the stages of each call with HIP events (see stage_ms) */
 } ctd_options;
+
+/* Stages timed when ctd_options.profile is set (milliseconds, device time
+ * between HIP events recorded on the handle's stream). */
+enum {
+  CTD_STAGE_SORT = 0,       /* fiber keys and radix sort (Algorithm 1 line 1) */
+  CTD_STAGE_SAMPLE = 1,     /* weights, prefix, draws, unique (lines 2-4) */
+  CTD_STAGE_PANEL = 2,      /* dense panel of the candidates */
+  CTD_STAGE_BASIS = 3,      /* independence filter and orthonormal basis (lines 5-15) */
+  CTD_STAGE_PROJECT = 4,    /* projection of all nonzeros and the residual (line 16, Eq. 14) */
+  CTD_STAGE_SPMM = 5,       /* the multi-nonzero fiber SpMM kernel alone (inside PROJECT) */
+  CTD_STAGE_CORE = 6,       /* C: CTD-S line 16 if want_C; CTD-D cross term and new columns */
+  CTD_STAGE_TOTAL = 7,
+  CTD_N_STAGES = 8
+};
 
 /* Results of the last call.  Scalars are copies; pointers are device
  * memory owned by the handle (valid until the next decompose/update/destroy). */
@@ -95,6 +110,7 @@ typedef struct {
   double rel_err;           /* err2 / norm2, Eq. 14 */
   double slice_err2;        /* CTD-D: ||dX - P dX||_F^2 of the last slice */
   int32_t status;           /* latched device status (ctd_status) */
+  float stage_ms[8];        /* per-stage device time of the last call if profiling, else 0 */
   /* device arrays */
   const uint64_t* draws;    /* [s] fiber ids in draw order */
   const uint64_t* unique;   /* [s'] ascending unique fiber ids */

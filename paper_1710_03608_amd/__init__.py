@@ -34,14 +34,14 @@ class CooStruct(ctypes.Structure):
 
 class OptionsStruct(ctypes.Structure):
     _fields_ = [("precision", c_i32), ("eps", c_dbl), ("want_C", c_i32),
-                ("want_fiber_stats", c_i32)]
+                ("want_fiber_stats", c_i32), ("profile", c_i32)]
 
 
 class ResultStruct(ctypes.Structure):
     _fields_ = [("s", c_i64), ("s_unique", c_i64), ("s_tilde", c_i64), ("n_f", c_i64),
                 ("n_rows", c_i64), ("step", c_i64), ("weight_total", c_u64),
                 ("norm2", c_dbl), ("err2", c_dbl), ("rel_err", c_dbl), ("slice_err2", c_dbl),
-                ("status", c_i32),
+                ("status", c_i32), ("stage_ms", ctypes.c_float * 8),
                 ("draws", c_vp), ("unique", c_vp), ("counts", c_vp), ("prob", c_vp),
                 ("scale", c_vp), ("accepted", c_vp),
                 ("Q", c_vp), ("ldq", c_i64), ("Linv_t", c_vp), ("ldx", c_i64),
@@ -151,13 +151,16 @@ def to_device(tensor_like, device="cuda", val_dtype="f64"):
 class Ctd:
     """One handle of the CTD library bound to torch's current stream."""
 
+    STAGES = ("sort", "sample", "panel", "basis", "project", "spmm", "core", "total")
+
     def __init__(self, precision="fp64", eps=1e-6, want_C=False, want_fiber_stats=False,
-                 stream=None):
+                 stream=None, profile=False):
         import torch
         lib = load_library()
         self.lib = lib
         opt = OptionsStruct(CTD_PREC_MIXED if precision == "mixed" else CTD_PREC_FP64,
-                            float(eps), int(bool(want_C)), int(bool(want_fiber_stats)))
+                            float(eps), int(bool(want_C)), int(bool(want_fiber_stats)),
+                            int(bool(profile)))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -205,6 +208,7 @@ class Ctd:
         out = {k: getattr(r, k) for k in ("s", "s_unique", "s_tilde", "n_f", "n_rows", "step",
                                           "weight_total", "norm2", "err2", "rel_err",
                                           "slice_err2", "n_cols")}
+        out["stage_ms"] = dict(zip(self.STAGES, [float(x) for x in r.stage_ms]))
         if arrays:
             out["draws"] = device_to_numpy(r.draws, r.s, np.uint64)
             out["unique"] = device_to_numpy(r.unique, r.s_unique, np.uint64)

@@ -26,6 +26,13 @@ void* Arena::take(size_t bytes) {
 }  // namespace ctd
 
 namespace ctd {
+void mark(ctd_handle* h, int i) {
+  if (!h->opt.profile) return;
+  if (!h->ev[i]) (void)hipEventCreate(&h->ev[i]);
+  (void)hipEventRecord(h->ev[i], h->stream);
+  h->ev_used[i] = true;
+}
+
 int bits_for(uint64_t n) {  // ceil(log2(n)) for n >= 1
   return n <= 1 ? 0 : 64 - __builtin_clzll(n - 1);
 }
@@ -192,6 +199,7 @@ ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay
   const int64_t n1 = std::max<int64_t>(nnz, 1);
   const bool alt = radix_sort(st, b.keys, b.perm, b.keys + n1, b.perm + n1, nnz, nullptr, nbits,
                               b.hist);
+  mark(h, MARK_SORTED);
   SegmentBuffers sb{};
   sb.keys = alt ? b.keys + n1 : b.keys;
   sb.perm = alt ? b.perm + n1 : b.perm;
@@ -220,6 +228,7 @@ ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay
   // A3: unique
   launch_unique(st, b.draw_fi, s, b.qpref, b.fptr, b.fid, b.uniq_fi, b.uniq_fid, b.counts, b.prob,
                 b.scale, sc);
+  mark(h, MARK_SAMPLED);
   return CTD_OK;
 }
 
@@ -268,11 +277,14 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   ctd_status rc = plan_static(h, nnz, s, n_rows, mixed, want_C, &b);
   if (rc != CTD_OK) return rc;
   DevScalars* sc = h->d_sc;
+  for (bool& u : h->ev_used) u = false;
+  mark(h, MARK_START);
   launch_reset_scalars(st, sc, false);
   rc = enqueue_input(h, X, lay, s, seed, 0u, given, b);
   if (rc != CTD_OK) return rc;
   // A4: candidate panel
   launch_panel(st, b.uniq_fi, s, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
+  mark(h, MARK_PANEL);
   // A5-A7: independence filter and orthonormal basis, block by block
   BasisArgs ba{};
   ba.P = b.P;
@@ -304,11 +316,21 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   ba.scratch = b.scratch;
   ba.cap = b.ld;
   launch_basis(st, ba, sc);
+  mark(h, MARK_BASIS);
   // A8: projection and residual
   ProjectArgs pa = project_args(h, b, b.Q, b.Qf, b.ld, b.lev, &sc->s_tilde, s);
-  launch_project(st, pa, nnz, sc);
+  if (h->opt.profile) {
+    mark(h, MARK_PROJ0);
+    mark(h, MARK_SPMM0);
+    mark(h, MARK_SPMM1);
+  }
+  launch_project(st, pa, nnz, sc, h->opt.profile ? h->ev[MARK_SPMM0] : nullptr,
+                 h->opt.profile ? h->ev[MARK_SPMM1] : nullptr);
+  mark(h, MARK_PROJECTED);
   if (want_C) launch_core_static(st, b, n_rows, nnz, sc);
+  mark(h, MARK_CORE);
   launch_static_totals(st, sc);
+  mark(h, MARK_END);
   HIP_TRY(h, hipGetLastError());
   h->s = s;
   h->n_rows = n_rows;
@@ -431,6 +453,8 @@ const char* ctd_last_error(const ctd_handle* h) { return h ? h->last_error.c_str
 void ctd_destroy(ctd_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
   dyn_free(h);
   if (h->arena.base) (void)hipFree(h->arena.base);
   if (h->d_sc) (void)hipFree(h->d_sc);

@@ -330,6 +330,22 @@ void dyn_free(ctd_handle* h) {
 
 void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out) {
   const StaticBufs& b = h->sb;
+  if (h->opt.profile) {
+    auto span = [&](int a, int c) -> float {
+      float ms = 0.f;
+      if (h->ev_used[a] && h->ev_used[c]) (void)hipEventElapsedTime(&ms, h->ev[a], h->ev[c]);
+      return ms;
+    };
+    out->stage_ms[CTD_STAGE_SORT] = span(MARK_START, MARK_SORTED);
+    out->stage_ms[CTD_STAGE_SAMPLE] = span(MARK_SORTED, MARK_SAMPLED);
+    out->stage_ms[CTD_STAGE_PANEL] = span(MARK_SAMPLED, MARK_PANEL);
+    out->stage_ms[CTD_STAGE_BASIS] = span(MARK_PANEL, MARK_BASIS);
+    out->stage_ms[CTD_STAGE_PROJECT] = span(MARK_PROJ0, MARK_PROJECTED);
+    out->stage_ms[CTD_STAGE_SPMM] = span(MARK_SPMM0, MARK_SPMM1);
+    out->stage_ms[CTD_STAGE_CORE] =
+        h->last_was_update ? span(MARK_BASIS, MARK_CORE) : span(MARK_PROJECTED, MARK_CORE);
+    out->stage_ms[CTD_STAGE_TOTAL] = span(MARK_START, MARK_END);
+  }
   out->s = h->s;
   out->s_unique = sc.s_unique;
   out->n_f = sc.n_f;
@@ -444,6 +460,8 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
   double* Wacc = scratch + basis_scratch_doubles(n_rows, S.capD);
   double* Y = Wacc + (size_t)d * S.capD;
 
+  for (bool& u : h->ev_used) u = false;
+  mark(h, MARK_START);
   launch_reset_scalars(st, sc, true);
   const uint64_t t_off = (uint64_t)S.T * (uint64_t)S.dN;
   if (nnz > 0) {
@@ -451,6 +469,7 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
     if (rc != CTD_OK) return rc;
     // candidates against R^(t) and each other; kept ones extend R, Q, M (lines 5-16)
     launch_panel(st, b.uniq_fi, d, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
+    mark(h, MARK_PANEL);
     BasisArgs ba{};
     ba.P = b.P;
     ba.ldp = b.ld;
@@ -481,6 +500,7 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
     ba.scratch = scratch;
     ba.cap = S.capD;
     launch_basis(st, ba, sc);
+    mark(h, MARK_BASIS);
     // C: cross term over the columns held (Eq. 13), then the new columns R^(t+1)T dX
     hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave)), dim3(kBlock), 0, st, S.Xt,
                        S.capD, Wacc, S.capD, Y, S.capD, sc);
@@ -491,11 +511,20 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
                        &sc->n_cols_total);
     hipLaunchKernelGGL(k_append_ids, dim3(grid_for(nnz)), dim3(kBlock), 0, st, b.fid, &sc->n_f,
                        S.col_fid, nullptr, &sc->n_cols_total, t_off);
+    mark(h, MARK_CORE);
     // slice residual against the grown basis
     ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total, S.capD);
-    launch_project(st, pa, nnz, sc);
+    if (h->opt.profile) {
+      mark(h, MARK_PROJ0);
+      mark(h, MARK_SPMM0);
+      mark(h, MARK_SPMM1);
+    }
+    launch_project(st, pa, nnz, sc, h->opt.profile ? h->ev[MARK_SPMM0] : nullptr,
+                   h->opt.profile ? h->ev[MARK_SPMM1] : nullptr);
+    mark(h, MARK_PROJECTED);
   }
   hipLaunchKernelGGL(k_finish_slice, dim3(1), dim3(1), 0, st, sc);
+  mark(h, MARK_END);
   HIP_CHECK(h, hipGetLastError());
   h->s = d;
   h->step += 1;

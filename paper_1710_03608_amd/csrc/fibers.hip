@@ -35,9 +35,11 @@ __global__ __launch_bounds__(kKeyBlock) void k_build_keys(FiberLayout lay,
                                                           int64_t nnz, uint64_t* __restrict__ keys,
                                                           uint32_t* __restrict__ perm,
                                                           DevScalars* sc) {
-  const int64_t e = (int64_t)blockIdx.x * kKeyBlock + threadIdx.x;
+  __shared__ uint64_t wmax[kKeyBlock / kWave];
   uint64_t v2bits = 0;
-  if (e < nnz) {
+  bool oob_any = false, nan_any = false;
+  for (int64_t e = (int64_t)blockIdx.x * kKeyBlock + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * kKeyBlock) {
     uint64_t fid = 0;
     uint64_t row = 0;
     bool oob = false;
@@ -51,23 +53,31 @@ __global__ __launch_bounds__(kKeyBlock) void k_build_keys(FiberLayout lay,
     }
     const double v = load_val(val, dtype, e);
     if (oob) {
-      latch_status(sc, CTD_ERR_INDEX_OOB);
+      oob_any = true;
       fid = 0;
       row = 0;
     }
-    if (!isfinite(v)) latch_status(sc, CTD_ERR_NONFINITE);
+    const bool fin = isfinite(v);
+    nan_any |= !fin;
     keys[e] = (fid << lay.rbits) | row;
     perm[e] = (uint32_t)e;
-    const double v2 = isfinite(v) ? v * v : 0.0;
-    v2bits = (uint64_t)__double_as_longlong(v2);
+    const uint64_t b = (uint64_t)__double_as_longlong(fin ? v * v : 0.0);
+    v2bits = b > v2bits ? b : v2bits;   // positive doubles order like their bit patterns
   }
-  // positive doubles order like their bit patterns
+  if (oob_any) latch_status(sc, CTD_ERR_INDEX_OOB);
+  if (nan_any) latch_status(sc, CTD_ERR_NONFINITE);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const uint64_t o = __shfl_xor(v2bits, off, kWave);
     v2bits = o > v2bits ? o : v2bits;
   }
-  if (lane_id() == 0 && v2bits) atomicMax((unsigned long long*)&sc->vmax2_bits, (unsigned long long)v2bits);
+  if (lane_id() == 0) wmax[threadIdx.x / kWave] = v2bits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t m = 0;
+    for (int w = 0; w < kKeyBlock / kWave; ++w) m = wmax[w] > m ? wmax[w] : m;
+    if (m) atomicMax((unsigned long long*)&sc->vmax2_bits, (unsigned long long)m);
+  }
 }
 
 __global__ void k_sigma(int64_t nnz, DevScalars* sc) {
@@ -213,8 +223,8 @@ void launch_build_keys(hipStream_t st, const FiberLayout& lay, const int32_t* id
                        const void* val, int val_dtype, int64_t nnz, uint64_t* keys,
                        uint32_t* perm, DevScalars* sc) {
   if (nnz > 0)
-    hipLaunchKernelGGL(k_build_keys, dim3(div_up(nnz, kKeyBlock)), dim3(kKeyBlock), 0, st, lay,
-                       idx, val, val_dtype, nnz, keys, perm, sc);
+    hipLaunchKernelGGL(k_build_keys, dim3(std::min(1024, div_up(nnz, kKeyBlock))), dim3(kKeyBlock),
+                       0, st, lay, idx, val, val_dtype, nnz, keys, perm, sc);
   hipLaunchKernelGGL(k_sigma, dim3(1), dim3(1), 0, st, nnz, sc);
 }
 

@@ -131,6 +131,8 @@ struct ProjectArgs {
   double* partial;         // workspace
   bool mixed;
 };
-void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc);
+// ev0/ev1 (optional) are recorded right before and after the multi-nonzero SpMM kernel.
+void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace ctd

@@ -176,16 +176,19 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_final(const double* __rest
 __global__ void k_zero_i32(int32_t* p) { *p = 0; }
 }  // namespace
 
-void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc) {
+void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,
+                    hipEvent_t ev0, hipEvent_t ev1) {
   int32_t* n_multi = &sc->n_multi;
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, n_multi);
   const int gs = std::max(1, std::min(8192, div_up(nnz_max, kBlock)));
   hipLaunchKernelGGL(k_proj_single, dim3(gs), dim3(kBlock), 0, st, a, sc, n_multi);
   const int gm = std::max(1, std::min(4096, div_up(nnz_max / 2 * kWave, kBlock)));
+  if (ev0) (void)hipEventRecord(ev0, st);
   if (a.mixed)
     hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(gm), dim3(kBlock), 0, st, a, sc, n_multi);
   else
     hipLaunchKernelGGL((k_proj_multi<double, 4>), dim3(gm), dim3(kBlock), 0, st, a, sc, n_multi);
+  if (ev1) (void)hipEventRecord(ev1, st);
   const int np = std::max(1, div_up(nnz_max, kRedBlock * kRedItems));
   hipLaunchKernelGGL(k_reduce_partial, dim3(np), dim3(kRedBlock), 0, st, a.resid, a.partial, sc);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedBlock), 0, st, a.partial, np, sc);
