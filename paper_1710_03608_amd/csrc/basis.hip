@@ -25,6 +25,66 @@ constexpr int kB = 64;        // candidates per block
 constexpr int kSplit = 64;    // row splits of the 64 x 64 Gram products
 constexpr int kBlock = 256;
 
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; the 16 x 16 result D[i][j] sits in lane j + 16 (i % 4)
+// at component i / 4 (lane l holds D[l / 16 + 4 r][l % 16], r = 0..3).
+__device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Double-double arithmetic (a value is hi + lo with |lo| <= ulp(hi)/2): the
+// error-free transforms of Knuth (two_sum) and Dekker/FMA (two_prod).  FMA
+// contraction is switched off inside them: fusing a product into the sum
+// that follows it would break the exactness the transforms rely on.
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ inline void quick_two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  e = b - (s - a);
+}
+__device__ inline void two_prod(double a, double b, double& p, double& e) {
+#pragma clang fp contract(off)
+  p = a * b;
+  e = fma(a, b, -p);
+}
+// (ah, al) -= (bh, bl) * (ch, cl)
+__device__ inline void dd_fnma(double& ah, double& al, double bh, double bl, double ch, double cl) {
+#pragma clang fp contract(off)
+  double p, pe;
+  two_prod(bh, ch, p, pe);
+  pe = fma(bh, cl, pe);
+  pe = fma(bl, ch, pe);
+  double s, se;
+  two_sum(ah, -p, s, se);
+  se += al - pe;
+  quick_two_sum(s, se, ah, al);
+}
+__device__ inline void dd_sqrt(double ah, double al, double& sh, double& sl) {
+#pragma clang fp contract(off)
+  const double s = sqrt(ah);
+  double p, pe;
+  two_prod(s, s, p, pe);
+  const double r = ((ah - p) - pe) + al;
+  quick_two_sum(s, r / (2.0 * s), sh, sl);
+}
+__device__ inline void dd_div(double ah, double al, double bh, double bl, double& qh, double& ql) {
+#pragma clang fp contract(off)
+  const double q1 = ah / bh;
+  double p, pe;
+  two_prod(q1, bh, p, pe);
+  pe = fma(q1, bl, pe);
+  const double r = ((ah - p) - pe) + al;
+  quick_two_sum(q1, r / bh, qh, ql);
+}
+
 __device__ inline int64_t blk_count(const DevScalars* sc, int64_t b0) {
   const int64_t sp = sc->status == 0 ? sc->s_unique : 0;
   return b0 < sp ? min((int64_t)kB, sp - b0) : 0;
@@ -47,8 +107,8 @@ __global__ __launch_bounds__(kBlock) void k_blk_norms(const int32_t* __restrict_
   if (lane_id() == 0) g[j] = s;
 }
 
-// W[j][c] = sum_e v_e Q[r_e][c] for c < k; one wave per (candidate, 128
-// columns), eight nonzeros in flight per iteration.
+// W[j][c] = sum_e v_e Q[r_e][c] for c < k; one wave per (candidate, 64
+// columns), sixteen nonzeros in flight per iteration.
 __global__ __launch_bounds__(kBlock) void k_blk_w(const double* __restrict__ Q, int64_t ldq,
                                                   const int32_t* __restrict__ uniq_fi,
                                                   const int32_t* __restrict__ fptr,
@@ -56,102 +116,159 @@ __global__ __launch_bounds__(kBlock) void k_blk_w(const double* __restrict__ Q, 
                                                   const double* __restrict__ val, int64_t b0,
                                                   double* __restrict__ W, int64_t ldw, int nchunk,
                                                   const DevScalars* sc) {
+  constexpr int kU = 16;
   const int64_t nb = blk_count(sc, b0);
   const int64_t k = sc->n_accept_total;
   const int64_t wid = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const int j = (int)(wid / nchunk);
-  const int64_t c = (wid % nchunk) * 2 * kWave + 2 * lane_id();
-  if (j >= nb || (wid % nchunk) * 2 * kWave >= k) return;
+  const int64_t cbase = (wid % nchunk) * kWave;
+  if (j >= nb || cbase >= k) return;
+  const int64_t c = cbase + lane_id();
   const bool active = c < k;
+  const double* Qc = Q + (active ? c : 0);
   const int32_t f = uniq_fi[b0 + j];
   const int32_t e0 = fptr[f], e1 = fptr[f + 1];
-  double a0 = 0.0, a1 = 0.0;
+  double acc = 0.0;
   int32_t e = e0;
-  for (; e + 8 <= e1; e += 8) {
-    int32_t r[8];
-    double v[8];
+  for (; e + kU <= e1; e += kU) {
+    int32_t r[kU];
+    double v[kU], q[kU];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kU; ++u) {
       r[u] = row[e + u];
       v[u] = val[e + u];
     }
-    double2 q[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      q[u] = active ? *(const double2*)(Q + (int64_t)r[u] * ldq + c) : make_double2(0.0, 0.0);
+    for (int u = 0; u < kU; ++u) q[u] = Qc[(int64_t)r[u] * ldq];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a0 += v[u] * q[u].x;
-      a1 += v[u] * q[u].y;
-    }
+    for (int u = 0; u < kU; ++u) acc += v[u] * q[u];
   }
-  for (; e < e1; ++e) {
-    const double v = val[e];
-    if (active) {
-      const double2 q = *(const double2*)(Q + (int64_t)row[e] * ldq + c);
-      a0 += v * q.x;
-      a1 += v * q.y;
-    }
-  }
-  if (active) {
-    double* w = W + (int64_t)j * ldw + c;
-    w[0] = a0;
-    if (c + 1 < k) w[1] = a1;
-  }
+  for (; e < e1; ++e) acc += val[e] * Qc[(int64_t)row[e] * ldq];
+  if (active) W[(int64_t)j * ldw + c] = acc;
 }
 
 // Y[r][j] = P[r][b0 + j] - sum_{c<k} Q[r][c] W[j][c] for every candidate j of
 // the block (residuals against span(Q)), into Ybuf (n_rows x 64).  One
-// workgroup per 32 rows; each thread owns 2 rows x 4 candidates.
+// workgroup per 32 rows; wave w computes rows 16 (w / 2) .. + 16 and
+// candidates 32 (w % 2) .. + 32 with two f64 MFMA accumulators.
+// With reproject set, the base is Ybuf itself (second projection pass):
+// Ybuf[r][j] -= sum_c Q[r][c] W2[j][c].
 __global__ __launch_bounds__(kBlock) void k_blk_form_y(const double* __restrict__ P, int64_t ldp,
                                                        int64_t n_rows, const double* __restrict__ Q,
                                                        int64_t ldq, const double* __restrict__ W,
                                                        int64_t ldw, int64_t b0,
-                                                       double* __restrict__ Ybuf,
+                                                       double* __restrict__ Ybuf, bool reproject,
                                                        const DevScalars* sc) {
   constexpr int kR = 32;
   constexpr int kK = 32;
-  __shared__ double Qs[kK][kR + 1];   // [c][row]
-  __shared__ double Ws[kK][kB + 1];   // [c][j]
+  __shared__ double As[kR][kK + 1];   // Q tile [row][c]
+  __shared__ double Bs[kK][kB + 1];   // W^T tile [c][j]
   const int64_t nb = blk_count(sc, b0);
   if (nb == 0) return;
   const int64_t k = sc->n_accept_total;
+  if (reproject && k == 0) return;
   const int64_t r0 = (int64_t)blockIdx.x * kR;
-  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  double acc[2][4] = {};
+  const int w = threadIdx.x / kWave, l = lane_id();
+  const int rb = (w / 2) * 16, cb = (w % 2) * 32;
+  dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   for (int64_t c0 = 0; c0 < k; c0 += kK) {
     __syncthreads();
-    for (int t = threadIdx.x; t < kK * kR; t += kBlock) {
-      const int a = t / kK, c = t % kK;
-      Qs[c][a] = (c0 + c < k && r0 + a < n_rows) ? Q[(r0 + a) * ldq + c0 + c] : 0.0;
+    for (int t = threadIdx.x; t < kR * kK; t += kBlock) {
+      const int r = t / kK, c = t % kK;
+      As[r][c] = (c0 + c < k && r0 + r < n_rows) ? Q[(r0 + r) * ldq + c0 + c] : 0.0;
     }
     for (int t = threadIdx.x; t < kK * kB; t += kBlock) {
-      const int a = t / kK, c = t % kK;
-      Ws[c][a] = (c0 + c < k && a < nb) ? W[(int64_t)a * ldw + c0 + c] : 0.0;
+      const int j = t / kK, c = t % kK;
+      Bs[c][j] = (c0 + c < k && j < nb) ? W[(int64_t)j * ldw + c0 + c] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int c = 0; c < kK; ++c) {
-      const double x0 = Qs[c][ty * 2], x1 = Qs[c][ty * 2 + 1];
-      double y[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) y[v] = Ws[c][tx * 4 + v];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        acc[0][v] += x0 * y[v];
-        acc[1][v] += x1 * y[v];
-      }
+    for (int ks = 0; ks < kK / 4; ++ks) {
+      const double a = As[rb + l % 16][ks * 4 + l / 16];
+      const double b0v = Bs[ks * 4 + l / 16][cb + l % 16];
+      const double b1v = Bs[ks * 4 + l / 16][cb + 16 + l % 16];
+      acc0 = mfma16(a, b0v, acc0);
+      acc1 = mfma16(a, b1v, acc1);
     }
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int64_t r = r0 + ty * 2 + u;
-    if (r >= n_rows) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = tx * 4 + v;
-      Ybuf[r * kB + j] = j < nb ? P[r * ldp + b0 + j] - acc[u][v] : 0.0;
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = r0 + rb + l / 16 + 4 * r;
+    if (row >= n_rows) continue;
+    const int j0 = cb + l % 16, j1 = cb + 16 + l % 16;
+    if (reproject) {
+      if (j0 < nb) Ybuf[row * kB + j0] -= acc0[r];
+      if (j1 < nb) Ybuf[row * kB + j1] -= acc1[r];
+    } else {
+      Ybuf[row * kB + j0] = j0 < nb ? P[row * ldp + b0 + j0] - acc0[r] : 0.0;
+      Ybuf[row * kB + j1] = j1 < nb ? P[row * ldp + b0 + j1] - acc1[r] : 0.0;
     }
+  }
+}
+
+// Second projection coefficients W2[j][c] = sum_r Q[r][c] Y[r][j] for c < k,
+// partial over kSplitW row ranges: workgroup (ct, s) covers c in
+// [64 ct, 64 ct + 64); wave w computes c rows 16 w .. + 16 against all 64 j
+// with four f64 MFMA tiles.
+constexpr int kSplitW = 16;
+__global__ __launch_bounds__(kBlock) void k_blk_w2_part(const double* __restrict__ Q, int64_t ldq,
+                                                        int64_t n_rows,
+                                                        const double* __restrict__ Y,
+                                                        double* __restrict__ W2p, int64_t ldw,
+                                                        int64_t b0, const DevScalars* sc) {
+  constexpr int kK = 32;
+  __shared__ double Qs[kK][kB + 1];   // [r][c]
+  __shared__ double Ys[kK][kB + 1];   // [r][j]
+  const int64_t nb = blk_count(sc, b0);
+  const int64_t k = sc->n_accept_total;
+  const int64_t c0 = (int64_t)blockIdx.x * kB;
+  if (nb == 0 || c0 >= k) return;
+  const int64_t chunk = (n_rows + kSplitW - 1) / kSplitW;
+  const int64_t r0 = blockIdx.y * chunk, r1 = min(n_rows, r0 + chunk);
+  const int w = threadIdx.x / kWave, l = lane_id();
+  dbl4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int64_t rr = r0; rr < r1; rr += kK) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < kK * kB; t += kBlock) {
+      const int r = t / kB, c = t % kB;
+      const bool rin = rr + r < r1;
+      Qs[r][c] = (rin && c0 + c < k) ? Q[(rr + r) * ldq + c0 + c] : 0.0;
+      Ys[r][c] = (rin && c < nb) ? Y[(rr + r) * kB + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kK / 4; ++ks) {
+      const double a = Qs[ks * 4 + l / 16][w * 16 + l % 16];   // A = Q^T: A[c][r] = Q[r][c]
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = mfma16(a, Ys[ks * 4 + l / 16][q * 16 + l % 16], acc[q]);
+    }
+  }
+  double* p = W2p + (int64_t)blockIdx.y * kB * ldw;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t c = c0 + w * 16 + l / 16 + 4 * r;
+      const int j = q * 16 + l % 16;
+      if (c < k) p[(int64_t)j * ldw + c] = acc[q][r];
+    }
+}
+
+// W2[j][c] = sum_s W2p[s][j][c] (fixed order); W[j][c] += W2[j][c].
+__global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const double* __restrict__ W2p,
+                                                       double* __restrict__ W2,
+                                                       double* __restrict__ W, int64_t ldw,
+                                                       int64_t b0, const DevScalars* sc) {
+  const int64_t nb = blk_count(sc, b0);
+  const int64_t k = sc->n_accept_total;
+  const int64_t total = nb * k;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t j = t / k, c = t % k;
+    double s = 0.0;
+    for (int p = 0; p < kSplitW; ++p) s += W2p[(int64_t)p * kB * ldw + j * ldw + c];
+    W2[j * ldw + c] = s;
+    W[j * ldw + c] += s;
   }
 }
 
@@ -159,26 +276,67 @@ __global__ __launch_bounds__(kBlock) void k_blk_form_y(const double* __restrict_
 //   part[s][i][j] = sum_{r in range s} Y[r][col0 + i] Y[r][col0 + j]
 // mode 0: Y = the block buffer (col0 = 0, width = candidates of the block)
 // mode 1: Y = Q[:, k : k + na]   (the kept block after its first pass)
+// Wave w computes rows 16 w .. + 16 of the 64 x 64 result (four MFMA tiles).
 __global__ __launch_bounds__(kBlock) void k_blk_gram_part(const double* __restrict__ A, int64_t lda,
                                                           int64_t K, int mode, int64_t b0,
                                                           double* __restrict__ part,
                                                           const DevScalars* sc) {
-  __shared__ double As[kB][kB + 1];   // [kk][i]
+  constexpr int kK = 64;
+  __shared__ double Ys[kK][kB + 1];   // [row][col]
   const int64_t col0 = mode == 0 ? 0 : (int64_t)sc->n_accept_total;
   const int64_t width = mode == 0 ? blk_count(sc, b0) : (int64_t)sc->blk_na;
   if (width == 0) return;  // nothing downstream reads part for an empty block
   const int64_t chunk = (K + kSplit - 1) / kSplit;
   const int64_t k0 = blockIdx.x * chunk;
   const int64_t k1 = min(K, k0 + chunk);
+  const int w = threadIdx.x / kWave, l = lane_id();
+  dbl4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int64_t kk0 = k0; kk0 < k1; kk0 += kK) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < kK * kB; t += kBlock) {
+      const int kk = t / kB, i = t % kB;
+      Ys[kk][i] = (kk0 + kk < k1 && i < width) ? A[(kk0 + kk) * lda + col0 + i] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kK / 4; ++ks) {
+      const double a = Ys[ks * 4 + l / 16][w * 16 + l % 16];   // A = Y^T: A[i][kk] = Y[kk][i]
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = mfma16(a, Ys[ks * 4 + l / 16][q * 16 + l % 16], acc[q]);
+    }
+  }
+  double* p = part + (int64_t)blockIdx.x * kB * kB;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p[(w * 16 + l / 16 + 4 * r) * kB + q * 16 + l % 16] = acc[q][r];
+}
+
+// Double-double Gram of the block buffer, partial over kSplitDD row ranges:
+// (hi, lo)[s][i][j] = sum_{r in range s} Y[r][i] Y[r][j], each product split
+// exactly by an FMA and accumulated with two_sum.  The independence decisions
+// need the block Gram to about u^2: rounding it to float64 alone moves the
+// Schur complement of an exactly dependent candidate to ~u * cond^2 ||x||^2,
+// which can reach eps^2 ||x||^2.
+constexpr int kSplitDD = 128;
+__global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const double* __restrict__ Y,
+                                                        int64_t n_rows, int64_t b0,
+                                                        double* __restrict__ part_hi,
+                                                        double* __restrict__ part_lo,
+                                                        const DevScalars* sc) {
+  __shared__ double Ys[kB][kB + 1];   // [row][col]
+  const int64_t width = blk_count(sc, b0);
+  if (width == 0) return;
+  const int64_t chunk = (n_rows + kSplitDD - 1) / kSplitDD;
+  const int64_t k0 = blockIdx.x * chunk;
+  const int64_t k1 = min(n_rows, k0 + chunk);
   const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  double acc[4][4] = {};
+  double hi[4][4] = {}, lo[4][4] = {};
   for (int64_t kk0 = k0; kk0 < k1; kk0 += kB) {
     __syncthreads();
     for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
       const int kk = t / kB, i = t % kB;
-      double v = 0.0;
-      if (kk0 + kk < k1 && i < width) v = A[(kk0 + kk) * lda + col0 + i];
-      As[kk][i] = v;
+      Ys[kk][i] = (kk0 + kk < k1 && i < width) ? Y[(kk0 + kk) * kB + i] : 0.0;
     }
     __syncthreads();
     const int kn = (int)min((int64_t)kB, k1 - kk0);
@@ -186,20 +344,50 @@ __global__ __launch_bounds__(kBlock) void k_blk_gram_part(const double* __restri
       double x[4], y[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        x[u] = As[kk][ty * 4 + u];
-        y[u] = As[kk][tx * 4 + u];
+        x[u] = Ys[kk][ty * 4 + u];
+        y[u] = Ys[kk][tx * 4 + u];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
+        for (int v = 0; v < 4; ++v) {
+          double p, pe, s2, se;
+          two_prod(x[u], y[v], p, pe);
+          two_sum(hi[u][v], p, s2, se);
+          hi[u][v] = s2;
+          lo[u][v] += se + pe;
+        }
     }
   }
-  double* p = part + (int64_t)blockIdx.x * kB * kB;
+  const int64_t off = (int64_t)blockIdx.x * kB * kB;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) p[(ty * 4 + u) * kB + tx * 4 + v] = acc[u][v];
+    for (int v = 0; v < 4; ++v) {
+      const int t = (ty * 4 + u) * kB + tx * 4 + v;
+      double h, l;
+      quick_two_sum(hi[u][v], lo[u][v], h, l);
+      part_hi[off + t] = h;
+      part_lo[off + t] = l;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_blk_sum_dd(const double* __restrict__ part_hi,
+                                                       const double* __restrict__ part_lo,
+                                                       double* __restrict__ G_hi,
+                                                       double* __restrict__ G_lo, int64_t b0,
+                                                       const DevScalars* sc) {
+  if (blk_count(sc, b0) == 0) return;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= kB * kB) return;
+  double h = 0.0, l = 0.0;
+  for (int p = 0; p < kSplitDD; ++p) {
+    double s2, e;
+    two_sum(h, part_hi[(int64_t)p * kB * kB + t], s2, e);
+    h = s2;
+    l += e + part_lo[(int64_t)p * kB * kB + t];
+  }
+  quick_two_sum(h, l, G_hi[t], G_lo[t]);
 }
 
 // G[i][j] = sum_s part[s][i][j] in a fixed order (deterministic).
@@ -215,22 +403,105 @@ __global__ __launch_bounds__(kBlock) void k_blk_sum_parts(const double* __restri
   G[t] = s;
 }
 
-// Lane c of one wave: column c of L^{-1} for the na x na lower factor in Lm
-// (identity-padded), written transposed into Tout: Tout[c][r] = L^{-1}[r][c].
-__device__ inline void wave_tri_inverse_t(double (*Lm)[kB + 1], double (*Xs)[kB + 1], int na,
-                                          double* __restrict__ Tout) {
-  const int c = threadIdx.x;
-  for (int r = 0; r < kB; ++r) Xs[r][c] = 0.0;
-  if (c < na) {
-    Xs[c][c] = 1.0 / Lm[c][c];
-    for (int r = c + 1; r < na; ++r) {
-      double x = 0.0;
-      for (int j = c; j < r; ++j) x += Lm[r][j] * Xs[j][c];
-      Xs[r][c] = -x / Lm[r][r];
+// Broadcast a double from a compile-time lane (two v_readlane_b32).
+__device__ inline double bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// One wave factors a 64 x 64 symmetric matrix held one row per lane
+// (row[c] = G[i][c], c <= i): a right-looking Cholesky in candidate order.
+// Step j broadcasts the pivot, keeps or drops candidate j, scales column j and
+// updates the trailing rows; elements of column j travel by readlane.  Fully
+// unrolled so that every row element stays in a register.  With drop == false
+// every pivot is kept.  Returns the kept mask; dropped rows/columns come out
+// as identity rows, so the inverse of the result restricted to the kept set is
+// the inverse of the kept factor.
+__device__ inline uint64_t wave_chol(double (&row)[kB], bool drop, double eps2, double gi, int n,
+                                     int64_t room) {
+  const int i = threadIdx.x;
+  uint64_t kept_mask = 0;
+  int kept = 0;
+#pragma unroll
+  for (int j = 0; j < kB; ++j) {
+    const double d = bcast(row[j], j);
+    const double gj = bcast(gi, j);
+    const bool keep = j < n && (drop ? (d > eps2 * gj && kept < room) : true);
+    if (keep) {
+      const double l = sqrt(fmax(d, 1e-300));
+      const double rl = 1.0 / l;
+      if (i == j) row[j] = l;
+      if (i > j) row[j] *= rl;
+#pragma unroll
+      for (int c = j + 1; c < kB; ++c) {
+        const double lcj = bcast(row[j], c);
+        if (i >= c) row[c] -= row[j] * lcj;
+      }
+      ++kept;
+      kept_mask |= 1ull << j;
+    } else if (i >= j) {
+      row[j] = 0.0;
     }
   }
-  __syncthreads();
-  for (int b = 0; b < kB; ++b) Tout[c * kB + b] = (c < na && b < na) ? Xs[b][c] : 0.0;
+  if (!((kept_mask >> i) & 1ull)) {
+#pragma unroll
+    for (int c = 0; c < kB; ++c) row[c] = (c == i) ? 1.0 : 0.0;
+  }
+  return kept_mask;
+}
+
+// Lane c computes column c of L^{-1} (L held one row per lane in `row`) by
+// forward substitution: x[r] = L^{-1}[r][c].
+__device__ inline void wave_tri_inv_col(const double (&row)[kB], double (&x)[kB]) {
+  const int c = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < kB; ++r) {
+    double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < r; ++j) s -= bcast(row[j], r) * x[j];
+    x[r] = s / bcast(row[r], r);
+  }
+}
+
+// The drop decisions of wave_chol in double-double: rows (rh, rl) held one
+// per lane.  Returns the kept mask; rh comes out as the float64 factor with
+// identity rows for dropped candidates (as wave_chol).
+__device__ inline uint64_t wave_chol_dd(double (&rh)[kB], double (&rl)[kB], double eps2, double gi,
+                                        int n, int64_t room) {
+  const int i = threadIdx.x;
+  uint64_t kept_mask = 0;
+  int kept = 0;
+#pragma unroll
+  for (int j = 0; j < kB; ++j) {
+    const double dh = bcast(rh[j], j), dl = bcast(rl[j], j);
+    const double gj = bcast(gi, j);
+    const bool keep = j < n && ((dh - eps2 * gj) + dl > 0.0) && kept < room;
+    if (keep) {
+      double lh, ll;
+      dd_sqrt(dh, dl, lh, ll);
+      if (i == j) {
+        rh[j] = lh;
+        rl[j] = ll;
+      }
+      if (i > j) dd_div(rh[j], rl[j], lh, ll, rh[j], rl[j]);
+#pragma unroll
+      for (int c = j + 1; c < kB; ++c) {
+        const double ch = bcast(rh[j], c), cl = bcast(rl[j], c);
+        if (i >= c) dd_fnma(rh[c], rl[c], rh[j], rl[j], ch, cl);
+      }
+      ++kept;
+      kept_mask |= 1ull << j;
+    } else if (i >= j) {
+      rh[j] = 0.0;
+      rl[j] = 0.0;
+    }
+  }
+  if (!((kept_mask >> i) & 1ull)) {
+#pragma unroll
+    for (int c = 0; c < kB; ++c) rh[c] = (c == i) ? 1.0 : 0.0;
+  }
+  return kept_mask;
 }
 
 // One wave: the block's residual Gram G; Cholesky with column drop in
@@ -238,13 +509,13 @@ __device__ inline void wave_tri_inverse_t(double (*Lm)[kB + 1], double (*Xs)[kB 
 // pos[0..na), na into sc->blk_na; Tacc = L_A^{-T} over the kept rows/columns
 // (first Cholesky-QR pass of the kept residuals).
 __global__ __launch_bounds__(kWave) void k_blk_decide(const double* __restrict__ G,
+                                                      const double* __restrict__ Glo,
                                                       const double* __restrict__ g, double eps2,
                                                       int64_t b0, int64_t n_rows,
                                                       int32_t* __restrict__ pos,
                                                       int32_t* __restrict__ accept_all,
                                                       double* __restrict__ Tacc,
                                                       DevScalars* sc) {
-  __shared__ double T[kB][kB + 1];
   __shared__ double Xs[kB][kB + 1];
   __shared__ int32_t ps[kB];
   const int64_t nb = blk_count(sc, b0);
@@ -253,36 +524,18 @@ __global__ __launch_bounds__(kWave) void k_blk_decide(const double* __restrict__
     if (i == 0) sc->blk_na = 0;
     return;
   }
-  const int64_t k_now = sc->n_accept_total;
-  for (int j = 0; j < kB; ++j) T[j][i] = (i < nb && j < nb && i <= j) ? G[j * kB + i] : 0.0;
-  const double gi = i < nb ? g[i] : 0.0;
-  __syncthreads();
-  int kept = 0;
-  bool my_keep = false;
-  for (int j = 0; j < nb; ++j) {
-    const double d = T[j][j];
-    const double gj = __shfl(gi, j, kWave);
-    // at most n_rows fibers can be independent
-    const bool keep = d > eps2 * gj && k_now + kept < n_rows;
-    kept += keep ? 1 : 0;
-    __syncthreads();
-    if (keep) {
-      const double l = sqrt(d);
-      if (i >= j) T[i][j] = (i == j) ? l : T[i][j] / l;
-      __syncthreads();
-      if (i > j && i < nb) {
-        const double lij = T[i][j];
-        for (int c = j + 1; c <= i; ++c) T[i][c] -= lij * T[c][j];
-      }
-    } else {
-      if (i >= j) T[i][j] = 0.0;
-    }
-    if (i == j) my_keep = keep;
-    __syncthreads();
+  const int64_t room = n_rows - (int64_t)sc->n_accept_total;   // at most n_rows independent fibers
+  double row[kB], rlo[kB];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) {
+    row[c] = (i < nb && c <= i) ? G[i * kB + c] : 0.0;
+    rlo[c] = (i < nb && c <= i) ? Glo[i * kB + c] : 0.0;
   }
-  const uint64_t m = __ballot(my_keep && i < nb);
+  const double gi = i < nb ? g[i] : 0.0;
+  const uint64_t m = wave_chol_dd(row, rlo, eps2, gi, (int)nb, room);
+  const bool my_keep = (m >> i) & 1ull;
   const int na = (int)__popcll(m);
-  if (my_keep && i < nb) {
+  if (my_keep) {
     const uint64_t lt = i == 0 ? 0ull : ((~0ull) >> (kWave - i));
     const int slot = (int)__popcll(m & lt);
     pos[slot] = i;
@@ -290,12 +543,15 @@ __global__ __launch_bounds__(kWave) void k_blk_decide(const double* __restrict__
   }
   if (i < nb && accept_all) accept_all[b0 + i] = my_keep ? 1 : 0;
   if (i == 0) sc->blk_na = na;
+  double x[kB];
+  wave_tri_inv_col(row, x);      // x[r] = L^{-1}[r][i]
+#pragma unroll
+  for (int r = 0; r < kB; ++r) Xs[r][i] = x[r];
   __syncthreads();
-  // compact L_A into Xs (reused as the factor), then invert
-  for (int r = 0; r < kB; ++r)
-    Xs[r][i] = (r < na && i < na) ? (i <= r ? T[ps[r]][ps[i]] : 0.0) : (r == i ? 1.0 : 0.0);
-  __syncthreads();
-  wave_tri_inverse_t(Xs, T, na, Tacc);
+  // Tacc[a][b] = L_A^{-1}[b][a] = L^{-1}[ps[b]][ps[a]]
+  const int pa = i < na ? ps[i] : 0;
+  for (int bb = 0; bb < kB; ++bb)
+    Tacc[i * kB + bb] = (i < na && bb < na) ? Xs[ps[bb]][pa] : 0.0;
 }
 
 // One wave: Cholesky (no drop) of the kept block's Gram after its first pass,
@@ -304,40 +560,36 @@ __global__ __launch_bounds__(kWave) void k_blk_cholinv(const double* __restrict_
                                                        double* __restrict__ Tcur,
                                                        double* __restrict__ Tacc,
                                                        const DevScalars* sc) {
-  __shared__ double Lm[kB][kB + 1];
-  __shared__ double Xs[kB][kB + 1];
   const int na = sc->blk_na;
   const int i = threadIdx.x;
   if (na == 0) return;
-  for (int j = 0; j < kB; ++j)
-    Lm[j][i] = (i < na && j < na) ? G[j * kB + i] : (i == j ? 1.0 : 0.0);
-  __syncthreads();
-  for (int j = 0; j < na; ++j) {
-    const double l = sqrt(fmax(Lm[j][j], 1e-300));
-    __syncthreads();
-    if (i >= j) Lm[i][j] = (i == j) ? l : Lm[i][j] / l;
-    __syncthreads();
-    if (i > j && i < na) {
-      const double lij = Lm[i][j];
-      for (int c = j + 1; c <= i; ++c) Lm[i][c] -= lij * Lm[c][j];
-    }
-    __syncthreads();
+  double row[kB];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) row[c] = (i < na && c <= i) ? G[i * kB + c] : 0.0;
+  wave_chol(row, false, 0.0, 0.0, na, kB);
+  double x[kB];
+  wave_tri_inv_col(row, x);      // x[r] = L^{-1}[r][i] = Tcur[i][r]
+  const bool live = i < na;
+#pragma unroll
+  for (int r = 0; r < kB; ++r) Tcur[i * kB + r] = (live && r < na) ? x[r] : 0.0;
+  // Tacc <- Tacc Tcur: row i of the product; Tcur[a][b] = x[b] of lane a
+#pragma unroll
+  for (int c = 0; c < kB; ++c) row[c] = Tacc[i * kB + c];
+  double out[kB];
+#pragma unroll
+  for (int bcol = 0; bcol < kB; ++bcol) out[bcol] = 0.0;
+#pragma unroll
+  for (int a = 0; a < kB; ++a) {
+#pragma unroll
+    for (int bcol = a; bcol < kB; ++bcol) out[bcol] += row[a] * bcast(x[bcol], a);
   }
-  wave_tri_inverse_t(Lm, Xs, na, Tcur);
-  __syncthreads();
-  // Tacc <- Tacc Tcur: stage Tacc in Lm, Tcur is Xs^T
-  for (int b = 0; b < kB; ++b) Lm[i][b] = Tacc[i * kB + b];
-  __syncthreads();
-  for (int b = 0; b < kB; ++b) {
-    double s = 0.0;
-    for (int a = 0; a <= b; ++a) s += Lm[i][a] * Xs[b][a];
-    Tacc[i * kB + b] = (i < na && b < na) ? s : 0.0;
-  }
+#pragma unroll
+  for (int bcol = 0; bcol < kB; ++bcol) Tacc[i * kB + bcol] = (live && bcol < na) ? out[bcol] : 0.0;
 }
 
 // Kept residuals times the first-pass factor: Q[r][k + a] = sum_{a' <= a}
-// Ybuf[r][pos[a']] T[a'][a]; R[r][k + a] = P[r][b0 + pos[a]].  Four threads
-// per row, 16 output columns each.
+// Ybuf[r][pos[a']] T[a'][a]; R[r][k + a] = P[r][b0 + pos[a]].  A workgroup
+// stages 64 rows of Ybuf in LDS; four threads per row, 16 outputs each.
 __global__ __launch_bounds__(kBlock) void k_blk_take(const double* __restrict__ Ybuf,
                                                      const double* __restrict__ P, int64_t ldp,
                                                      int64_t n_rows, const int32_t* __restrict__ pos,
@@ -346,81 +598,86 @@ __global__ __launch_bounds__(kBlock) void k_blk_take(const double* __restrict__ 
                                                      double* __restrict__ R, int64_t ldr,
                                                      const DevScalars* sc) {
   __shared__ double Ts[kB][kB + 1];
+  __shared__ double Ys[kB][kB + 1];
   __shared__ int32_t ps[kB];
   const int na = sc->blk_na;
   if (na == 0) return;
   const int64_t k = sc->n_accept_total;
-  for (int t = threadIdx.x; t < kB * kB; t += kBlock) Ts[t / kB][t % kB] = T[t];
+  const int64_t r0 = (int64_t)blockIdx.x * kB;
+  for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
+    Ts[t / kB][t % kB] = T[t];
+    const int64_t rr = r0 + t / kB;
+    Ys[t / kB][t % kB] = rr < n_rows ? Ybuf[rr * kB + t % kB] : 0.0;
+  }
   if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
   __syncthreads();
-  const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 4;
-  const int q4 = threadIdx.x % 4;
-  if (r >= n_rows) return;
-  const int a_lo = q4 * 16;
-  if (a_lo >= na) return;
-  const int a_hi = min(na, a_lo + 16);
+  const int rl = threadIdx.x / 4;
+  const int64_t r = r0 + rl;
+  const int a_lo = (threadIdx.x % 4) * 16;
+  if (r >= n_rows || a_lo >= na) return;
   double out[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) out[u] = 0.0;
-  for (int ap = 0; ap < a_hi; ++ap) {
-    const double y = Ybuf[r * kB + ps[ap]];
+  for (int ap = 0; ap < na; ++ap) {
+    const double y = Ys[rl][ps[ap]];
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (ap <= a_lo + u) out[u] += y * Ts[ap][a_lo + u];
+    for (int u = 0; u < 16; ++u) out[u] += y * Ts[ap][a_lo + u];
   }
   double* q = Q + r * ldq + k;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int a = a_lo + u;
-    if (a < a_hi) {
+    if (a < na) {
       q[a] = out[u];
       if (R) R[r * ldr + k + a] = P[r * ldp + b0 + ps[a]];
     }
   }
 }
 
-// Q[r][k + a] <- sum_{a' <= a} Q[r][k + a'] T[a'][a]; four threads per row.
+// Q[r][k + a] <- sum_{a' <= a} Q[r][k + a'] T[a'][a]; rows staged in LDS.
 __global__ __launch_bounds__(kBlock) void k_blk_apply(double* __restrict__ Q, int64_t ldq,
                                                       int64_t n_rows, const double* __restrict__ T,
                                                       const DevScalars* sc) {
   __shared__ double Ts[kB][kB + 1];
+  __shared__ double Ys[kB][kB + 1];
   const int na = sc->blk_na;
   if (na == 0) return;
   const int64_t k = sc->n_accept_total;
-  for (int t = threadIdx.x; t < kB * kB; t += kBlock) Ts[t / kB][t % kB] = T[t];
+  const int64_t r0 = (int64_t)blockIdx.x * kB;
+  for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
+    Ts[t / kB][t % kB] = T[t];
+    const int64_t rr = r0 + t / kB;
+    const int c = t % kB;
+    Ys[t / kB][c] = (rr < n_rows && c < na) ? Q[rr * ldq + k + c] : 0.0;
+  }
   __syncthreads();
-  const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 4;
-  const int q4 = threadIdx.x % 4;
-  const bool live = r < n_rows && q4 * 16 < na;
-  double* q = Q + r * ldq + k;
-  const int a_lo = q4 * 16;
-  const int a_hi = min(na, a_lo + 16);
+  const int rl = threadIdx.x / 4;
+  const int64_t r = r0 + rl;
+  const int a_lo = (threadIdx.x % 4) * 16;
+  if (r >= n_rows || a_lo >= na) return;
   double out[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) out[u] = 0.0;
-  if (live) {
-    for (int ap = 0; ap < a_hi; ++ap) {
-      const double y = q[ap];
+  for (int ap = 0; ap < na; ++ap) {
+    const double y = Ys[rl][ap];
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (ap <= a_lo + u) out[u] += y * Ts[ap][a_lo + u];
-    }
+    for (int u = 0; u < 16; ++u) out[u] += y * Ts[ap][a_lo + u];
   }
-  // all four threads of a row read the row before any writes it
-  __syncthreads();
-  if (live) {
+  double* q = Q + r * ldq + k;
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (a_lo + u < a_hi) q[a_lo + u] = out[u];
-  }
+  for (int u = 0; u < 16; ++u)
+    if (a_lo + u < na) q[a_lo + u] = out[u];
 }
 
-// Z[a][c] = sum_{c <= j < k} M[c][j] W[pos[a]][j] for c < k; one workgroup
-// per 64 rows of M, 4 x 4 outputs per thread.
+// Z[a][c] = sum_{c <= j < k} M[c][j] W[pos[a]][j] for c < k (M upper
+// triangular), split over j: workgroup (ct, js) covers rows 64 ct .. + 64 and
+// j in [256 js, 256 js + 256), writing Zp[js][a][c] (zero when the range is
+// empty); k_blk_zsum adds the splits in a fixed order.
+constexpr int kJSplit = 256;
 __global__ __launch_bounds__(kBlock) void k_blk_cross(const double* __restrict__ M, int64_t ldm,
                                                       const double* __restrict__ W, int64_t ldw,
                                                       const int32_t* __restrict__ pos,
-                                                      double* __restrict__ Z, int64_t ldz,
+                                                      double* __restrict__ Zp, int64_t ldz,
                                                       const DevScalars* sc) {
   __shared__ double Ms[kB][kB + 1];   // [j][c]
   __shared__ double Wsh[kB][kB + 1];  // [j][a]
@@ -428,15 +685,18 @@ __global__ __launch_bounds__(kBlock) void k_blk_cross(const double* __restrict__
   const int64_t k = sc->n_accept_total;
   const int na = sc->blk_na;
   const int64_t c0 = (int64_t)blockIdx.x * kB;
+  const int64_t js = blockIdx.y;
   if (c0 >= k || na == 0) return;
+  double* zp = Zp + js * kB * ldz;
+  const int64_t jlo = max(c0, js * kJSplit), jhi = min(k, (js + 1) * kJSplit);
   if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
   const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
   double acc[4][4] = {};
-  for (int64_t j0 = c0; j0 < k; j0 += kB) {
+  for (int64_t j0 = jlo; j0 < jhi; j0 += kB) {
     __syncthreads();
     for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
       const int a = t / kB, jj = t % kB;
-      const bool jin = j0 + jj < k;
+      const bool jin = j0 + jj < jhi;
       Ms[jj][a] = (jin && c0 + a < k) ? M[(c0 + a) * ldm + j0 + jj] : 0.0;
       Wsh[jj][a] = (jin && a < na) ? W[(int64_t)ps[a] * ldw + j0 + jj] : 0.0;
     }
@@ -462,8 +722,24 @@ __global__ __launch_bounds__(kBlock) void k_blk_cross(const double* __restrict__
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int a = tx * 4 + v;
-      if (a < na) Z[(int64_t)a * ldz + c] = acc[u][v];
+      if (a < na) zp[(int64_t)a * ldz + c] = acc[u][v];
     }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_blk_zsum(const double* __restrict__ Zp, int njs,
+                                                     double* __restrict__ Z, int64_t ldz,
+                                                     const DevScalars* sc) {
+  const int64_t k = sc->n_accept_total;
+  const int na = sc->blk_na;
+  const int64_t total = (int64_t)na * k;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t a = t / k, c = t % k;
+    const int js_hi = (int)min((int64_t)njs, (k + kJSplit - 1) / kJSplit);
+    double s = 0.0;
+    for (int js = (int)(c / kJSplit); js < js_hi; ++js) s += Zp[(int64_t)js * kB * ldz + a * ldz + c];
+    Z[a * ldz + c] = s;
   }
 }
 
@@ -554,8 +830,12 @@ __global__ __launch_bounds__(kBlock) void k_lev(const double* __restrict__ Q, in
 }  // namespace
 
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
+  const int64_t njs = (cap + kJSplit - 1) / kJSplit;
   return (size_t)kB * cap            // W
+         + (size_t)kSplitW * kB * cap + (size_t)kB * cap   // W2p, W2
+         + (size_t)njs * kB * cap    // Zp
          + (size_t)kSplit * kB * kB  // part
+         + (size_t)kSplitDD * kB * kB * 2 + (size_t)kB * kB  // part_hi/lo, G_lo
          + (size_t)kB * kB * 3       // G, Tcur, Tacc
          + kB                        // g
          + (size_t)kB * cap          // Z
@@ -564,18 +844,25 @@ size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
 }
 
 void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
+  const int njs = div_up(a.cap, kJSplit);
   double* W = a.scratch;
-  double* part = W + (size_t)kB * a.cap;
-  double* G = part + (size_t)kSplit * kB * kB;
+  double* W2p = W + (size_t)kB * a.cap;
+  double* W2 = W2p + (size_t)kSplitW * kB * a.cap;
+  double* Zp = W2 + (size_t)kB * a.cap;
+  double* part = Zp + (size_t)njs * kB * a.cap;
+  double* part_hi = part + (size_t)kSplit * kB * kB;
+  double* part_lo = part_hi + (size_t)kSplitDD * kB * kB;
+  double* Glo = part_lo + (size_t)kSplitDD * kB * kB;
+  double* G = Glo + kB * kB;
   double* Tcur = G + kB * kB;
   double* Tacc = Tcur + kB * kB;
   double* g = Tacc + kB * kB;
   double* Z = g + kB;
   double* Ybuf = Z + (size_t)kB * a.cap;
   int32_t* pos = (int32_t*)(Ybuf + (size_t)kB * a.n_rows);
-  const int nchunk = div_up(a.cap, 2 * kWave);
+  const int nchunk = div_up(a.cap, kWave);
   const int rows_tiles32 = div_up(a.n_rows, 32);
-  const int rows4 = div_up(a.n_rows * 4, kBlock);
+  const int rows4 = div_up(a.n_rows, kB);
   const int cross_tiles = div_up(a.cap, kB);
   const int ext_grid = std::max(1, std::min(4096, div_up((a.cap + kB) * kB, 256)));
   hipLaunchKernelGGL(k_begin_basis, dim3(1), dim3(1), 0, st, sc);
@@ -585,13 +872,20 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
     hipLaunchKernelGGL(k_blk_w, dim3(div_up((int64_t)kB * nchunk * kWave, kBlock)), dim3(kBlock), 0,
                        st, a.Q, a.ldq, a.uniq_fi, a.fptr, a.row, a.val, b0, W, a.cap, nchunk, sc);
     hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kBlock), 0, st, a.P, a.ldp, a.n_rows,
-                       a.Q, a.ldq, W, a.cap, b0, Ybuf, sc);
-    hipLaunchKernelGGL(k_blk_gram_part, dim3(kSplit), dim3(kBlock), 0, st, Ybuf, (int64_t)kB,
-                       a.n_rows, 0, b0, part, sc);
-    hipLaunchKernelGGL(k_blk_sum_parts, dim3(kB * kB / kBlock), dim3(kBlock), 0, st, part, G, 0, b0,
-                       sc);
-    hipLaunchKernelGGL(k_blk_decide, dim3(1), dim3(kWave), 0, st, G, g, a.eps2, b0, a.n_rows, pos,
-                       a.accept, Tacc, sc);
+                       a.Q, a.ldq, W, a.cap, b0, Ybuf, false, sc);
+    // second projection against Q (block classical Gram-Schmidt, twice)
+    hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(a.cap, kB), kSplitW), dim3(kBlock), 0, st, a.Q,
+                       a.ldq, a.n_rows, Ybuf, W2p, a.cap, b0, sc);
+    hipLaunchKernelGGL(k_blk_w2_sum, dim3(std::max(1, std::min(1024, div_up((int64_t)kB * a.cap, kBlock)))),
+                       dim3(kBlock), 0, st, W2p, W2, W, a.cap, b0, sc);
+    hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kBlock), 0, st, a.P, a.ldp, a.n_rows,
+                       a.Q, a.ldq, W2, a.cap, b0, Ybuf, true, sc);
+    hipLaunchKernelGGL(k_blk_gram_dd, dim3(kSplitDD), dim3(kBlock), 0, st, Ybuf, a.n_rows, b0,
+                       part_hi, part_lo, sc);
+    hipLaunchKernelGGL(k_blk_sum_dd, dim3(kB * kB / kBlock), dim3(kBlock), 0, st, part_hi, part_lo,
+                       G, Glo, b0, sc);
+    hipLaunchKernelGGL(k_blk_decide, dim3(1), dim3(kWave), 0, st, G, Glo, g, a.eps2, b0, a.n_rows,
+                       pos, a.accept, Tacc, sc);
     hipLaunchKernelGGL(k_blk_take, dim3(rows4), dim3(kBlock), 0, st, Ybuf, a.P, a.ldp, a.n_rows,
                        pos, Tacc, b0, a.Q, a.ldq, a.R, a.ldr, sc);
     hipLaunchKernelGGL(k_blk_gram_part, dim3(kSplit), dim3(kBlock), 0, st, a.Q, a.ldq, a.n_rows,
@@ -601,8 +895,10 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
     hipLaunchKernelGGL(k_blk_cholinv, dim3(1), dim3(kWave), 0, st, G, Tcur, Tacc, sc);
     hipLaunchKernelGGL(k_blk_apply, dim3(rows4), dim3(kBlock), 0, st, a.Q, a.ldq, a.n_rows, Tcur,
                        sc);
-    hipLaunchKernelGGL(k_blk_cross, dim3(cross_tiles), dim3(kBlock), 0, st, a.M, a.ldm, W, a.cap,
-                       pos, Z, a.cap, sc);
+    hipLaunchKernelGGL(k_blk_cross, dim3(cross_tiles, njs), dim3(kBlock), 0, st, a.M, a.ldm, W,
+                       a.cap, pos, Zp, a.cap, sc);
+    hipLaunchKernelGGL(k_blk_zsum, dim3(std::max(1, std::min(1024, div_up((int64_t)kB * a.cap, kBlock)))),
+                       dim3(kBlock), 0, st, Zp, njs, Z, a.cap, sc);
     hipLaunchKernelGGL(k_blk_extend_m, dim3(ext_grid), dim3(256), 0, st, a.M, a.ldm, Z, a.cap, Tacc,
                        sc);
     hipLaunchKernelGGL(k_blk_finish, dim3(1), dim3(256), 0, st, pos, b0, a.uniq_fi, a.uniq_fid,
