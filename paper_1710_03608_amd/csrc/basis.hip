@@ -403,112 +403,98 @@ __global__ __launch_bounds__(kBlock) void k_blk_sum_parts(const double* __restri
   G[t] = s;
 }
 
-// Broadcast a double from a compile-time lane (two v_readlane_b32).
-__device__ inline double bcast(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
+// The 64 x 64 factorizations run in one workgroup of kChol threads with the
+// matrix in LDS: a right-looking Cholesky (step j scales column j, then every
+// thread updates its share of the trailing triangle) and a forward sweep for
+// L^{-1}.  Loops stay rolled so that the code fits the instruction cache.
+constexpr int kChol = 1024;
+typedef double LdsMat[kB][kB + 1];
 
-// One wave factors a 64 x 64 symmetric matrix held one row per lane
-// (row[c] = G[i][c], c <= i): a right-looking Cholesky in candidate order.
-// Step j broadcasts the pivot, keeps or drops candidate j, scales column j and
-// updates the trailing rows; elements of column j travel by readlane.  Fully
-// unrolled so that every row element stays in a register.  With drop == false
-// every pivot is kept.  Returns the kept mask; dropped rows/columns come out
-// as identity rows, so the inverse of the result restricted to the kept set is
-// the inverse of the kept factor.
-__device__ inline uint64_t wave_chol(double (&row)[kB], bool drop, double eps2, double gi, int n,
-                                     int64_t room) {
-  const int i = threadIdx.x;
-  uint64_t kept_mask = 0;
+// Cholesky of the leading n x n block of A (lower triangle, rows hold
+// A[i][c] for c <= i; double-double when Al != nullptr), in candidate order.
+// With drop set, candidate j is kept iff its pivot exceeds eps2 * gs[j] and
+// fewer than `room` are kept so far; a dropped column is zeroed from row j
+// down.  Rows of dropped candidates (and rows >= n) end as identity rows, so
+// the inverse restricted to the kept set is the inverse of the kept factor.
+// Returns the kept mask (identical in every thread).
+template <bool kDD>
+__device__ uint64_t wg_chol(LdsMat& Ah, LdsMat* Al, double* ch, double* cl, const double* gs,
+                            int n, bool drop, double eps2, int64_t room) {
+  const int tid = threadIdx.x;
+  uint64_t mask = 0;
   int kept = 0;
-#pragma unroll
-  for (int j = 0; j < kB; ++j) {
-    const double d = bcast(row[j], j);
-    const double gj = bcast(gi, j);
-    const bool keep = j < n && (drop ? (d > eps2 * gj && kept < room) : true);
+  for (int j = 0; j < n; ++j) {
+    const double dh = Ah[j][j];
+    const double dl = kDD ? (*Al)[j][j] : 0.0;
+    const bool keep = !drop || (((dh - eps2 * gs[j]) + dl > 0.0) && kept < room);
     if (keep) {
-      const double l = sqrt(fmax(d, 1e-300));
-      const double rl = 1.0 / l;
-      if (i == j) row[j] = l;
-      if (i > j) row[j] *= rl;
-#pragma unroll
-      for (int c = j + 1; c < kB; ++c) {
-        const double lcj = bcast(row[j], c);
-        if (i >= c) row[c] -= row[j] * lcj;
+      if (tid >= j && tid < n) {
+        double vh, vl = 0.0;
+        if (kDD) {
+          double lh, ll;
+          dd_sqrt(dh, dl, lh, ll);
+          vh = lh;
+          vl = ll;
+          if (tid > j) dd_div(Ah[tid][j], (*Al)[tid][j], lh, ll, vh, vl);
+          (*Al)[tid][j] = vl;
+        } else {
+          const double l = sqrt(fmax(dh, 1e-300));
+          vh = tid == j ? l : Ah[tid][j] / l;
+        }
+        Ah[tid][j] = vh;
+        ch[tid] = vh;
+        cl[tid] = vl;
+      }
+      __syncthreads();
+      const int m = n - j - 1;
+      for (int e = tid; e < m * m; e += kChol) {
+        const int i = j + 1 + e / m, c = j + 1 + e % m;
+        if (c > i) continue;
+        if (kDD)
+          dd_fnma(Ah[i][c], (*Al)[i][c], ch[i], cl[i], ch[c], cl[c]);
+        else
+          Ah[i][c] -= ch[i] * ch[c];
       }
       ++kept;
-      kept_mask |= 1ull << j;
-    } else if (i >= j) {
-      row[j] = 0.0;
+      mask |= 1ull << j;
+    } else if (tid >= j && tid < n) {
+      Ah[tid][j] = 0.0;
+      if (kDD) (*Al)[tid][j] = 0.0;
     }
+    __syncthreads();
   }
-  if (!((kept_mask >> i) & 1ull)) {
-#pragma unroll
-    for (int c = 0; c < kB; ++c) row[c] = (c == i) ? 1.0 : 0.0;
+  for (int e = tid; e < kB * kB; e += kChol) {
+    const int i = e / kB, c = e % kB;
+    if (!((mask >> i) & 1ull)) Ah[i][c] = (c == i) ? 1.0 : 0.0;
   }
-  return kept_mask;
+  __syncthreads();
+  return mask;
 }
 
-// Lane c computes column c of L^{-1} (L held one row per lane in `row`) by
-// forward substitution: x[r] = L^{-1}[r][c].
-__device__ inline void wave_tri_inv_col(const double (&row)[kB], double (&x)[kB]) {
-  const int c = threadIdx.x;
-#pragma unroll
-  for (int r = 0; r < kB; ++r) {
-    double s = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-    for (int j = 0; j < r; ++j) s -= bcast(row[j], r) * x[j];
-    x[r] = s / bcast(row[r], r);
-  }
-}
-
-// The drop decisions of wave_chol in double-double: rows (rh, rl) held one
-// per lane.  Returns the kept mask; rh comes out as the float64 factor with
-// identity rows for dropped candidates (as wave_chol).
-__device__ inline uint64_t wave_chol_dd(double (&rh)[kB], double (&rl)[kB], double eps2, double gi,
-                                        int n, int64_t room) {
-  const int i = threadIdx.x;
-  uint64_t kept_mask = 0;
-  int kept = 0;
-#pragma unroll
-  for (int j = 0; j < kB; ++j) {
-    const double dh = bcast(rh[j], j), dl = bcast(rl[j], j);
-    const double gj = bcast(gi, j);
-    const bool keep = j < n && ((dh - eps2 * gj) + dl > 0.0) && kept < room;
-    if (keep) {
-      double lh, ll;
-      dd_sqrt(dh, dl, lh, ll);
-      if (i == j) {
-        rh[j] = lh;
-        rl[j] = ll;
-      }
-      if (i > j) dd_div(rh[j], rl[j], lh, ll, rh[j], rl[j]);
-#pragma unroll
-      for (int c = j + 1; c < kB; ++c) {
-        const double ch = bcast(rh[j], c), cl = bcast(rl[j], c);
-        if (i >= c) dd_fnma(rh[c], rl[c], rh[j], rl[j], ch, cl);
-      }
-      ++kept;
-      kept_mask |= 1ull << j;
-    } else if (i >= j) {
-      rh[j] = 0.0;
-      rl[j] = 0.0;
+// X = L^{-1} for the lower-triangular L in Ah whose rows >= n are identity
+// rows (forward sweep: row j is final once divided by L[j][j]; it is then
+// eliminated from the rows below).
+__device__ void wg_tri_inv(const LdsMat& L, LdsMat& X, int n) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kB * kB; e += kChol) X[e / kB][e % kB] = (e / kB == e % kB) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid <= j) X[j][tid] /= L[j][j];
+    __syncthreads();
+    const int w = j + 1, m = n - j - 1;
+    for (int e = tid; e < m * w; e += kChol) {
+      const int r = j + 1 + e / w, c = e % w;
+      X[r][c] -= L[r][j] * X[j][c];
     }
+    __syncthreads();
   }
-  if (!((kept_mask >> i) & 1ull)) {
-#pragma unroll
-    for (int c = 0; c < kB; ++c) rh[c] = (c == i) ? 1.0 : 0.0;
-  }
-  return kept_mask;
 }
 
-// One wave: the block's residual Gram G; Cholesky with column drop in
+// The block's residual Gram G (double-double): Cholesky with column drop in
 // candidate order (pivot vs eps^2 ||x||^2); kept positions compacted into
 // pos[0..na), na into sc->blk_na; Tacc = L_A^{-T} over the kept rows/columns
 // (first Cholesky-QR pass of the kept residuals).
-__global__ __launch_bounds__(kWave) void k_blk_decide(const double* __restrict__ G,
+__global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__ G,
                                                       const double* __restrict__ Glo,
                                                       const double* __restrict__ g, double eps2,
                                                       int64_t b0, int64_t n_rows,
@@ -516,75 +502,72 @@ __global__ __launch_bounds__(kWave) void k_blk_decide(const double* __restrict__
                                                       int32_t* __restrict__ accept_all,
                                                       double* __restrict__ Tacc,
                                                       DevScalars* sc) {
-  __shared__ double Xs[kB][kB + 1];
+  __shared__ LdsMat Ah, Al, X;
+  __shared__ double ch[kB], cl[kB], gs[kB];
   __shared__ int32_t ps[kB];
   const int64_t nb = blk_count(sc, b0);
-  const int i = threadIdx.x;
+  const int tid = threadIdx.x;
   if (nb == 0) {
-    if (i == 0) sc->blk_na = 0;
+    if (tid == 0) sc->blk_na = 0;
     return;
   }
   const int64_t room = n_rows - (int64_t)sc->n_accept_total;   // at most n_rows independent fibers
-  double row[kB], rlo[kB];
-#pragma unroll
-  for (int c = 0; c < kB; ++c) {
-    row[c] = (i < nb && c <= i) ? G[i * kB + c] : 0.0;
-    rlo[c] = (i < nb && c <= i) ? Glo[i * kB + c] : 0.0;
+  for (int e = tid; e < kB * kB; e += kChol) {
+    const int i = e / kB, c = e % kB;
+    const bool in = i < nb && c <= i;
+    Ah[i][c] = in ? G[e] : 0.0;
+    Al[i][c] = in ? Glo[e] : 0.0;
   }
-  const double gi = i < nb ? g[i] : 0.0;
-  const uint64_t m = wave_chol_dd(row, rlo, eps2, gi, (int)nb, room);
-  const bool my_keep = (m >> i) & 1ull;
-  const int na = (int)__popcll(m);
-  if (my_keep) {
-    const uint64_t lt = i == 0 ? 0ull : ((~0ull) >> (kWave - i));
-    const int slot = (int)__popcll(m & lt);
-    pos[slot] = i;
-    ps[slot] = i;
-  }
-  if (i < nb && accept_all) accept_all[b0 + i] = my_keep ? 1 : 0;
-  if (i == 0) sc->blk_na = na;
-  double x[kB];
-  wave_tri_inv_col(row, x);      // x[r] = L^{-1}[r][i]
-#pragma unroll
-  for (int r = 0; r < kB; ++r) Xs[r][i] = x[r];
+  if (tid < kB) gs[tid] = tid < nb ? g[tid] : 0.0;
   __syncthreads();
+  const uint64_t m = wg_chol<true>(Ah, &Al, ch, cl, gs, (int)nb, true, eps2, room);
+  const int na = (int)__popcll(m);
+  if (tid < kB) {
+    const bool my_keep = (m >> tid) & 1ull;
+    if (my_keep) {
+      const uint64_t lt = tid == 0 ? 0ull : ((~0ull) >> (kWave - tid));
+      const int slot = (int)__popcll(m & lt);
+      pos[slot] = tid;
+      ps[slot] = tid;
+    }
+    if (tid < nb && accept_all) accept_all[b0 + tid] = my_keep ? 1 : 0;
+  }
+  if (tid == 0) sc->blk_na = na;
+  wg_tri_inv(Ah, X, (int)nb);
   // Tacc[a][b] = L_A^{-1}[b][a] = L^{-1}[ps[b]][ps[a]]
-  const int pa = i < na ? ps[i] : 0;
-  for (int bb = 0; bb < kB; ++bb)
-    Tacc[i * kB + bb] = (i < na && bb < na) ? Xs[ps[bb]][pa] : 0.0;
+  for (int e = tid; e < kB * kB; e += kChol) {
+    const int a = e / kB, bb = e % kB;
+    Tacc[e] = (a < na && bb < na) ? X[ps[bb]][ps[a]] : 0.0;
+  }
 }
 
-// One wave: Cholesky (no drop) of the kept block's Gram after its first pass,
-// Tcur = L^{-T}, Tacc <- Tacc Tcur.
-__global__ __launch_bounds__(kWave) void k_blk_cholinv(const double* __restrict__ G,
+// Cholesky (no drop) of the kept block's Gram after its first pass,
+// Tcur = L^{-T}, Tacc <- Tacc Tcur (both upper triangular).
+__global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict__ G,
                                                        double* __restrict__ Tcur,
                                                        double* __restrict__ Tacc,
                                                        const DevScalars* sc) {
+  __shared__ LdsMat L, X, Ta;
+  __shared__ double ch[kB], cl[kB];
   const int na = sc->blk_na;
-  const int i = threadIdx.x;
+  const int tid = threadIdx.x;
   if (na == 0) return;
-  double row[kB];
-#pragma unroll
-  for (int c = 0; c < kB; ++c) row[c] = (i < na && c <= i) ? G[i * kB + c] : 0.0;
-  wave_chol(row, false, 0.0, 0.0, na, kB);
-  double x[kB];
-  wave_tri_inv_col(row, x);      // x[r] = L^{-1}[r][i] = Tcur[i][r]
-  const bool live = i < na;
-#pragma unroll
-  for (int r = 0; r < kB; ++r) Tcur[i * kB + r] = (live && r < na) ? x[r] : 0.0;
-  // Tacc <- Tacc Tcur: row i of the product; Tcur[a][b] = x[b] of lane a
-#pragma unroll
-  for (int c = 0; c < kB; ++c) row[c] = Tacc[i * kB + c];
-  double out[kB];
-#pragma unroll
-  for (int bcol = 0; bcol < kB; ++bcol) out[bcol] = 0.0;
-#pragma unroll
-  for (int a = 0; a < kB; ++a) {
-#pragma unroll
-    for (int bcol = a; bcol < kB; ++bcol) out[bcol] += row[a] * bcast(x[bcol], a);
+  for (int e = tid; e < kB * kB; e += kChol) {
+    const int i = e / kB, c = e % kB;
+    L[i][c] = (i < na && c <= i) ? G[e] : 0.0;
+    Ta[i][c] = Tacc[e];
   }
-#pragma unroll
-  for (int bcol = 0; bcol < kB; ++bcol) Tacc[i * kB + bcol] = (live && bcol < na) ? out[bcol] : 0.0;
+  __syncthreads();
+  wg_chol<false>(L, nullptr, ch, cl, nullptr, na, false, 0.0, kB);
+  wg_tri_inv(L, X, na);
+  for (int e = tid; e < kB * kB; e += kChol) {
+    const int i = e / kB, bcol = e % kB;
+    const bool live = i < na && bcol < na;
+    Tcur[e] = live ? X[bcol][i] : 0.0;
+    double acc = 0.0;
+    for (int c = i; c <= bcol; ++c) acc += Ta[i][c] * X[bcol][c];   // Tacc upper, Tcur[c][bcol] = X[bcol][c]
+    Tacc[e] = live ? acc : 0.0;
+  }
 }
 
 // Kept residuals times the first-pass factor: Q[r][k + a] = sum_{a' <= a}
@@ -884,7 +867,7 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
                        part_hi, part_lo, sc);
     hipLaunchKernelGGL(k_blk_sum_dd, dim3(kB * kB / kBlock), dim3(kBlock), 0, st, part_hi, part_lo,
                        G, Glo, b0, sc);
-    hipLaunchKernelGGL(k_blk_decide, dim3(1), dim3(kWave), 0, st, G, Glo, g, a.eps2, b0, a.n_rows,
+    hipLaunchKernelGGL(k_blk_decide, dim3(1), dim3(kChol), 0, st, G, Glo, g, a.eps2, b0, a.n_rows,
                        pos, a.accept, Tacc, sc);
     hipLaunchKernelGGL(k_blk_take, dim3(rows4), dim3(kBlock), 0, st, Ybuf, a.P, a.ldp, a.n_rows,
                        pos, Tacc, b0, a.Q, a.ldq, a.R, a.ldr, sc);
@@ -892,7 +875,7 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
                        1, b0, part, sc);
     hipLaunchKernelGGL(k_blk_sum_parts, dim3(kB * kB / kBlock), dim3(kBlock), 0, st, part, G, 1, b0,
                        sc);
-    hipLaunchKernelGGL(k_blk_cholinv, dim3(1), dim3(kWave), 0, st, G, Tcur, Tacc, sc);
+    hipLaunchKernelGGL(k_blk_cholinv, dim3(1), dim3(kChol), 0, st, G, Tcur, Tacc, sc);
     hipLaunchKernelGGL(k_blk_apply, dim3(rows4), dim3(kBlock), 0, st, a.Q, a.ldq, a.n_rows, Tcur,
                        sc);
     hipLaunchKernelGGL(k_blk_cross, dim3(cross_tiles, njs), dim3(kBlock), 0, st, a.M, a.ldm, W,
