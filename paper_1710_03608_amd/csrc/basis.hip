@@ -147,110 +147,178 @@ __global__ __launch_bounds__(kBlock) void k_blk_w(const double* __restrict__ Q, 
   if (active) W[(int64_t)j * ldw + c] = acc;
 }
 
+// Dense f64 MFMA kernels below run 512 threads as two groups of four waves
+// that split the reduction dimension between them (chunks alternate), with
+// the next chunk's global loads in registers while the current one is in
+// MFMAs; the two partial tiles are combined through LDS at the end.
+constexpr int kGemm = 512;
+constexpr int kGK = 32;       // reduction chunk
+
 // Y[r][j] = P[r][b0 + j] - sum_{c<k} Q[r][c] W[j][c] for every candidate j of
 // the block (residuals against span(Q)), into Ybuf (n_rows x 64).  One
-// workgroup per 32 rows; wave w computes rows 16 (w / 2) .. + 16 and
-// candidates 32 (w % 2) .. + 32 with two f64 MFMA accumulators.
+// workgroup per 32 rows; wave w of a group computes rows 16 (w / 2) .. + 16
+// and candidates 32 (w % 2) .. + 32 with two f64 MFMA accumulators.
 // With reproject set, the base is Ybuf itself (second projection pass):
 // Ybuf[r][j] -= sum_c Q[r][c] W2[j][c].
-__global__ __launch_bounds__(kBlock) void k_blk_form_y(const double* __restrict__ P, int64_t ldp,
-                                                       int64_t n_rows, const double* __restrict__ Q,
-                                                       int64_t ldq, const double* __restrict__ W,
-                                                       int64_t ldw, int64_t b0,
-                                                       double* __restrict__ Ybuf, bool reproject,
-                                                       const DevScalars* sc) {
+__global__ __launch_bounds__(kGemm) void k_blk_form_y(const double* __restrict__ P, int64_t ldp,
+                                                      int64_t n_rows, const double* __restrict__ Q,
+                                                      int64_t ldq, const double* __restrict__ W,
+                                                      int64_t ldw, int64_t b0,
+                                                      double* __restrict__ Ybuf, bool reproject,
+                                                      const DevScalars* sc) {
   constexpr int kR = 32;
-  constexpr int kK = 32;
-  __shared__ double As[kR][kK + 1];   // Q tile [row][c]
-  __shared__ double Bs[kK][kB + 1];   // W^T tile [c][j]
+  __shared__ double As[2][kR][kGK + 1];   // Q tile [row][c]
+  __shared__ double Bs[2][kGK][kB + 1];   // W^T tile [c][j]
   const int64_t nb = blk_count(sc, b0);
   if (nb == 0) return;
   const int64_t k = sc->n_accept_total;
   if (reproject && k == 0) return;
   const int64_t r0 = (int64_t)blockIdx.x * kR;
-  const int w = threadIdx.x / kWave, l = lane_id();
+  const int grp = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
+  const int w = t / kWave, l = lane_id();
   const int rb = (w / 2) * 16, cb = (w % 2) * 32;
+  const int64_t nch = (k + kGK - 1) / kGK;
+  const int64_t iters = (nch + 1) / 2;
+  double ra[kR * kGK / kBlock], rw[kB * kGK / kBlock];
+  auto load = [&](int64_t ch) {
+    const int64_t c0 = ch * kGK;
+#pragma unroll
+    for (int u = 0; u < kR * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t, r = idx / kGK, c = idx % kGK;
+      ra[u] = (ch < nch && c0 + c < k && r0 + r < n_rows) ? Q[(r0 + r) * ldq + c0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kB * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t, j = idx / kGK, c = idx % kGK;
+      rw[u] = (ch < nch && c0 + c < k && j < nb) ? W[(int64_t)j * ldw + c0 + c] : 0.0;
+    }
+  };
   dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  for (int64_t c0 = 0; c0 < k; c0 += kK) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < kR * kK; t += kBlock) {
-      const int r = t / kK, c = t % kK;
-      As[r][c] = (c0 + c < k && r0 + r < n_rows) ? Q[(r0 + r) * ldq + c0 + c] : 0.0;
-    }
-    for (int t = threadIdx.x; t < kK * kB; t += kBlock) {
-      const int j = t / kK, c = t % kK;
-      Bs[c][j] = (c0 + c < k && j < nb) ? W[(int64_t)j * ldw + c0 + c] : 0.0;
-    }
+  load(grp);
+  for (int64_t it = 0; it < iters; ++it) {
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < kK / 4; ++ks) {
-      const double a = As[rb + l % 16][ks * 4 + l / 16];
-      const double b0v = Bs[ks * 4 + l / 16][cb + l % 16];
-      const double b1v = Bs[ks * 4 + l / 16][cb + 16 + l % 16];
+    for (int u = 0; u < kR * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t;
+      As[grp][idx / kGK][idx % kGK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kB * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t;
+      Bs[grp][idx % kGK][idx / kGK] = rw[u];
+    }
+    __syncthreads();
+    load(grp + 2 * (it + 1));
+#pragma unroll
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const double a = As[grp][rb + l % 16][ks * 4 + l / 16];
+      const double b0v = Bs[grp][ks * 4 + l / 16][cb + l % 16];
+      const double b1v = Bs[grp][ks * 4 + l / 16][cb + 16 + l % 16];
       acc0 = mfma16(a, b0v, acc0);
       acc1 = mfma16(a, b1v, acc1);
     }
   }
+  // combine the two groups: group 1 parks its tile in LDS
+  double(*red)[kB + 1] = Bs[0];   // 32 x 65 doubles
+  __syncthreads();
+  if (grp == 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      red[rb + l / 16 + 4 * r][cb + l % 16] = acc0[r];
+      red[rb + l / 16 + 4 * r][cb + 16 + l % 16] = acc1[r];
+    }
+  }
+  __syncthreads();
+  if (grp == 1) return;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int64_t row = r0 + rb + l / 16 + 4 * r;
+    const int rr = rb + l / 16 + 4 * r;
+    const int64_t row = r0 + rr;
     if (row >= n_rows) continue;
     const int j0 = cb + l % 16, j1 = cb + 16 + l % 16;
+    const double s0 = acc0[r] + red[rr][j0], s1 = acc1[r] + red[rr][j1];
     if (reproject) {
-      if (j0 < nb) Ybuf[row * kB + j0] -= acc0[r];
-      if (j1 < nb) Ybuf[row * kB + j1] -= acc1[r];
+      if (j0 < nb) Ybuf[row * kB + j0] -= s0;
+      if (j1 < nb) Ybuf[row * kB + j1] -= s1;
     } else {
-      Ybuf[row * kB + j0] = j0 < nb ? P[row * ldp + b0 + j0] - acc0[r] : 0.0;
-      Ybuf[row * kB + j1] = j1 < nb ? P[row * ldp + b0 + j1] - acc1[r] : 0.0;
+      Ybuf[row * kB + j0] = j0 < nb ? P[row * ldp + b0 + j0] - s0 : 0.0;
+      Ybuf[row * kB + j1] = j1 < nb ? P[row * ldp + b0 + j1] - s1 : 0.0;
     }
   }
 }
 
 // Second projection coefficients W2[j][c] = sum_r Q[r][c] Y[r][j] for c < k,
 // partial over kSplitW row ranges: workgroup (ct, s) covers c in
-// [64 ct, 64 ct + 64); wave w computes c rows 16 w .. + 16 against all 64 j
-// with four f64 MFMA tiles.
+// [64 ct, 64 ct + 64); wave w of a group computes c rows 16 w .. + 16 against
+// all 64 j with four f64 MFMA tiles.
 constexpr int kSplitW = 16;
-__global__ __launch_bounds__(kBlock) void k_blk_w2_part(const double* __restrict__ Q, int64_t ldq,
-                                                        int64_t n_rows,
-                                                        const double* __restrict__ Y,
-                                                        double* __restrict__ W2p, int64_t ldw,
-                                                        int64_t b0, const DevScalars* sc) {
-  constexpr int kK = 32;
-  __shared__ double Qs[kK][kB + 1];   // [r][c]
-  __shared__ double Ys[kK][kB + 1];   // [r][j]
+__global__ __launch_bounds__(kGemm) void k_blk_w2_part(const double* __restrict__ Q, int64_t ldq,
+                                                       int64_t n_rows,
+                                                       const double* __restrict__ Y,
+                                                       double* __restrict__ W2p, int64_t ldw,
+                                                       int64_t b0, const DevScalars* sc) {
+  __shared__ double Qs[2][kGK][kB + 1];   // [r][c]
+  __shared__ double Ys[2][kGK][kB + 1];   // [r][j]
   const int64_t nb = blk_count(sc, b0);
   const int64_t k = sc->n_accept_total;
   const int64_t c0 = (int64_t)blockIdx.x * kB;
   if (nb == 0 || c0 >= k) return;
   const int64_t chunk = (n_rows + kSplitW - 1) / kSplitW;
   const int64_t r0 = blockIdx.y * chunk, r1 = min(n_rows, r0 + chunk);
-  const int w = threadIdx.x / kWave, l = lane_id();
+  const int grp = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
+  const int w = t / kWave, l = lane_id();
+  const int64_t nch = (r1 - r0 + kGK - 1) / kGK;
+  const int64_t iters = (nch + 1) / 2;
+  double rq[kGK * kB / kBlock], ry[kGK * kB / kBlock];
+  auto load = [&](int64_t ch) {
+    const int64_t rr = r0 + ch * kGK;
+#pragma unroll
+    for (int u = 0; u < kGK * kB / kBlock; ++u) {
+      const int idx = u * kBlock + t, r = idx / kB, c = idx % kB;
+      const bool rin = ch < nch && rr + r < r1;
+      rq[u] = (rin && c0 + c < k) ? Q[(rr + r) * ldq + c0 + c] : 0.0;
+      ry[u] = (rin && c < nb) ? Y[(rr + r) * kB + c] : 0.0;
+    }
+  };
   dbl4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int64_t rr = r0; rr < r1; rr += kK) {
+  load(grp);
+  for (int64_t it = 0; it < iters; ++it) {
     __syncthreads();
-    for (int t = threadIdx.x; t < kK * kB; t += kBlock) {
-      const int r = t / kB, c = t % kB;
-      const bool rin = rr + r < r1;
-      Qs[r][c] = (rin && c0 + c < k) ? Q[(rr + r) * ldq + c0 + c] : 0.0;
-      Ys[r][c] = (rin && c < nb) ? Y[(rr + r) * kB + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kGK * kB / kBlock; ++u) {
+      const int idx = u * kBlock + t;
+      Qs[grp][idx / kB][idx % kB] = rq[u];
+      Ys[grp][idx / kB][idx % kB] = ry[u];
     }
     __syncthreads();
+    load(grp + 2 * (it + 1));
 #pragma unroll
-    for (int ks = 0; ks < kK / 4; ++ks) {
-      const double a = Qs[ks * 4 + l / 16][w * 16 + l % 16];   // A = Q^T: A[c][r] = Q[r][c]
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const double a = Qs[grp][ks * 4 + l / 16][w * 16 + l % 16];   // A = Q^T: A[c][r] = Q[r][c]
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = mfma16(a, Ys[ks * 4 + l / 16][q * 16 + l % 16], acc[q]);
+      for (int q = 0; q < 4; ++q)
+        acc[q] = mfma16(a, Ys[grp][ks * 4 + l / 16][q * 16 + l % 16], acc[q]);
     }
   }
+  double(*red)[kB + 1] = Qs[0];   // reuse Qs (2 x 32 x 65 doubles) as a 64 x 65 tile
+  __syncthreads();
+  if (grp == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[w * 16 + l / 16 + 4 * r][q * 16 + l % 16] = acc[q][r];
+  }
+  __syncthreads();
+  if (grp == 1) return;
   double* p = W2p + (int64_t)blockIdx.y * kB * ldw;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t c = c0 + w * 16 + l / 16 + 4 * r;
+      const int cc = w * 16 + l / 16 + 4 * r;
+      const int64_t c = c0 + cc;
       const int j = q * 16 + l % 16;
-      if (c < k) p[(int64_t)j * ldw + c] = acc[q][r];
+      if (c < k) p[(int64_t)j * ldw + c] = acc[q][r] + red[cc][j];
     }
 }
 
@@ -408,86 +476,127 @@ __global__ __launch_bounds__(kBlock) void k_blk_sum_parts(const double* __restri
 // thread updates its share of the trailing triangle) and a forward sweep for
 // L^{-1}.  Loops stay rolled so that the code fits the instruction cache.
 constexpr int kChol = 1024;
+constexpr int kRowsPer = kChol / kB;   // rows per thread slot group
+constexpr int kSlots = kB / kRowsPer;   // elements held per thread
 typedef double LdsMat[kB][kB + 1];
 
-// Cholesky of the leading n x n block of A (lower triangle, rows hold
-// A[i][c] for c <= i; double-double when Al != nullptr), in candidate order.
+// (ah, al) *= (bh, bl)
+__device__ inline void dd_mul(double& ah, double& al, double bh, double bl) {
+#pragma clang fp contract(off)
+  double p, pe;
+  two_prod(ah, bh, p, pe);
+  pe = fma(ah, bl, pe);
+  pe = fma(al, bh, pe);
+  quick_two_sum(p, pe, ah, al);
+}
+
+// Cholesky of the leading n x n block of A (lower triangle, A[i][c] for
+// c <= i, zeros above; double-double when Al != nullptr) in candidate order,
+// producing X = L^{-1} in place of A.  Thread t holds column t % 64 of rows
+// t / 64 + 16 q (q < 4) in registers.  Step j (right-looking): the pivot and
+// the scaled column j of L are broadcast through LDS together with row j of
+// X (scaled by 1 / L[j][j]); entries right of column j take the Schur update
+// A[i][c] -= L[i][j] L[c][j], entries at or left of it take the elimination
+// X[i][c] -= L[i][j] X[j][c].  Entry (i, j) turns from A into X at step j.
 // With drop set, candidate j is kept iff its pivot exceeds eps2 * gs[j] and
-// fewer than `room` are kept so far; a dropped column is zeroed from row j
-// down.  Rows of dropped candidates (and rows >= n) end as identity rows, so
-// the inverse restricted to the kept set is the inverse of the kept factor.
-// Returns the kept mask (identical in every thread).
+// fewer than `room` are kept so far; a dropped candidate gets an identity row
+// and a zero column in X, so X restricted to the kept set is the inverse of
+// the kept factor.  X goes to LDS; returns the kept mask (same in every
+// thread).
 template <bool kDD>
-__device__ uint64_t wg_chol(LdsMat& Ah, LdsMat* Al, double* ch, double* cl, const double* gs,
-                            int n, bool drop, double eps2, int64_t room) {
-  const int tid = threadIdx.x;
+__device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, double* ch,
+                                double* cl, double* xrow, double* piv, const double* gs, int n,
+                                bool drop, double eps2, int64_t room) {
+  const int tid = threadIdx.x, c = tid % kB, i0 = tid / kB;
+  double ah[kSlots], al[kSlots];
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) {
+    ah[q] = Ah[i0 + kRowsPer * q][c];
+    al[q] = kDD ? (*Al)[i0 + kRowsPer * q][c] : 0.0;
+  }
+  if (tid == 0) {
+    piv[0] = ah[0];
+    piv[1] = al[0];
+  }
+  __syncthreads();
   uint64_t mask = 0;
   int kept = 0;
   for (int j = 0; j < n; ++j) {
-    const double dh = Ah[j][j];
-    const double dl = kDD ? (*Al)[j][j] : 0.0;
+    const double dh = piv[0], dl = piv[1];
     const bool keep = !drop || (((dh - eps2 * gs[j]) + dl > 0.0) && kept < room);
     if (keep) {
-      if (tid >= j && tid < n) {
-        double vh, vl = 0.0;
-        if (kDD) {
-          double lh, ll;
-          dd_sqrt(dh, dl, lh, ll);
-          vh = lh;
-          vl = ll;
-          if (tid > j) dd_div(Ah[tid][j], (*Al)[tid][j], lh, ll, vh, vl);
-          (*Al)[tid][j] = vl;
-        } else {
-          const double l = sqrt(fmax(dh, 1e-300));
-          vh = tid == j ? l : Ah[tid][j] / l;
+      double lh, ll, rh, rl;
+      if (kDD) {
+        dd_sqrt(dh, dl, lh, ll);
+        dd_div(1.0, 0.0, lh, ll, rh, rl);
+      } else {
+        lh = sqrt(fmax(dh, 1e-300));
+        rh = 1.0 / lh;
+        ll = rl = 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        const int i = i0 + kRowsPer * q;
+        if (c == j) {
+          if (i > j && i < n) {          // L[i][j]
+            if (kDD)
+              dd_mul(ah[q], al[q], rh, rl);
+            else
+              ah[q] *= rh;
+            ch[i] = ah[q];
+            cl[i] = al[q];
+          } else if (i == j) {           // X[j][j]
+            ah[q] = rh;
+            xrow[j] = rh;
+          }
+        } else if (c < j && i == j) {    // row j of X
+          ah[q] *= rh;
+          xrow[c] = ah[q];
         }
-        Ah[tid][j] = vh;
-        ch[tid] = vh;
-        cl[tid] = vl;
       }
       __syncthreads();
-      const int m = n - j - 1;
-      for (int e = tid; e < m * m; e += kChol) {
-        const int i = j + 1 + e / m, c = j + 1 + e % m;
-        if (c > i) continue;
-        if (kDD)
-          dd_fnma(Ah[i][c], (*Al)[i][c], ch[i], cl[i], ch[c], cl[c]);
-        else
-          Ah[i][c] -= ch[i] * ch[c];
+      const double cch = ch[c], ccl = cl[c], xr = xrow[c < j ? c : j];
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        const int i = i0 + kRowsPer * q;
+        if (i >= n || i <= j) continue;
+        if (c > j) {
+          if (i >= c) {
+            if (kDD)
+              dd_fnma(ah[q], al[q], ch[i], cl[i], cch, ccl);
+            else
+              ah[q] -= ch[i] * cch;
+          }
+        } else if (c == j) {
+          ah[q] = -ah[q] * xr;           // X[i][j] = -L[i][j] X[j][j]
+        } else {
+          ah[q] -= ch[i] * xr;           // X[i][c] -= L[i][j] X[j][c]
+        }
       }
       ++kept;
       mask |= 1ull << j;
-    } else if (tid >= j && tid < n) {
-      Ah[tid][j] = 0.0;
-      if (kDD) (*Al)[tid][j] = 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        const int i = i0 + kRowsPer * q;
+        if ((c == j && i >= j) || (c < j && i == j)) ah[q] = (i == c) ? 1.0 : 0.0;
+      }
+      __syncthreads();   // every thread has read piv
+    }
+    if (c == j + 1 && j + 1 < n) {
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q)
+        if (i0 + kRowsPer * q == j + 1) {
+          piv[0] = ah[q];
+          piv[1] = al[q];
+        }
     }
     __syncthreads();
   }
-  for (int e = tid; e < kB * kB; e += kChol) {
-    const int i = e / kB, c = e % kB;
-    if (!((mask >> i) & 1ull)) Ah[i][c] = (c == i) ? 1.0 : 0.0;
-  }
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) X[i0 + kRowsPer * q][c] = ah[q];
   __syncthreads();
   return mask;
-}
-
-// X = L^{-1} for the lower-triangular L in Ah whose rows >= n are identity
-// rows (forward sweep: row j is final once divided by L[j][j]; it is then
-// eliminated from the rows below).
-__device__ void wg_tri_inv(const LdsMat& L, LdsMat& X, int n) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kB * kB; e += kChol) X[e / kB][e % kB] = (e / kB == e % kB) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (tid <= j) X[j][tid] /= L[j][j];
-    __syncthreads();
-    const int w = j + 1, m = n - j - 1;
-    for (int e = tid; e < m * w; e += kChol) {
-      const int r = j + 1 + e / w, c = e % w;
-      X[r][c] -= L[r][j] * X[j][c];
-    }
-    __syncthreads();
-  }
 }
 
 // The block's residual Gram G (double-double): Cholesky with column drop in
@@ -503,7 +612,7 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__
                                                       double* __restrict__ Tacc,
                                                       DevScalars* sc) {
   __shared__ LdsMat Ah, Al, X;
-  __shared__ double ch[kB], cl[kB], gs[kB];
+  __shared__ double ch[kB], cl[kB], xrow[kB], gs[kB], piv[2];
   __shared__ int32_t ps[kB];
   const int64_t nb = blk_count(sc, b0);
   const int tid = threadIdx.x;
@@ -520,7 +629,7 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__
   }
   if (tid < kB) gs[tid] = tid < nb ? g[tid] : 0.0;
   __syncthreads();
-  const uint64_t m = wg_chol<true>(Ah, &Al, ch, cl, gs, (int)nb, true, eps2, room);
+  const uint64_t m = wg_chol_inv<true>(Ah, &Al, X, ch, cl, xrow, piv, gs, (int)nb, true, eps2, room);
   const int na = (int)__popcll(m);
   if (tid < kB) {
     const bool my_keep = (m >> tid) & 1ull;
@@ -533,7 +642,7 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__
     if (tid < nb && accept_all) accept_all[b0 + tid] = my_keep ? 1 : 0;
   }
   if (tid == 0) sc->blk_na = na;
-  wg_tri_inv(Ah, X, (int)nb);
+  __syncthreads();   // ps
   // Tacc[a][b] = L_A^{-1}[b][a] = L^{-1}[ps[b]][ps[a]]
   for (int e = tid; e < kB * kB; e += kChol) {
     const int a = e / kB, bb = e % kB;
@@ -548,7 +657,7 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict_
                                                        double* __restrict__ Tacc,
                                                        const DevScalars* sc) {
   __shared__ LdsMat L, X, Ta;
-  __shared__ double ch[kB], cl[kB];
+  __shared__ double ch[kB], cl[kB], xrow[kB], piv[2];
   const int na = sc->blk_na;
   const int tid = threadIdx.x;
   if (na == 0) return;
@@ -558,8 +667,7 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict_
     Ta[i][c] = Tacc[e];
   }
   __syncthreads();
-  wg_chol<false>(L, nullptr, ch, cl, nullptr, na, false, 0.0, kB);
-  wg_tri_inv(L, X, na);
+  wg_chol_inv<false>(L, nullptr, X, ch, cl, xrow, piv, nullptr, na, false, 0.0, kB);
   for (int e = tid; e < kB * kB; e += kChol) {
     const int i = e / kB, bcol = e % kB;
     const bool live = i < na && bcol < na;
@@ -854,14 +962,14 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
                        a.fptr, a.val, b0, g, sc);
     hipLaunchKernelGGL(k_blk_w, dim3(div_up((int64_t)kB * nchunk * kWave, kBlock)), dim3(kBlock), 0,
                        st, a.Q, a.ldq, a.uniq_fi, a.fptr, a.row, a.val, b0, W, a.cap, nchunk, sc);
-    hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kBlock), 0, st, a.P, a.ldp, a.n_rows,
+    hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kGemm), 0, st, a.P, a.ldp, a.n_rows,
                        a.Q, a.ldq, W, a.cap, b0, Ybuf, false, sc);
     // second projection against Q (block classical Gram-Schmidt, twice)
-    hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(a.cap, kB), kSplitW), dim3(kBlock), 0, st, a.Q,
+    hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(a.cap, kB), kSplitW), dim3(kGemm), 0, st, a.Q,
                        a.ldq, a.n_rows, Ybuf, W2p, a.cap, b0, sc);
     hipLaunchKernelGGL(k_blk_w2_sum, dim3(std::max(1, std::min(1024, div_up((int64_t)kB * a.cap, kBlock)))),
                        dim3(kBlock), 0, st, W2p, W2, W, a.cap, b0, sc);
-    hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kBlock), 0, st, a.P, a.ldp, a.n_rows,
+    hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kGemm), 0, st, a.P, a.ldp, a.n_rows,
                        a.Q, a.ldq, W2, a.cap, b0, Ybuf, true, sc);
     hipLaunchKernelGGL(k_blk_gram_dd, dim3(kSplitDD), dim3(kBlock), 0, st, Ybuf, a.n_rows, b0,
                        part_hi, part_lo, sc);
