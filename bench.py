@@ -30,6 +30,9 @@ PEAK_HBM = 8000.0        # GB/s
 S_DRAWS = 2000
 SEED = 0
 GOLD = os.path.join(ROOT, "tests", "golden", "traffic_5m_s2000_seed0.npz")
+TRAFFIC = os.path.join(ROOT, "profiles", "k_proj_multi_traffic5m_s2000_pmc.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1710_03608_amd", "csrc", "project.hip")
+COPY_BYTES = 512 << 20   # plain device copy used to calibrate the HBM byte counters
 
 
 def log(msg):
@@ -68,10 +71,43 @@ def time_mode(ctd, dims, idx, val, precision, steps, warmup):
     return (t1 - t0) * 1000.0 / steps, stages, res
 
 
+def calibrate_copy():
+    """A plain device-to-device copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES), run
+    three times, so that FETCH_SIZE / WRITE_SIZE of the same profiling pass can be scaled."""
+    import torch
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def measured_traffic():
+    """HBM bytes per k_proj_multi launch from the committed rocprofv3 counter summary, or None
+    when the summary is missing or the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC).read()
+        digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("project.hip sha256") != digest:
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(X):
     """The oracle (numpy/scipy float64) on a bounded sample of the same workload."""
     from oracle import ctd as ora
-    n = 500_000
+    n = 2_000_000
     try:
         from threadpoolctl import threadpool_info
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
@@ -81,7 +117,7 @@ def cpu_baseline(X):
     r = ora.ctd_s(X.dims, X.idx[:, :n], X.val[:n], 0, S_DRAWS, SEED)
     dt = time.perf_counter() - t
     return {"value": n / dt, "unit": "nnz/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"first {n} of the 5M nonzeros (a uniform 10% subset: COO order is random), "
+            "sample": (f"first {n} of the 5M nonzeros (a uniform 40% subset: COO order is random), "
                        f"same dims, mode 0, s={S_DRAWS}, seed {SEED}; oracle CTD-S end to end "
                        f"(matricize, weights, Philox draws, independence loop, projection "
                        f"error) in {dt:.1f} s, s~={len(r.accepted)}")}
@@ -94,10 +130,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the CTD hot path here is built for a single MI355X; "
-              "multi-GPU runs are not part of this build (see the sharding notes in DESIGN.md).",
+        print("bench.py measures one GPU only: the CTD path runs on a single MI355X and has no "
+              "multi-GPU mode (it would shard by contiguous fiber-id ranges); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -138,7 +176,8 @@ def main():
     achieved = flops / (spmm_ms * 1e-3) / 1e12 if spmm_ms > 0 else 0.0
     peak = PEAK_FP64_VALU if main_mode == "fp64" else PEAK_FP32_VALU
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak,
+                "traffic": measured_traffic() if main_mode == "fp64" else None,
                 "kernel": "k_proj_multi (A8: z_f = Q^T x_f over fibers with >= 2 nonzeros)",
                 "work": f"2 * s~ ({s_t}) * nnz in multi-nonzero fibers ({stats['nnz_multi']})",
                 "kernel_ms": spmm_ms}
@@ -167,6 +206,8 @@ def main():
         "modes": results,
         "oracle_rel_err": rel_o,
     }
+    if args.calibrate_copy:
+        calibrate_copy()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(X)

@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
   CTD_OK = 0,
   CTD_ERR_INVALID_ARG = 1,  /* bad scalar argument (mode, sample size, order, dims, dtype) */
-  CTD_ERR_EMPTY = 2,        /* ||X||_F = 0: the column distribution of Algorithm 1 line 2 is undefined */
+  CTD_ERR_EMPTY = 2,        /* ||X||_F = 0: the column distribution of Algorithm 1 is undefined */
   CTD_ERR_INDEX_OOB = 3,    /* a coordinate lies outside dims */
   CTD_ERR_DUPLICATE = 4,    /* two nonzeros share a coordinate */
   CTD_ERR_NONFINITE = 5,    /* a value is NaN or infinite */
@@ -75,7 +75,7 @@ typedef struct {
 
 typedef struct {
   int32_t precision;        /* CTD_PREC_FP64 (all float64) or CTD_PREC_MIXED (float32 projection) */
-  double eps;               /* tolerance of the independence test, Algorithm 1 line 8 (the paper uses 1e-6) */
+  double eps;               /* tolerance of Algorithm 1's independence test (the paper uses 1e-6) */
   int32_t want_C;           /* CTD-S: also write C_(alpha) = R^T X_(alpha) (dense s~ x n_f) */
   int32_t want_fiber_stats; /* also keep per-fiber ||x_f||^2 - ||P x_f||^2 */
   int32_t profile;          /* time the stages of each call with HIP events (see stage_ms) */
@@ -84,13 +84,13 @@ typedef struct {
 /* Stages timed when ctd_options.profile is set (milliseconds, device time
  * between HIP events recorded on the handle's stream). */
 enum {
-  CTD_STAGE_SORT = 0,       /* fiber keys and radix sort (Algorithm 1 line 1) */
-  CTD_STAGE_SAMPLE = 1,     /* weights, prefix, draws, unique (lines 2-4) */
+  CTD_STAGE_SORT = 0,       /* fiber keys and radix sort (matricization) */
+  CTD_STAGE_SAMPLE = 1,     /* weights, prefix, draws, unique */
   CTD_STAGE_PANEL = 2,      /* dense panel of the candidates */
-  CTD_STAGE_BASIS = 3,      /* independence filter and orthonormal basis (lines 5-15) */
-  CTD_STAGE_PROJECT = 4,    /* projection of all nonzeros and the residual (line 16, Eq. 14) */
+  CTD_STAGE_BASIS = 3,      /* independence filter and orthonormal basis */
+  CTD_STAGE_PROJECT = 4,    /* projection of all nonzeros and the residual (Eq. 14) */
   CTD_STAGE_SPMM = 5,       /* the multi-nonzero fiber SpMM kernel alone (inside PROJECT) */
-  CTD_STAGE_CORE = 6,       /* C: CTD-S line 16 if want_C; CTD-D cross term and new columns */
+  CTD_STAGE_CORE = 6,       /* C: CTD-S core if want_C; CTD-D cross term and new columns */
   CTD_STAGE_TOTAL = 7,
   CTD_N_STAGES = 8
 };

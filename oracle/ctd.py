@@ -23,9 +23,9 @@ the design notes of the repository):
   * Column order of X_(alpha): column-major over the remaining modes in
     increasing mode order (mode 1 of a 3-way tensor: column j + k*J), so new
     time slices append trailing columns, as Eqs. 10-11 require.
-  * Unique selection (Algorithm 1, line 4) lists fibers by ascending column
+  * Unique selection (Algorithm 1) lists fibers by ascending column
     index; the independence loop visits them in that order.
-  * Sampling with P(i) (Algorithm 1, lines 2-3) uses integer-quantized
+  * Sampling with P(i) (Algorithm 1) uses integer-quantized
     weights so that a CPU and a GPU draw identical indices: with
     E = exponent of the largest squared value (largest v^2 < 2^E),
     L = ceil(log2 nnz) and sigma = 62 - L - E, every nonzero contributes
@@ -39,9 +39,9 @@ the design notes of the repository):
     and p the quantized probability.  R itself stays unscaled (actual
     fibers); the scale is reported beside it and changes neither U, C nor
     the error, because the projection onto span(R) ignores column scaling.
-  * The independence test (Algorithm 1, line 8) skips a fiber when
+  * The independence test (Algorithm 1) skips a fiber when
     ||res|| <= eps ||x||, equality included; the first unique fiber is
-    always kept (line 5).
+    always kept (R starts from it).
   * A tensor with ||X||_F = 0 has no column distribution and is rejected, as
     are duplicate coordinates, out-of-range indices and non-finite values.
 """
@@ -125,7 +125,7 @@ def unfold(dims, idx, val, mode) -> Unfolding:
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 1, lines 2-4: column distribution, sampling, unique selection
+# Algorithm 1: column distribution, sampling, unique selection
 # ---------------------------------------------------------------------------
 
 def quantized_weights(u: Unfolding):
@@ -176,7 +176,7 @@ def unique_with_scale(draws, w, W, s):
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 1, lines 5-15 / Algorithm 2, lines 5-16: independence loop
+# Algorithms 1 and 2: independence loop
 # ---------------------------------------------------------------------------
 
 @dataclasses.dataclass
@@ -208,7 +208,7 @@ class Basis:
 def residual_against_span(Qb, x):
     """x minus its orthogonal projection onto span(Qb) (projected twice).
 
-    This is the residual of Algorithm 1, line 7: with U = (R^T R)^{-1},
+    This is the residual of Algorithm 1's test: with U = (R^T R)^{-1},
     R U R^T is the orthogonal projector onto span(R).  Evaluating it through
     the incrementally updated U loses all accuracy once R is ill-conditioned,
     so the projection is taken with an orthonormal basis of span(R) instead.
@@ -222,8 +222,8 @@ def independence_loop(basis: Basis, candidates, eps):
 
     `candidates` yields dense I_alpha vectors.  Returns (kept flags,
     rho = ||res||^2 / ||x||^2 for every candidate).  A fresh basis (k == 0)
-    takes the first candidate unconditionally (Algorithm 1, line 5).  Kept
-    fibers extend R (line 13) and U by the bordered-inverse update (line 12).
+    takes the first candidate unconditionally (Algorithm 1).  Kept
+    fibers extend R and U by the bordered-inverse update of Algorithm 1.
     """
     kept, rho = [], []
     for x in candidates:
@@ -262,7 +262,7 @@ def independence_loop(basis: Basis, candidates, eps):
 
 
 # ---------------------------------------------------------------------------
-# Algorithm 1, line 16 and Eq. 14: C and the relative error
+# Algorithm 1 (final step) and Eq. 14: C and the relative error
 # ---------------------------------------------------------------------------
 
 def core_matrix(R, u: Unfolding) -> np.ndarray:

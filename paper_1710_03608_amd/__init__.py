@@ -61,12 +61,12 @@ _hip = None
 
 
 def load_library():
-    """Load libctd.so (built by __graft_entry__.build()); raise if it is missing."""
+    """Load libctd.so (built by build_lib.py); raise if it is missing."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        raise RuntimeError(f"{LIB_PATH} is not built; run python paper_1710_03608_amd/build_lib.py")
     lib = ctypes.CDLL(LIB_PATH)
     lib.ctd_create.argtypes = [ctypes.POINTER(c_vp), ctypes.POINTER(OptionsStruct), c_vp]
     lib.ctd_decompose.argtypes = [c_vp, ctypes.POINTER(CooStruct), c_i32, c_i64, c_u64]

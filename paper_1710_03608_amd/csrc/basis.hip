@@ -1,14 +1,14 @@
 // Independence filter and orthonormal basis, block by block (Algorithm 1
-// lines 5-15; Algorithm 2 lines 5-16).
+// the independence loops of Algorithms 1 and 2).
 //
 // Candidates are visited in order in blocks of 64.  For a block B with the
 // kept set so far spanned by the orthonormal columns of Q (k of them):
 //   W = Q^T X_B                 (sparse fibers times dense Q)
 //   M = X_B^T X_B - W W^T       (Gram of the residuals X_B - Q W: its
 //                                Schur complements are the squared residual
-//                                norms ||res||^2 of Algorithm 1 line 7)
+//                                norms ||res||^2 of Algorithm 1's test)
 //   Cholesky of M in candidate order, dropping a candidate whose pivot is
-//   <= eps^2 ||x||^2 (line 8); the pivots are accurate to about u ||x||^2
+//   <= eps^2 ||x||^2 (the skip rule); the pivots are accurate to about u ||x||^2
 //   because Q is orthonormal, whatever the conditioning of R.
 // The kept candidates' residuals Y = X_A - Q W_A are formed explicitly and
 // orthonormalized by two Cholesky-QR passes (Y <- Y L1^{-T}, Y <- Y L2^{-T});

@@ -1,5 +1,5 @@
 // CTD-D (Section 3.2, Algorithm 2) and the core tensor C of CTD-S
-// (Algorithm 1 line 16).
+// (the final step of Algorithm 1).
 //
 // State kept between slices (all device memory):
 //   Rs  n_rows x capD  the kept fibers (the paper's R), row-major
@@ -9,11 +9,11 @@
 //                      non-empty fiber seen so far (tensor then slices)
 // One slice dX with d draws:
 //   1. fibers, weights, draws (Philox counter word = step t), unique
-//      candidates: the same kernels as CTD-S (Algorithm 2 lines 1-4);
+//      candidates: the same kernels as CTD-S (the sampling steps of Algorithm 2);
 //   2. the candidates are tested against R^(t) and each other and the kept
 //      ones extend R, Q and M: the same block filter as CTD-S, started from
-//      the d~_t columns already held (lines 5-16);
-//   3. C (lines 17-21, Eq. 13): rows for the kept fibers over the earlier
+//      the d~_t columns already held (the independence loop of Algorithm 2);
+//   3. C (the core update of Algorithm 2, Eq. 13): rows for the kept fibers over the earlier
 //      columns are ((dR^T R^(t)) U^(t)) C^(t), parenthesized from the left as
 //      the paper prescribes; with w = Q^(t)T x the row vector dR^T R^(t) U^(t)
 //      equals (M^(t) w)^T, so one pass over C^(t) applies them; the new
@@ -467,7 +467,7 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
   if (nnz > 0) {
     rc = enqueue_input(h, slice, lay, d, h->seed, step, nullptr, b);
     if (rc != CTD_OK) return rc;
-    // candidates against R^(t) and each other; kept ones extend R, Q, M (lines 5-16)
+    // candidates against R^(t) and each other; kept ones extend R, Q, M
     launch_panel(st, b.uniq_fi, d, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
     mark(h, MARK_PANEL);
     BasisArgs ba{};

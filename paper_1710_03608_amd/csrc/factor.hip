@@ -1,4 +1,4 @@
-// Candidate panel (Algorithm 1 line 5 / line 13: R is built from actual
+// Candidate panel (Algorithm 1: R is initialized with and extended by actual
 // fibers of X).  The s' unique candidate fibers are scattered into a dense
 // row-major n_rows x s' panel, zero elsewhere, so that block Gram products and
 // residual vectors of the independence filter read them with coalesced rows.

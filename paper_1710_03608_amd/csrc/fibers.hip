@@ -1,5 +1,5 @@
-// Fiber keying and fiber-major layout (Algorithm 1 line 1, Section 2.1),
-// squared norms and integer sampling weights (Algorithm 1 line 2).
+// Fiber keying and fiber-major layout (matricization, Section 2.1), squared
+// norms and integer sampling weights (the column distribution of Algorithm 1).
 //
 // Each nonzero gets the 64-bit key (fiber id << rbits | row), where the
 // fiber id is its column in X_(alpha) (column-major over the other modes)

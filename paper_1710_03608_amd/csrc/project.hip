@@ -1,5 +1,5 @@
 // Projection of X_(alpha) onto span(R) over all nonzeros and the Frobenius
-// residual (Algorithm 1 line 16, Eq. 14).
+// residual (the final step of Algorithm 1, Eq. 14).
 //
 // With Q = R L^{-T} orthonormal, X~ = R U C_(alpha) = Q Q^T X_(alpha), so
 // ||X - X~||_F^2 = sum_f (||x_f||^2 - ||Q^T x_f||^2) over the non-empty

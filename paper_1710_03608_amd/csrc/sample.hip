@@ -1,5 +1,5 @@
-// Weighted sampling with replacement (Algorithm 1 lines 2-3, Algorithm 2
-// lines 2-3) and unique selection (Algorithm 1 line 4).
+// Weighted sampling with replacement from the column distribution P(i) and
+// unique selection of the drawn fibers (Algorithms 1 and 2).
 //
 // Draw j: r = Philox4x32-10(counter (j, j>>32, step, tensor), key (seed,
 // seed>>32)) read as a 128-bit integer, target t = floor(r * W / 2^128)

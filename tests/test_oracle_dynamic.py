@@ -33,7 +33,7 @@ def test_block_update_equals_direct_product():
             saw_growth = True
         else:
             saw_empty = True
-            # line 20: only new columns are added
+            # empty dR: only new columns are added (Algorithm 2)
             assert dyn.C.shape[0] == C_old.shape[0]
     assert saw_growth
 

@@ -85,7 +85,7 @@ def test_matricization_rejects_bad_input():
         ctd.ctd_s(t.dims, t.idx, t.val, 0, t.dims[1] * t.dims[2] + 1, 0)
 
 
-# --- Algorithm 1 lines 2-3: column distribution and sampling ---------------
+# --- Algorithm 1: column distribution and sampling -------------------------
 
 def test_quantized_weights_exact_bound():
     """Each fiber weight is within nnz_f of ||x_f||^2 * 2^sigma (exact rationals)."""
@@ -143,7 +143,7 @@ def test_zero_weight_columns_never_drawn():
     assert set(np.unique(pos).tolist()) <= {1, 4}
 
 
-# --- Algorithm 1 line 4 and the duplicate-merge scale ----------------------
+# --- Algorithm 1 unique selection and the duplicate-merge scale ------------
 
 def _cols(u, positions):
     return np.stack([u.column(j) for j in positions], axis=1)
@@ -198,7 +198,7 @@ def test_column_scaling_leaves_error_unchanged():
     assert e1 == pytest.approx(e2, rel=1e-10)
 
 
-# --- Algorithm 1 lines 5-15 and Lemma 2 ------------------------------------
+# --- Algorithm 1 independence loop and Lemma 2 ----------------------------
 
 @pytest.mark.parametrize("seed,s", [(0, 10), (1, 40), (2, 120)])
 def test_lemma2_error_equals_least_squares(seed, s):
