@@ -513,7 +513,8 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
                        S.col_fid, nullptr, &sc->n_cols_total, t_off);
     mark(h, MARK_CORE);
     // slice residual against the grown basis
-    ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total, S.capD);
+    ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total,
+                                  std::min<int64_t>(n_rows, S.d_ub + d));
     if (h->opt.profile) {
       mark(h, MARK_PROJ0);
       mark(h, MARK_SPMM0);
