@@ -90,61 +90,76 @@ __device__ inline int64_t blk_count(const DevScalars* sc, int64_t b0) {
   return b0 < sp ? min((int64_t)kB, sp - b0) : 0;
 }
 
-// g[j] = ||x_{b0+j}||^2; one wave per candidate.
-__global__ __launch_bounds__(kBlock) void k_blk_norms(const int32_t* __restrict__ uniq_fi,
-                                                      const int32_t* __restrict__ fptr,
-                                                      const double* __restrict__ val, int64_t b0,
-                                                      double* __restrict__ g,
-                                                      const DevScalars* sc) {
-  const int64_t nb = blk_count(sc, b0);
-  const int j = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-  if (j >= nb) return;
-  const int32_t f = uniq_fi[b0 + j];
-  const int32_t e0 = fptr[f], e1 = fptr[f + 1];
-  double s = 0.0;
-  for (int32_t e = e0 + lane_id(); e < e1; e += kWave) s += val[e] * val[e];
-  s = wave_sum(s);
-  if (lane_id() == 0) g[j] = s;
-}
-
-// W[j][c] = sum_e v_e Q[r_e][c] for c < k; one wave per (candidate, 64
-// columns), sixteen nonzeros in flight per iteration.
-__global__ __launch_bounds__(kBlock) void k_blk_w(const double* __restrict__ Q, int64_t ldq,
-                                                  const int32_t* __restrict__ uniq_fi,
-                                                  const int32_t* __restrict__ fptr,
-                                                  const int32_t* __restrict__ row,
-                                                  const double* __restrict__ val, int64_t b0,
-                                                  double* __restrict__ W, int64_t ldw, int nchunk,
-                                                  const DevScalars* sc) {
+// W[j][c] = sum_e v_e Q[r_e][c] for c < k, and g[j] = ||x_{b0+j}||^2.
+// Workgroup (chunk, j) covers columns 128 chunk .. + 128 of candidate j (two
+// per lane); its eight waves take the fiber's nonzeros in interleaved groups
+// of 16 (sixteen row gathers in flight per wave) and their partial rows are
+// added in LDS in wave order.  Chunk 0 also forms the squared norm.
+constexpr int kWWaves = 8;
+constexpr int kWCols = 2 * kWave;
+__global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(
+    const double* __restrict__ Q, int64_t ldq, const int32_t* __restrict__ uniq_fi,
+    const int32_t* __restrict__ fptr, const int32_t* __restrict__ row,
+    const double* __restrict__ val, int64_t b0, double* __restrict__ W, int64_t ldw,
+    double* __restrict__ g, const DevScalars* sc) {
   constexpr int kU = 16;
+  __shared__ double part[kWWaves][kWCols];
+  __shared__ double gpart[kWWaves];
   const int64_t nb = blk_count(sc, b0);
   const int64_t k = sc->n_accept_total;
-  const int64_t wid = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int j = (int)(wid / nchunk);
-  const int64_t cbase = (wid % nchunk) * kWave;
-  if (j >= nb || cbase >= k) return;
-  const int64_t c = cbase + lane_id();
-  const bool active = c < k;
+  const int j = blockIdx.y;
+  const int64_t cbase = (int64_t)blockIdx.x * kWCols;
+  if (j >= nb || (blockIdx.x > 0 && cbase >= k)) return;
+  const int wv = threadIdx.x / kWave, l = lane_id();
+  const int64_t c = cbase + 2 * l;
+  const bool active = c < k;   // ldq is even, so the 16 B load at c stays in the row
   const double* Qc = Q + (active ? c : 0);
   const int32_t f = uniq_fi[b0 + j];
   const int32_t e0 = fptr[f], e1 = fptr[f + 1];
-  double acc = 0.0;
-  int32_t e = e0;
-  for (; e + kU <= e1; e += kU) {
+  double a0 = 0.0, a1 = 0.0, gs = 0.0;
+  for (int32_t eb = e0 + wv * kU; eb < e1; eb += kWWaves * kU) {
+    const int n = min(kU, e1 - eb);
     int32_t r[kU];
-    double v[kU], q[kU];
+    double v[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      r[u] = row[e + u];
-      v[u] = val[e + u];
+      r[u] = u < n ? row[eb + u] : 0;
+      v[u] = u < n ? val[eb + u] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) q[u] = Qc[(int64_t)r[u] * ldq];
+    for (int u = 0; u < kU; ++u) gs += v[u] * v[u];
+    if (active) {
+      double2 q[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) acc += v[u] * q[u];
+      for (int u = 0; u < kU; ++u)
+        q[u] = u < n ? *(const double2*)(Qc + (int64_t)r[u] * ldq) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        a0 += v[u] * q[u].x;
+        a1 += v[u] * q[u].y;
+      }
+    }
   }
-  for (; e < e1; ++e) acc += val[e] * Qc[(int64_t)row[e] * ldq];
-  if (active) W[(int64_t)j * ldw + c] = acc;
+  part[wv][2 * l] = a0;
+  part[wv][2 * l + 1] = a1;
+  if (l == 0) gpart[wv] = gs;
+  __syncthreads();
+  if (wv == 0) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWWaves; ++w) {
+      s0 += part[w][2 * l];
+      s1 += part[w][2 * l + 1];
+    }
+    if (c < k) W[(int64_t)j * ldw + c] = s0;
+    if (c + 1 < k) W[(int64_t)j * ldw + c + 1] = s1;
+    if (blockIdx.x == 0 && l == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWWaves; ++w) t += gpart[w];
+      g[j] = t;
+    }
+  }
 }
 
 // Dense f64 MFMA kernels below run 512 threads as two groups of four waves
@@ -650,17 +665,35 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__
   }
 }
 
-// Cholesky (no drop) of the kept block's Gram after its first pass,
-// Tcur = L^{-T}, Tacc <- Tacc Tcur (both upper triangular).
+// Second Cholesky-QR pass of the kept block, taken only when needed: if the
+// Gram of the first-pass columns is within kOrthTol of the identity they are
+// orthonormal to working accuracy and Tacc stays as it is (blk_reorth = 0).
+// Otherwise Cholesky (no drop) of that Gram, Tcur = L^{-T}, Tacc <- Tacc Tcur.
+constexpr double kOrthTol = 1e-12;
 __global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict__ G,
                                                        double* __restrict__ Tcur,
                                                        double* __restrict__ Tacc,
-                                                       const DevScalars* sc) {
+                                                       DevScalars* sc) {
   __shared__ LdsMat L, X, Ta;
   __shared__ double ch[kB], cl[kB], xrow[kB], piv[2];
+  __shared__ int any_off;
   const int na = sc->blk_na;
   const int tid = threadIdx.x;
   if (na == 0) return;
+  if (tid == 0) any_off = 0;
+  __syncthreads();
+  bool off = false;
+  for (int e = tid; e < kB * kB; e += kChol) {
+    const int i = e / kB, c = e % kB;
+    if (i < na && c < na) off = off || fabs(G[e] - (i == c ? 1.0 : 0.0)) > kOrthTol;
+  }
+  if (off) any_off = 1;
+  __syncthreads();
+  if (!any_off) {
+    if (tid == 0) sc->blk_reorth = 0;
+    return;
+  }
+  if (tid == 0) sc->blk_reorth = 1;
   for (int e = tid; e < kB * kB; e += kChol) {
     const int i = e / kB, c = e % kB;
     L[i][c] = (i < na && c <= i) ? G[e] : 0.0;
@@ -732,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_apply(double* __restrict__ Q, in
   __shared__ double Ts[kB][kB + 1];
   __shared__ double Ys[kB][kB + 1];
   const int na = sc->blk_na;
-  if (na == 0) return;
+  if (na == 0 || !sc->blk_reorth) return;
   const int64_t k = sc->n_accept_total;
   const int64_t r0 = (int64_t)blockIdx.x * kB;
   for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
@@ -951,17 +984,15 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
   double* Z = g + kB;
   double* Ybuf = Z + (size_t)kB * a.cap;
   int32_t* pos = (int32_t*)(Ybuf + (size_t)kB * a.n_rows);
-  const int nchunk = div_up(a.cap, kWave);
+  const int wchunks = std::max(1, div_up(a.cap, kWCols));
   const int rows_tiles32 = div_up(a.n_rows, 32);
   const int rows4 = div_up(a.n_rows, kB);
   const int cross_tiles = div_up(a.cap, kB);
   const int ext_grid = std::max(1, std::min(4096, div_up((a.cap + kB) * kB, 256)));
   hipLaunchKernelGGL(k_begin_basis, dim3(1), dim3(1), 0, st, sc);
   for (int64_t b0 = 0; b0 < a.s_max; b0 += kB) {
-    hipLaunchKernelGGL(k_blk_norms, dim3(kB * kWave / kBlock), dim3(kBlock), 0, st, a.uniq_fi,
-                       a.fptr, a.val, b0, g, sc);
-    hipLaunchKernelGGL(k_blk_w, dim3(div_up((int64_t)kB * nchunk * kWave, kBlock)), dim3(kBlock), 0,
-                       st, a.Q, a.ldq, a.uniq_fi, a.fptr, a.row, a.val, b0, W, a.cap, nchunk, sc);
+    hipLaunchKernelGGL(k_blk_w, dim3(wchunks, kB), dim3(kWWaves * kWave), 0, st, a.Q, a.ldq,
+                       a.uniq_fi, a.fptr, a.row, a.val, b0, W, a.cap, g, sc);
     hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kGemm), 0, st, a.P, a.ldp, a.n_rows,
                        a.Q, a.ldq, W, a.cap, b0, Ybuf, false, sc);
     // second projection against Q (block classical Gram-Schmidt, twice)

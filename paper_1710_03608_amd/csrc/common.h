@@ -26,12 +26,11 @@ struct DevScalars {
   int32_t n_f;           // non-empty fibers of the last input
   int32_t s_unique;      // s' of the last call
   int32_t s_tilde;       // fibers accepted by the last call
-  int32_t n_multi;       // fibers with 2 .. kSmallFiber nonzeros (projection work list, front)
-  int32_t n_multi_large; // fibers with more nonzeros (projection work list, back)
   int32_t n_accept_total;// accepted fibers held in R
   int32_t allow_empty;   // CTD-D: an all-zero slice is not an error
   int32_t base_accept;   // fibers kept before the current call
   int32_t blk_na;        // fibers kept by the current candidate block
+  int32_t blk_reorth;    // the block's first Cholesky-QR pass left it non-orthonormal
 };
 __device__ inline void latch_status(DevScalars* sc, int code) {
   atomicCAS(&sc->status, 0, code);

@@ -20,41 +20,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRedBlock = 1024;
 constexpr int kRedItems = 8;
-constexpr int kGrp = 16;        // lanes that share one nonzero's row segment (16 B each)
-constexpr int kSmallFiber = 8;  // fibers up to this length get one 16-lane group each
-
-// Fibers with one nonzero: residual from the row leverage.  Longer fibers are
-// listed for the panel kernel: up to kSmallFiber nonzeros from the front of
-// `multi`, longer ones from the back.
-__global__ __launch_bounds__(kBlock) void k_proj_single(ProjectArgs a, DevScalars* sc) {
-  const int64_t n_f = sc->status == 0 ? sc->n_f : 0;
-  const int lane = lane_id();
-  for (int64_t f0 = (int64_t)blockIdx.x * kBlock; f0 < n_f; f0 += (int64_t)gridDim.x * kBlock) {
-    const int64_t f = f0 + threadIdx.x;
-    bool small = false, large = false;
-    if (f < n_f) {
-      const int32_t e0 = a.fptr[f], e1 = a.fptr[f + 1];
-      if (e1 - e0 == 1) {
-        const double v = a.val[e0];
-        const double x2 = v * v;
-        const double z2 = x2 * a.lev[a.row[e0]];
-        a.resid[f] = (a.fiber_mark && a.fiber_mark[f]) ? 0.0 : x2 - z2;
-      } else {
-        small = e1 - e0 <= kSmallFiber;
-        large = !small;
-      }
-    }
-    const uint64_t lt = lane == 0 ? 0ull : ((~0ull) >> (kWave - lane));
-    const uint64_t ms = __ballot(small), ml = __ballot(large);
-    int32_t bs = 0, bl = 0;
-    if (lane == 0 && ms) bs = atomicAdd(&sc->n_multi, (int32_t)__popcll(ms));
-    if (lane == 0 && ml) bl = atomicAdd(&sc->n_multi_large, (int32_t)__popcll(ml));
-    bs = __shfl(bs, 0, kWave);
-    bl = __shfl(bl, 0, kWave);
-    if (small) a.multi[bs + __popcll(ms & lt)] = (int32_t)f;
-    if (large) a.multi[n_f - 1 - (bl + __popcll(ml & lt))] = (int32_t)f;
-  }
-}
 
 __device__ inline int32_t read_lane(int32_t v, int lane) {
   return __builtin_amdgcn_readlane(v, lane);
@@ -90,89 +55,113 @@ __device__ inline void load_seg(const T* p, T (&x)[VEC]) {
   }
 }
 
-// z_f = sum_e v_e Q[r_e, :] for every fiber with two or more nonzeros; one
-// wave per fiber, lane l holding columns VEC l .. VEC l + VEC of each
-// 64 VEC-column chunk.  The fiber's (row, value) pairs are loaded once per
-// 64 nonzeros into lanes and broadcast with readlane, so the inner loop only
-// issues row gathers: two nonzeros times two column chunks (8 KB per wave)
-// are in flight per iteration.  Column chunks of z are squared and summed as
-// they complete; z is never written.
+// Residual of every fiber.  A wave takes 64 consecutive fibers, one per
+// lane.  Fibers with one nonzero v at row r are done lane-parallel from the
+// row leverage: ||Q^T x||^2 = v^2 ||Q_r||^2.  The wave then walks the others
+// one at a time: z_f = sum_e v_e Q[r_e, :], lane l holding columns
+// VEC l .. VEC l + VEC of each 64 VEC-column chunk.  The fiber's (row, value)
+// pairs are loaded once per 64 nonzeros into lanes and broadcast with
+// readlane, so the inner loop only issues row gathers: two nonzeros times two
+// column chunks (8 KB per wave) in flight per iteration.  Column chunks of z
+// are squared and summed as they complete; z is never written.  Kept fibers
+// lie in span(Q) and get 0.
 template <typename T, int VEC>
 __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, const DevScalars* sc) {
   constexpr int kCols = VEC * kWave;
   if (sc->status != 0) return;
   const int64_t n_f = sc->n_f;
-  const int64_t n_small = sc->n_multi, nm = n_small + sc->n_multi_large;
   const int64_t ncols = *a.d_ncols;
   const int lane = lane_id();
   const T* Qb = sizeof(T) == 8 ? (const T*)a.Q : (const T*)a.Qf;
   const T* vals = sizeof(T) == 8 ? (const T*)a.val : (const T*)a.val32;
   const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
-  for (int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; w < nm; w += nwaves) {
-    const int32_t f = w < n_small ? a.multi[w] : a.multi[n_f - 1 - (w - n_small)];
-    const int32_t e0 = a.fptr[f], e1 = a.fptr[f + 1];
-    double x2 = 0.0, z2 = 0.0;
-    for (int64_t c0 = 0; c0 < ncols; c0 += 2 * kCols) {
-      const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
-      const bool ina = ca < ncols, inb = cb < ncols;
-      const T* qa = Qb + (ina ? ca : 0);
-      const T* qb = Qb + (inb ? cb : 0);
-      T acc0[VEC], acc1[VEC];
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) acc0[k] = acc1[k] = T(0);
-      for (int32_t eb = e0; eb < e1; eb += kWave) {
-        const int nb = min(kWave, e1 - eb);
-        const int32_t rr = lane < nb ? a.row[eb + lane] : 0;
-        const T vv = lane < nb ? vals[eb + lane] : T(0);
-        if (c0 == 0 && lane < nb) x2 += a.val[eb + lane] * a.val[eb + lane];
-        int k = 0;
-        for (; k + 1 < nb; k += 2) {
-          const int64_t r0 = read_lane(rr, k), r1 = read_lane(rr, k + 1);
-          const T v0 = read_lane(vv, k), v1 = read_lane(vv, k + 1);
-          T x0[VEC], x1[VEC], y0[VEC], y1[VEC];
-          if (ina) {
-            load_seg<T, VEC>(qa + r0 * a.ldq, x0);
-            load_seg<T, VEC>(qa + r1 * a.ldq, x1);
-          }
-          if (inb) {
-            load_seg<T, VEC>(qb + r0 * a.ldq, y0);
-            load_seg<T, VEC>(qb + r1 * a.ldq, y1);
-          }
-          if (ina) {
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) acc0[j] += v0 * x0[j] + v1 * x1[j];
-          }
-          if (inb) {
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) acc1[j] += v0 * y0[j] + v1 * y1[j];
-          }
-        }
-        if (k < nb) {
-          const int64_t r0 = read_lane(rr, k);
-          const T v0 = read_lane(vv, k);
-          T x0[VEC], y0[VEC];
-          if (ina) load_seg<T, VEC>(qa + r0 * a.ldq, x0);
-          if (inb) load_seg<T, VEC>(qb + r0 * a.ldq, y0);
-          if (ina) {
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) acc0[j] += v0 * x0[j];
-          }
-          if (inb) {
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) acc1[j] += v0 * y0[j];
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < VEC; ++j) {
-        const double d0 = (double)acc0[j], d1 = (double)acc1[j];
-        z2 += (ca + j < ncols) ? d0 * d0 : 0.0;
-        z2 += (cb + j < ncols) ? d1 * d1 : 0.0;
+  for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * kWave; fb < n_f;
+       fb += nwaves * kWave) {
+    const int64_t fl = fb + lane;
+    bool multi = false;
+    if (fl < n_f) {
+      const int32_t s0 = a.fptr[fl], s1 = a.fptr[fl + 1];
+      const bool kept = a.fiber_mark && a.fiber_mark[fl];
+      if (kept) {
+        a.resid[fl] = 0.0;
+      } else if (s1 - s0 == 1) {
+        const double v = a.val[s0];
+        const double x2 = v * v;
+        const double z2 = x2 * a.lev[a.row[s0]];
+        a.resid[fl] = x2 - z2;
+      } else {
+        multi = true;
       }
     }
-    x2 = wave_sum(x2);
-    z2 = wave_sum(z2);
-    if (lane == 0) a.resid[f] = (a.fiber_mark && a.fiber_mark[f]) ? 0.0 : x2 - z2;
+    uint64_t todo = __ballot(multi);
+    while (todo) {
+      const int i = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int64_t f = fb + i;
+      const int32_t e0 = a.fptr[f], e1 = a.fptr[f + 1];
+      double x2 = 0.0, z2 = 0.0;
+      for (int64_t c0 = 0; c0 < ncols; c0 += 2 * kCols) {
+        const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
+        const bool ina = ca < ncols, inb = cb < ncols;
+        const T* qa = Qb + (ina ? ca : 0);
+        const T* qb = Qb + (inb ? cb : 0);
+        T acc0[VEC], acc1[VEC];
+  #pragma unroll
+        for (int k = 0; k < VEC; ++k) acc0[k] = acc1[k] = T(0);
+        for (int32_t eb = e0; eb < e1; eb += kWave) {
+          const int nb = min(kWave, e1 - eb);
+          const int32_t rr = lane < nb ? a.row[eb + lane] : 0;
+          const T vv = lane < nb ? vals[eb + lane] : T(0);
+          if (c0 == 0 && lane < nb) x2 += a.val[eb + lane] * a.val[eb + lane];
+          int k = 0;
+          for (; k + 1 < nb; k += 2) {
+            const int64_t r0 = read_lane(rr, k), r1 = read_lane(rr, k + 1);
+            const T v0 = read_lane(vv, k), v1 = read_lane(vv, k + 1);
+            T x0[VEC], x1[VEC], y0[VEC], y1[VEC];
+            if (ina) {
+              load_seg<T, VEC>(qa + r0 * a.ldq, x0);
+              load_seg<T, VEC>(qa + r1 * a.ldq, x1);
+            }
+            if (inb) {
+              load_seg<T, VEC>(qb + r0 * a.ldq, y0);
+              load_seg<T, VEC>(qb + r1 * a.ldq, y1);
+            }
+            if (ina) {
+  #pragma unroll
+              for (int j = 0; j < VEC; ++j) acc0[j] += v0 * x0[j] + v1 * x1[j];
+            }
+            if (inb) {
+  #pragma unroll
+              for (int j = 0; j < VEC; ++j) acc1[j] += v0 * y0[j] + v1 * y1[j];
+            }
+          }
+          if (k < nb) {
+            const int64_t r0 = read_lane(rr, k);
+            const T v0 = read_lane(vv, k);
+            T x0[VEC], y0[VEC];
+            if (ina) load_seg<T, VEC>(qa + r0 * a.ldq, x0);
+            if (inb) load_seg<T, VEC>(qb + r0 * a.ldq, y0);
+            if (ina) {
+  #pragma unroll
+              for (int j = 0; j < VEC; ++j) acc0[j] += v0 * x0[j];
+            }
+            if (inb) {
+  #pragma unroll
+              for (int j = 0; j < VEC; ++j) acc1[j] += v0 * y0[j];
+            }
+          }
+        }
+  #pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+          const double d0 = (double)acc0[j], d1 = (double)acc1[j];
+          z2 += (ca + j < ncols) ? d0 * d0 : 0.0;
+          z2 += (cb + j < ncols) ? d1 * d1 : 0.0;
+        }
+      }
+      x2 = wave_sum(x2);
+      z2 = wave_sum(z2);
+      if (lane == 0) a.resid[f] = x2 - z2;
+    }
   }
 }
 
@@ -201,18 +190,11 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_final(const double* __rest
   if (threadIdx.x == 0) sc->err2 = s;
 }
 
-__global__ void k_zero_counts(DevScalars* sc) {
-  sc->n_multi = 0;
-  sc->n_multi_large = 0;
-}
 }  // namespace
 
 void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,
                     hipEvent_t ev0, hipEvent_t ev1) {
-  hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(1), 0, st, sc);
-  const int gs = std::max(1, std::min(8192, div_up(nnz_max, kBlock)));
-  hipLaunchKernelGGL(k_proj_single, dim3(gs), dim3(kBlock), 0, st, a, sc);
-  const int gm = std::max(1, std::min(4096, div_up(nnz_max / 2 * kWave, kBlock)));
+  const int gm = std::max(1, std::min(4096, div_up(nnz_max, kBlock)));
   if (ev0) (void)hipEventRecord(ev0, st);
   if (a.mixed)
     hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(gm), dim3(kBlock), 0, st, a, sc);
