@@ -71,6 +71,35 @@ def time_mode(ctd, dims, idx, val, precision, steps, warmup):
     return (t1 - t0) * 1000.0 / steps, stages, res
 
 
+STREAM_S, STREAM_D = 800, 8
+
+
+def time_stream(ctd, st, precision):
+    """CTD-D over the whole stream: the initial CTD-S (s = 800) and then every slice
+    (d = 8), slices resident on the device.  One untimed pass, then a timed one; the
+    timed region is the slice updates (the initial decomposition is reported apart)."""
+    import torch
+    dims0, idx0, val0 = ctd.to_device(st.initial, "cuda")
+    slices = [ctd.to_device(sl, "cuda") for sl in st.slices]
+    h = ctd.Ctd(precision=precision, want_C=True)
+    out = {}
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.decompose(dims0, idx0, val0, 0, STREAM_S, SEED)
+        h.sync()
+        t1 = time.perf_counter()
+        for sd, si, sv in slices:
+            h.update(sd, si, sv, STREAM_D)
+        h.sync()
+        t2 = time.perf_counter()
+        r = h.result(arrays=False)
+        out = {"initial_ms": (t1 - t0) * 1e3, "slices_ms": (t2 - t1) * 1e3,
+               "rel_err": r["rel_err"], "d_tilde": r["s_tilde"], "n_cols": r["n_cols"]}
+    h.close()
+    return out
+
+
 def calibrate_copy():
     """A plain device-to-device copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES), run
     three times, so that FETCH_SIZE / WRITE_SIZE of the same profiling pass can be scaled."""
@@ -130,6 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--no-stream", action="store_true", help="skip the CTD-D stream leg")
+    ap.add_argument("--stream-only", action="store_true", help="run only the CTD-D stream leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -144,6 +175,27 @@ def main():
 
     import paper_1710_03608_amd as ctd
     from workloads import synth
+
+    stream_line = None
+    if not args.no_stream:
+        log("generating the CTD-D traffic stream ...")
+        st = synth.traffic_stream()
+        torch.cuda.set_device(0)
+        slice_nnz = int(sum(x.nnz for x in st.slices))
+        stream_line = {"workload": "ctd_d_stream_4000x4000x200_nnz1000000_zipf1.1_200slices_s800_d8",
+                       "slices": len(st.slices), "slice_nnz": slice_nnz, "modes": {}}
+        for mode in args.modes.split(","):
+            log(f"CTD-D stream, {mode}")
+            r = time_stream(ctd, st, mode)
+            r["slice_nnz_per_s"] = slice_nnz / (r["slices_ms"] * 1e-3)
+            r["slices_per_s"] = len(st.slices) / (r["slices_ms"] * 1e-3)
+            stream_line["modes"][mode] = r
+            log(f"  {mode}: initial {r['initial_ms']:.1f} ms, 200 slices {r['slices_ms']:.1f} ms, "
+                f"{r['slice_nnz_per_s']:.3e} nnz/s, rel_err {r['rel_err']:.6f}")
+        del st
+        if args.stream_only:
+            print(json.dumps({"ctd_d_stream": stream_line}), flush=True)
+            return
 
     log("generating the 5M-nonzero traffic tensor ...")
     X = synth.traffic_5m()
@@ -206,6 +258,8 @@ def main():
         "modes": results,
         "oracle_rel_err": rel_o,
     }
+    if stream_line is not None:
+        line["ctd_d_stream"] = stream_line
     if args.calibrate_copy:
         calibrate_copy()
     if not args.no_cpu_baseline:

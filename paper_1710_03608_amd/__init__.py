@@ -114,6 +114,15 @@ def device_to_numpy(ptr, count, dtype):
     return out
 
 
+def device_columns(ptr, ld, rows, cols, dtype=np.float64):
+    """Columns `cols` (first `rows` entries each) of a column-major device matrix."""
+    dtype = np.dtype(dtype)
+    out = np.empty((rows, len(cols)), dtype=dtype)
+    for j, c in enumerate(cols):
+        out[:, j] = device_to_numpy(ptr + int(c) * ld * dtype.itemsize, rows, dtype)
+    return out
+
+
 def device_matrix(ptr, rows, cols, ld, dtype=np.float64, row_major=True):
     flat = device_to_numpy(ptr, rows * ld if row_major else cols * ld, dtype)
     if row_major:
@@ -201,6 +210,13 @@ class Ctd:
         r = ResultStruct()
         self._check(self.lib.ctd_get_result(self.h, ctypes.byref(r)))
         return r
+
+    def core_columns(self, cols):
+        """Selected columns of C_(alpha) (s~ rows each), copied to the host."""
+        r = self.raw_result()
+        if not r.C:
+            raise CtdError(8, "no C held")
+        return device_columns(r.C, r.ldc, r.s_tilde, cols)
 
     def result(self, arrays=True, factors=False):
         """Scalars plus host copies of the index arrays (and factors if asked)."""
