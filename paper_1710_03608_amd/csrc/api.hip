@@ -109,15 +109,17 @@ ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout*
   return CTD_OK;
 }
 
-int64_t round4(int64_t x) { return (x + 3) & ~int64_t(3); }
+// Leading dimensions of Q, R and M are multiples of 8, so a lane's 32-byte
+// row segment (4 float64 or 8 float32 columns) never crosses a row end.
+int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
 // Plan the workspace of one CTD-S call (or one CTD-D slice) and bind pointers.
 ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
-                       bool want_C, StaticBufs* b) {
+                       bool want_C, int64_t max_cols, StaticBufs* b) {
   Arena& A = h->arena;
   A.reset();
   const int64_t n = std::max<int64_t>(nnz, 1);
-  const int64_t ld = round4(s);
+  const int64_t ld = round8(s);
   const int64_t nb = (int64_t)segment_blocks(nnz);
   struct Item { void** p; size_t bytes; };
   std::vector<Item> items;
@@ -151,7 +153,10 @@ ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bo
   add(&b->lev, n_rows * 8);
   add(&b->fiber_mark, n);
   add(&b->resid, n * 8);
-  add(&b->multi, n * 4);
+  const int64_t n_long = n / (kLongFiber + 1) + 1;
+  const int64_t long_ld = std::max<int64_t>(1, (std::max(max_cols, ld) + kChunkCols - 1) / kChunkCols);
+  add(&b->long_list, n_long * 4);
+  add(&b->long_part, n_long * long_ld * 8);
   add(&b->partial, ((n + 8191) / 8192 + 1) * 8);
   add(&b->Rs, n_rows * ld * 8);
   add(&b->C, want_C ? (size_t)ld * n * 8 : 8);
@@ -175,6 +180,7 @@ ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bo
   for (size_t i = 0; i < items.size(); ++i) *items[i].p = (void*)(A.base + offs[i]);
   b->ld = ld;
   b->s_max = s;
+  b->long_ld = long_ld;
   return CTD_OK;
 }
 
@@ -255,7 +261,9 @@ ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const fl
   pa.d_ncols = d_ncols;
   pa.ncols_max = ncols_max;
   pa.resid = b.resid;
-  pa.multi = b.multi;
+  pa.long_list = b.long_list;
+  pa.long_part = b.long_part;
+  pa.long_ld = b.long_ld;
   pa.partial = b.partial;
   pa.mixed = mixed;
   return pa;
@@ -274,7 +282,7 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   const int64_t nnz = X->nnz;
   const int64_t n_rows = lay.n_rows;
   StaticBufs& b = h->sb;
-  ctd_status rc = plan_static(h, nnz, s, n_rows, mixed, want_C, &b);
+  ctd_status rc = plan_static(h, nnz, s, n_rows, mixed, want_C, round8(s), &b);
   if (rc != CTD_OK) return rc;
   DevScalars* sc = h->d_sc;
   for (bool& u : h->ev_used) u = false;

@@ -13,6 +13,12 @@ constexpr int kWave = 64;
 
 // Scalars produced on the device and read back only by ctd_get_result /
 // ctd_sync, so a whole decomposition runs without host round trips.
+// Fibers with more than kLongFiber nonzeros are gathered by a workgroup of
+// kLongWaves waves per column chunk of kChunkCols (float64) columns.
+constexpr int kLongFiber = 64;
+constexpr int kLongWaves = 8;
+constexpr int kChunkCols = 256;
+
 struct DevScalars {
   uint64_t W;            // total integer sampling weight of the last input
   uint64_t vmax2_bits;   // bit pattern of the largest squared value (positive doubles order like u64)
@@ -29,6 +35,7 @@ struct DevScalars {
   int32_t n_accept_total;// accepted fibers held in R
   int32_t allow_empty;   // CTD-D: an all-zero slice is not an error
   int32_t base_accept;   // fibers kept before the current call
+  int32_t n_long;        // fibers listed for the workgroup-per-chunk gather
   int32_t blk_na;        // fibers kept by the current candidate block
   int32_t blk_reorth;    // the block's first Cholesky-QR pass left it non-orthonormal
 };

@@ -25,6 +25,7 @@
 
 #include <string>
 
+#include "gather.h"
 #include "state.h"
 
 namespace ctd {
@@ -52,44 +53,101 @@ __global__ void k_static_totals(DevScalars* sc) {
   sc->n_cols_total = sc->n_f;
 }
 
-// One wave per fiber f < n_f: out[(col0 + f) * ldo + k] = sum_e v_e M[r_e][k], k < ncols.
+// Columns of R^T X: out[(col0 + f) * ldo + k] = sum_e v_e A[r_e][k] for
+// k < ncols and every fiber f < n_f.  A wave takes 64 consecutive fibers and
+// walks those of up to kLongFiber nonzeros (rows and values loaded once into
+// lanes and broadcast, two nonzeros times two 256-column chunks in flight);
+// longer ones are listed for k_spmm_long.
 __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict__ fptr,
                                                       const int32_t* __restrict__ row,
                                                       const double* __restrict__ val,
-                                                      const DevScalars* sc,
-                                                      const double* __restrict__ M, int64_t ldm,
+                                                      DevScalars* sc,
+                                                      const double* __restrict__ A, int64_t lda,
                                                       const int32_t* d_ncols,
                                                       double* __restrict__ out, int64_t ldo,
-                                                      const int64_t* d_col0) {
+                                                      const int64_t* d_col0,
+                                                      int32_t* __restrict__ long_list) {
+  constexpr int VEC = 4, kCols = VEC * kWave;
   const int64_t n_f = sc->status == 0 ? sc->n_f : 0;
   const int64_t ncols = *d_ncols;
   const int64_t col0 = d_col0 ? *d_col0 : 0;
   const int lane = lane_id();
+  const uint64_t lt = lane == 0 ? 0ull : ((~0ull) >> (kWave - lane));
   const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
-  for (int64_t f = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; f < n_f; f += nwaves) {
-    const int32_t e0 = fptr[f], e1 = fptr[f + 1];
-    double* o = out + (col0 + f) * ldo;
-    for (int64_t c0 = 0; c0 < ncols; c0 += 4 * kWave) {
-      const int64_t c = c0 + 4 * lane;
-      double a[4] = {0, 0, 0, 0};
-      if (c < ncols) {
-        for (int32_t e = e0; e < e1; ++e) {
-          const double v = val[e];
-          const double* mr = M + (int64_t)row[e] * ldm + c;
-          const double2 x = *(const double2*)mr;
-          const double2 y = *(const double2*)(mr + 2);
-          a[0] += v * x.x;
-          a[1] += v * x.y;
-          a[2] += v * y.x;
-          a[3] += v * y.y;
+  for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * kWave; fb < n_f;
+       fb += nwaves * kWave) {
+    const int64_t fl = fb + lane;
+    int32_t len = 0;
+    if (fl < n_f) len = fptr[fl + 1] - fptr[fl];
+    const bool lng = len > kLongFiber;
+    const uint64_t ml = __ballot(lng);
+    if (ml) {
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(&sc->n_long, (int32_t)__popcll(ml));
+      base = __shfl(base, 0, kWave);
+      if (lng) long_list[base + __popcll(ml & lt)] = (int32_t)fl;
+    }
+    uint64_t todo = __ballot(len > 0 && !lng);
+    while (todo) {
+      const int i = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int64_t f = fb + i;
+      const int32_t e0 = fptr[f];
+      const int n = fptr[f + 1] - e0;
+      const int32_t rr = lane < n ? row[e0 + lane] : 0;
+      const double vv = lane < n ? val[e0 + lane] : 0.0;
+      double* o = out + (col0 + f) * ldo;
+      for (int64_t c0 = 0; c0 < ncols; c0 += 2 * kCols) {
+        const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
+        const bool ina = ca < ncols, inb = cb < ncols;
+        double acc0[VEC], acc1[VEC];
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) acc0[k] = acc1[k] = 0.0;
+        gather_batch<double, VEC>(rr, vv, n, A + (ina ? ca : 0), A + (inb ? cb : 0), ina, inb,
+                                  lda, acc0, acc1);
+#pragma unroll
+        for (int k = 0; k < VEC; ++k) {
+          if (ca + k < ncols) o[ca + k] = acc0[k];
+          if (cb + k < ncols) o[cb + k] = acc1[k];
         }
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (c + k < ncols) o[c + k] = a[k];
     }
   }
 }
+
+// Listed long fibers: workgroup (chunk, i) writes one 256-column chunk of
+// fiber i's column.
+__global__ __launch_bounds__(kLongWaves * kWave) void k_spmm_long(
+    const int32_t* __restrict__ fptr, const int32_t* __restrict__ row,
+    const double* __restrict__ val, const DevScalars* sc, const double* __restrict__ A,
+    int64_t lda, const int32_t* d_ncols, double* __restrict__ out, int64_t ldo,
+    const int64_t* d_col0, const int32_t* __restrict__ long_list) {
+  constexpr int VEC = 4, kCols = VEC * kWave;
+  __shared__ double red[kLongWaves * VEC * kWave];
+  if (sc->status != 0) return;
+  const int64_t n_long = sc->n_long;
+  const int64_t ncols = *d_ncols;
+  const int64_t col0 = d_col0 ? *d_col0 : 0;
+  const int64_t c0 = (int64_t)blockIdx.x * kCols;
+  if (c0 >= ncols) return;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int64_t c = c0 + (int64_t)VEC * lane;
+  const bool in = c < ncols;
+  for (int64_t i = blockIdx.y; i < n_long; i += gridDim.y) {
+    const int32_t f = long_list[i];
+    double z[VEC];
+    wg_gather_chunk<double, VEC>(row, val, fptr[f], fptr[f + 1], A + (in ? c : 0), in, lda, red,
+                                 z);
+    if (wv == 0) {
+      double* o = out + (col0 + f) * ldo;
+#pragma unroll
+      for (int k = 0; k < VEC; ++k)
+        if (c + k < ncols) o[c + k] = z[k];
+    }
+  }
+}
+
+__global__ void k_zero_long(DevScalars* sc) { sc->n_long = 0; }
 
 // Rows of ((dR^T R^(t)) U^(t)): Y[a][c] = sum_{c <= j < d} M[c][j] Wacc[a][j]
 // for c < d = d~_t (columns held before the slice); one wave per row c of M.
@@ -158,7 +216,24 @@ __global__ void k_finish_slice(DevScalars* sc) {
   sc->n_cols_total += sc->n_f;
 }
 
-int grid_for(int64_t work, int per = kBlock) {
+int grid_for(int64_t work, int per = kBlock);
+
+// C columns R^T X for the fibers of the current input (short and long paths).
+void launch_cols(hipStream_t st, const StaticBufs& b, int64_t nnz_max, DevScalars* sc,
+                 const double* A, int64_t lda, const int32_t* d_ncols, int64_t ncols_max,
+                 double* out, int64_t ldo, const int64_t* d_col0) {
+  hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
+  const int gm = std::max(1, std::min(4096, (int)((nnz_max + kBlock - 1) / kBlock)));
+  hipLaunchKernelGGL(k_spmm_cols, dim3(gm), dim3(kBlock), 0, st, b.fptr, b.row, b.val, sc, A, lda,
+                     d_ncols, out, ldo, d_col0, b.long_list);
+  const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
+  const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
+  const int nch = (int)std::max<int64_t>(1, (ncols_max + 4 * kWave - 1) / (4 * kWave));
+  hipLaunchKernelGGL(k_spmm_long, dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, b.fptr, b.row,
+                     b.val, sc, A, lda, d_ncols, out, ldo, d_col0, b.long_list);
+}
+
+int grid_for(int64_t work, int per) {
   return std::max(1, std::min(8192, div_up(std::max<int64_t>(work, 1), per)));
 }
 
@@ -174,7 +249,7 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
   DynState& S = h->dyn;
   const int64_t n_rows = h->n_rows;
   const bool mixed = h->opt.precision == CTD_PREC_MIXED;
-  capD = std::min<int64_t>(round4(capD), round4(n_rows));
+  capD = std::min<int64_t>(round8(capD), round8(n_rows));
   if (capD <= S.capD && capN <= S.capN) return CTD_OK;
   capD = std::max(capD, S.capD);
   capN = std::max(capN, S.capN);
@@ -265,8 +340,7 @@ void launch_static_totals(hipStream_t st, DevScalars* sc) {
 void launch_core_static(hipStream_t st, StaticBufs& b, int64_t n_rows, int64_t nnz_max,
                         DevScalars* sc) {
   (void)n_rows;
-  hipLaunchKernelGGL(k_spmm_cols, dim3(grid_for(nnz_max * kWave)), dim3(kBlock), 0, st, b.fptr,
-                     b.row, b.val, sc, b.Rs, b.ld, &sc->s_tilde, b.C, b.ld, nullptr);
+  launch_cols(st, b, nnz_max, sc, b.Rs, b.ld, &sc->s_tilde, b.ld, b.C, b.ld, nullptr);
 }
 
 ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X) {
@@ -439,7 +513,7 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
     }
   }
   StaticBufs& b = h->sb;
-  rc = plan_static(h, nnz, d, n_rows, mixed, false, &b);
+  rc = plan_static(h, nnz, d, n_rows, mixed, false, S.capD, &b);
   if (rc != CTD_OK) return rc;
   // per-slice workspace: block-filter scratch, kept W rows, cross rows
   const size_t ws_doubles = basis_scratch_doubles(n_rows, S.capD) + (size_t)2 * d * S.capD + 64;
@@ -506,9 +580,8 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
                        S.capD, Wacc, S.capD, Y, S.capD, sc);
     hipLaunchKernelGGL(k_cross_term, dim3(grid_for(S.n_cols_ub * kWave)), dim3(kBlock), 0, st,
                        S.C, S.capD, Y, S.capD, sc);
-    hipLaunchKernelGGL(k_spmm_cols, dim3(grid_for(nnz * kWave)), dim3(kBlock), 0, st, b.fptr,
-                       b.row, b.val, sc, S.Rs, S.capD, &sc->n_accept_total, S.C, S.capD,
-                       &sc->n_cols_total);
+    launch_cols(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total,
+                std::min<int64_t>(n_rows, S.d_ub + d), S.C, S.capD, &sc->n_cols_total);
     hipLaunchKernelGGL(k_append_ids, dim3(grid_for(nnz)), dim3(kBlock), 0, st, b.fid, &sc->n_f,
                        S.col_fid, nullptr, &sc->n_cols_total, t_off);
     mark(h, MARK_CORE);

@@ -127,7 +127,9 @@ struct ProjectArgs {
   const int32_t* d_ncols;  // device count of columns of Q
   int64_t ncols_max;
   double* resid;           // [n_f] out
-  int32_t* multi;          // [n_f] workspace: fibers with >= 2 nonzeros
+  int32_t* long_list;      // [nnz / (kLongFiber + 1) + 1] workspace: long fibers
+  double* long_part;       // [long_list size x long_ld] per-chunk ||z||^2 of long fibers
+  int64_t long_ld;         // column chunks held per long fiber
   double* partial;         // workspace
   bool mixed;
 };

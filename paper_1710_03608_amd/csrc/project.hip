@@ -12,6 +12,7 @@
 // ||z_f||^2 without ever being written.  Per-fiber residuals land in a
 // fiber-indexed array and are summed by a fixed reduction tree, so the
 // result is bit-identical from run to run.
+#include "gather.h"
 #include "kernels.h"
 
 namespace ctd {
@@ -21,52 +22,17 @@ constexpr int kBlock = 256;
 constexpr int kRedBlock = 1024;
 constexpr int kRedItems = 8;
 
-__device__ inline int32_t read_lane(int32_t v, int lane) {
-  return __builtin_amdgcn_readlane(v, lane);
-}
-template <typename T>
-__device__ inline T read_lane(T v, int lane) {
-  static_assert(sizeof(T) == 8 || sizeof(T) == 4, "float or double");
-  if constexpr (sizeof(T) == 8) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-  } else {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-  }
-}
-
-// VEC consecutive elements of a row of Q (32 B per lane: two 16 B loads).
-template <typename T, int VEC>
-__device__ inline void load_seg(const T* p, T (&x)[VEC]) {
-#pragma unroll
-  for (int k = 0; k < VEC; k += 16 / sizeof(T)) {
-    if constexpr (sizeof(T) == 8) {
-      const double2 u = *(const double2*)(p + k);
-      x[k] = u.x;
-      x[k + 1] = u.y;
-    } else {
-      const float4 u = *(const float4*)(p + k);
-      x[k] = u.x;
-      x[k + 1] = u.y;
-      x[k + 2] = u.z;
-      x[k + 3] = u.w;
-    }
-  }
-}
-
 // Residual of every fiber.  A wave takes 64 consecutive fibers, one per
-// lane.  Fibers with one nonzero v at row r are done lane-parallel from the
-// row leverage: ||Q^T x||^2 = v^2 ||Q_r||^2.  The wave then walks the others
-// one at a time: z_f = sum_e v_e Q[r_e, :], lane l holding columns
-// VEC l .. VEC l + VEC of each 64 VEC-column chunk.  The fiber's (row, value)
-// pairs are loaded once per 64 nonzeros into lanes and broadcast with
-// readlane, so the inner loop only issues row gathers: two nonzeros times two
-// column chunks (8 KB per wave) in flight per iteration.  Column chunks of z
-// are squared and summed as they complete; z is never written.  Kept fibers
-// lie in span(Q) and get 0.
+// lane.  Kept fibers lie in span(Q) and get 0.  Fibers with one nonzero v at
+// row r are done lane-parallel from the row leverage: ||Q^T x||^2 =
+// v^2 ||Q_r||^2.  Fibers of more than kLongFiber nonzeros are listed for
+// k_proj_long.  The wave walks the rest one at a time: z_f = sum_e v_e
+// Q[r_e, :], lane l holding columns VEC l .. VEC l + VEC of each 64 VEC-column
+// chunk, the fiber's (row, value) pairs loaded once into lanes and
+// broadcast, two nonzeros times two chunks of row gathers in flight.  Column
+// chunks of z are squared and summed as they complete; z is never written.
 template <typename T, int VEC>
-__global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, const DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars* sc) {
   constexpr int kCols = VEC * kWave;
   if (sc->status != 0) return;
   const int64_t n_f = sc->n_f;
@@ -75,10 +41,11 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, const DevS
   const T* Qb = sizeof(T) == 8 ? (const T*)a.Q : (const T*)a.Qf;
   const T* vals = sizeof(T) == 8 ? (const T*)a.val : (const T*)a.val32;
   const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  const uint64_t lt = lane == 0 ? 0ull : ((~0ull) >> (kWave - lane));
   for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * kWave; fb < n_f;
        fb += nwaves * kWave) {
     const int64_t fl = fb + lane;
-    bool multi = false;
+    bool multi = false, lng = false;
     if (fl < n_f) {
       const int32_t s0 = a.fptr[fl], s1 = a.fptr[fl + 1];
       const bool kept = a.fiber_mark && a.fiber_mark[fl];
@@ -89,9 +56,18 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, const DevS
         const double x2 = v * v;
         const double z2 = x2 * a.lev[a.row[s0]];
         a.resid[fl] = x2 - z2;
+      } else if (s1 - s0 > kLongFiber) {
+        lng = true;
       } else {
         multi = true;
       }
+    }
+    const uint64_t ml = __ballot(lng);
+    if (ml) {
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(&sc->n_long, (int32_t)__popcll(ml));
+      base = __shfl(base, 0, kWave);
+      if (lng) a.long_list[base + __popcll(ml & lt)] = (int32_t)fl;
     }
     uint64_t todo = __ballot(multi);
     while (todo) {
@@ -99,71 +75,89 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, const DevS
       todo &= todo - 1;
       const int64_t f = fb + i;
       const int32_t e0 = a.fptr[f], e1 = a.fptr[f + 1];
-      double x2 = 0.0, z2 = 0.0;
+      const int n = e1 - e0;
+      const int32_t rr = lane < n ? a.row[e0 + lane] : 0;
+      const T vv = lane < n ? vals[e0 + lane] : T(0);
+      const double v64 = lane < n ? a.val[e0 + lane] : 0.0;
+      double z2 = 0.0;
       for (int64_t c0 = 0; c0 < ncols; c0 += 2 * kCols) {
         const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
         const bool ina = ca < ncols, inb = cb < ncols;
-        const T* qa = Qb + (ina ? ca : 0);
-        const T* qb = Qb + (inb ? cb : 0);
         T acc0[VEC], acc1[VEC];
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < VEC; ++k) acc0[k] = acc1[k] = T(0);
-        for (int32_t eb = e0; eb < e1; eb += kWave) {
-          const int nb = min(kWave, e1 - eb);
-          const int32_t rr = lane < nb ? a.row[eb + lane] : 0;
-          const T vv = lane < nb ? vals[eb + lane] : T(0);
-          if (c0 == 0 && lane < nb) x2 += a.val[eb + lane] * a.val[eb + lane];
-          int k = 0;
-          for (; k + 1 < nb; k += 2) {
-            const int64_t r0 = read_lane(rr, k), r1 = read_lane(rr, k + 1);
-            const T v0 = read_lane(vv, k), v1 = read_lane(vv, k + 1);
-            T x0[VEC], x1[VEC], y0[VEC], y1[VEC];
-            if (ina) {
-              load_seg<T, VEC>(qa + r0 * a.ldq, x0);
-              load_seg<T, VEC>(qa + r1 * a.ldq, x1);
-            }
-            if (inb) {
-              load_seg<T, VEC>(qb + r0 * a.ldq, y0);
-              load_seg<T, VEC>(qb + r1 * a.ldq, y1);
-            }
-            if (ina) {
-  #pragma unroll
-              for (int j = 0; j < VEC; ++j) acc0[j] += v0 * x0[j] + v1 * x1[j];
-            }
-            if (inb) {
-  #pragma unroll
-              for (int j = 0; j < VEC; ++j) acc1[j] += v0 * y0[j] + v1 * y1[j];
-            }
-          }
-          if (k < nb) {
-            const int64_t r0 = read_lane(rr, k);
-            const T v0 = read_lane(vv, k);
-            T x0[VEC], y0[VEC];
-            if (ina) load_seg<T, VEC>(qa + r0 * a.ldq, x0);
-            if (inb) load_seg<T, VEC>(qb + r0 * a.ldq, y0);
-            if (ina) {
-  #pragma unroll
-              for (int j = 0; j < VEC; ++j) acc0[j] += v0 * x0[j];
-            }
-            if (inb) {
-  #pragma unroll
-              for (int j = 0; j < VEC; ++j) acc1[j] += v0 * y0[j];
-            }
-          }
-        }
-  #pragma unroll
+        gather_batch<T, VEC>(rr, vv, n, Qb + (ina ? ca : 0), Qb + (inb ? cb : 0), ina, inb,
+                             a.ldq, acc0, acc1);
+#pragma unroll
         for (int j = 0; j < VEC; ++j) {
           const double d0 = (double)acc0[j], d1 = (double)acc1[j];
           z2 += (ca + j < ncols) ? d0 * d0 : 0.0;
           z2 += (cb + j < ncols) ? d1 * d1 : 0.0;
         }
       }
-      x2 = wave_sum(x2);
+      const double x2 = wave_sum(v64 * v64);
       z2 = wave_sum(z2);
       if (lane == 0) a.resid[f] = x2 - z2;
     }
   }
 }
+
+// Long fibers: workgroup (chunk, i) forms z of listed fiber i over one
+// column chunk with all its waves and stores ||z_chunk||^2.
+template <typename T, int VEC>
+__global__ __launch_bounds__(kLongWaves * kWave) void k_proj_long(ProjectArgs a,
+                                                                  const DevScalars* sc) {
+  constexpr int kCols = VEC * kWave;
+  __shared__ double red[kLongWaves * VEC * kWave];
+  if (sc->status != 0) return;
+  const int64_t n_long = sc->n_long;
+  const int64_t ncols = *a.d_ncols;
+  const int64_t c0 = (int64_t)blockIdx.x * kCols;
+  if (c0 >= ncols) return;
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const T* Qb = sizeof(T) == 8 ? (const T*)a.Q : (const T*)a.Qf;
+  const T* vals = sizeof(T) == 8 ? (const T*)a.val : (const T*)a.val32;
+  const int64_t c = c0 + (int64_t)VEC * lane;
+  const bool in = c < ncols;
+  for (int64_t i = blockIdx.y; i < n_long; i += gridDim.y) {
+    const int32_t f = a.long_list[i];
+    double z[VEC];
+    wg_gather_chunk<T, VEC>(a.row, vals, a.fptr[f], a.fptr[f + 1], Qb + (in ? c : 0), in,
+                            a.ldq, red, z);
+    if (wv == 0) {
+      double z2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < VEC; ++j) z2 += (c + j < ncols) ? z[j] * z[j] : 0.0;
+      z2 = wave_sum(z2);
+      if (lane == 0) a.long_part[i * a.long_ld + blockIdx.x] = z2;
+    }
+  }
+}
+
+// resid of listed fiber i = ||x_f||^2 - sum over chunks (in chunk order); one wave each.
+__global__ __launch_bounds__(kBlock) void k_proj_long_fin(ProjectArgs a, const DevScalars* sc,
+                                                          int chunk_cols) {
+  if (sc->status != 0) return;
+  const int64_t n_long = sc->n_long;
+  const int64_t ncols = *a.d_ncols;
+  const int64_t nch = (ncols + chunk_cols - 1) / chunk_cols;
+  const int lane = lane_id();
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; i < n_long; i += nwaves) {
+    const int32_t f = a.long_list[i];
+    const int32_t e0 = a.fptr[f], e1 = a.fptr[f + 1];
+    double x2 = 0.0;
+    for (int32_t e = e0 + lane; e < e1; e += kWave) x2 += a.val[e] * a.val[e];
+    x2 = wave_sum(x2);
+    if (lane == 0) {
+      double z2 = 0.0;
+      for (int64_t ch = 0; ch < nch; ++ch) z2 += a.long_part[i * a.long_ld + ch];
+      a.resid[f] = x2 - z2;
+    }
+  }
+}
+
+__global__ void k_zero_long(DevScalars* sc) { sc->n_long = 0; }
 
 __global__ __launch_bounds__(kRedBlock) void k_reduce_partial(const double* __restrict__ x,
                                                               double* __restrict__ partial,
@@ -194,12 +188,24 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_final(const double* __rest
 
 void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,
                     hipEvent_t ev0, hipEvent_t ev1) {
+  hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
   const int gm = std::max(1, std::min(4096, div_up(nnz_max, kBlock)));
+  const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
+  const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
+  const int cols = a.mixed ? 8 * kWave : 4 * kWave;
+  const int nch = (int)std::max<int64_t>(1, div_up(a.ncols_max, cols));
   if (ev0) (void)hipEventRecord(ev0, st);
-  if (a.mixed)
+  if (a.mixed) {
     hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(gm), dim3(kBlock), 0, st, a, sc);
-  else
+    hipLaunchKernelGGL((k_proj_long<float, 8>), dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, a,
+                       sc);
+  } else {
     hipLaunchKernelGGL((k_proj_multi<double, 4>), dim3(gm), dim3(kBlock), 0, st, a, sc);
+    hipLaunchKernelGGL((k_proj_long<double, 4>), dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, a,
+                       sc);
+  }
+  hipLaunchKernelGGL(k_proj_long_fin, dim3(std::max(1, std::min(1024, (int)div_up(max_long * kWave, kBlock)))),
+                     dim3(kBlock), 0, st, a, sc, cols);
   if (ev1) (void)hipEventRecord(ev1, st);
   const int np = std::max(1, div_up(nnz_max, kRedBlock * kRedItems));
   hipLaunchKernelGGL(k_reduce_partial, dim3(np), dim3(kRedBlock), 0, st, a.resid, a.partial, sc);

@@ -50,7 +50,9 @@ struct StaticBufs {
   double* lev;
   uint8_t* fiber_mark;
   double* resid;
-  int32_t* multi;
+  int32_t* long_list;
+  double* long_part;
+  int64_t long_ld;
   double* partial;
   double* Rs;
   double* C;
@@ -113,12 +115,12 @@ enum { MARK_START = 0, MARK_SORTED = 1, MARK_SAMPLED = 2, MARK_PANEL = 3, MARK_B
        MARK_PROJ0 = 10, MARK_COUNT = 11 };
 void mark(ctd_handle* h, int i);
 int bits_for(uint64_t n);
-int64_t round4(int64_t x);
+int64_t round8(int64_t x);
 ctd_status fail(ctd_handle* h, ctd_status st, const std::string& msg);
 ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout* lay,
                      uint64_t* n_cols_total);
 ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
-                       bool want_C, StaticBufs* b);
+                       bool want_C, int64_t max_cols, StaticBufs* b);
 ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
                          uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b);
 int key_bits(const FiberLayout& lay);
