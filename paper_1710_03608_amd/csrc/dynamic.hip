@@ -171,31 +171,74 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 }
 
 // Cross term: C[d + a][f] = sum_{k<d} Y[a][k] C[k][f] for the columns held
-// before this slice; one wave per column, up to 8 new rows per pass.
-__global__ __launch_bounds__(kBlock) void k_cross_term(double* __restrict__ C, int64_t ldc,
-                                                       const double* __restrict__ Y, int64_t ldy,
-                                                       const DevScalars* sc) {
+// before this slice (the HBM-bound step of CTD-D: all of C^(t) is read).  A
+// workgroup owns 256 columns and streams them in chunks of 32 rows: 32
+// threads read one column's 256 contiguous bytes into LDS, the next chunk is
+// prefetched into registers meanwhile, and thread t accumulates the new rows
+// of column t from LDS.  Up to kCrossRows new rows per pass over C.
+constexpr int kCrossCols = 256, kCrossK = 32, kCrossRows = 16;
+__global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ C, int64_t ldc,
+                                                           const double* __restrict__ Y,
+                                                           int64_t ldy, const DevScalars* sc) {
+  __shared__ double Cs[kCrossCols][kCrossK + 1];
+  __shared__ __align__(16) double Ys[kCrossK][kCrossRows];   // [row k][new row a]
   const int64_t d = sc->base_accept;
   const int64_t na = sc->s_tilde;
   const int64_t ncols = sc->n_cols_total;
-  if (na == 0) return;
-  const int lane = lane_id();
-  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
-  for (int64_t f = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave; f < ncols; f += nwaves) {
-    double* col = C + f * ldc;
-    for (int64_t a0 = 0; a0 < na; a0 += 8) {
-      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int64_t k = lane; k < d; k += kWave) {
-        const double cv = col[k];
+  const int64_t f0 = (int64_t)blockIdx.x * kCrossCols;
+  if (na == 0 || f0 >= ncols || sc->status != 0) return;
+  const int t = threadIdx.x;
+  const int64_t nch = (d + kCrossK - 1) / kCrossK;
+  for (int64_t a0 = 0; a0 < na; a0 += kCrossRows) {
+    const int nr = (int)min<int64_t>(kCrossRows, na - a0);
+    double acc[kCrossRows];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (a0 + u < na) acc[u] += Y[(a0 + u) * ldy + k] * cv;
-      }
+    for (int u = 0; u < kCrossRows; ++u) acc[u] = 0.0;
+    // thread t loads rows k0 + t % 32 of columns f0 + t / 32 + 8 u (u < 32)
+    double pre[kCrossK];
+    const int64_t fcol = f0 + t / kCrossK;
+    const int rr = t % kCrossK;
+    const double* base = C + fcol * ldc + rr;
+    const int64_t stride = (int64_t)(kCrossCols / kCrossK) * ldc;
+    auto load = [&](int64_t ch) {
+      const int64_t k0 = ch * kCrossK;
+      const bool kin = ch < nch && k0 + rr < d;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double s = wave_sum(acc[u]);
-        if (lane == 0 && a0 + u < na) col[d + a0 + u] = s;
+      for (int u = 0; u < kCrossK; ++u) {
+        const bool in = kin && fcol + (kCrossCols / kCrossK) * u < ncols;
+        pre[u] = in ? base[k0 + u * stride] : 0.0;
       }
+    };
+    load(0);
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kCrossK; ++u) Cs[t / kCrossK + (kCrossCols / kCrossK) * u][rr] = pre[u];
+      for (int i = t; i < kCrossRows * kCrossK; i += kCrossCols) {
+        const int a = i / kCrossK, r = i % kCrossK;
+        const int64_t k = ch * kCrossK + r;
+        Ys[r][a] = (a < nr && k < d) ? Y[(a0 + a) * ldy + k] : 0.0;
+      }
+      __syncthreads();
+      load(ch + 1);
+#pragma unroll 4
+      for (int r = 0; r < kCrossK; ++r) {
+        const double cv = Cs[t][r];
+        const double2* yr = (const double2*)Ys[r];
+#pragma unroll
+        for (int u = 0; u < kCrossRows / 2; ++u) {
+          const double2 y = yr[u];
+          acc[2 * u] += y.x * cv;
+          acc[2 * u + 1] += y.y * cv;
+        }
+      }
+    }
+    const int64_t f = f0 + t;
+    if (f < ncols) {
+      double* col = C + f * ldc + d + a0;
+#pragma unroll
+      for (int u = 0; u < kCrossRows; ++u)
+        if (u < nr) col[u] = acc[u];
     }
   }
 }
@@ -578,7 +621,8 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
     // C: cross term over the columns held (Eq. 13), then the new columns R^(t+1)T dX
     hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave)), dim3(kBlock), 0, st, S.Xt,
                        S.capD, Wacc, S.capD, Y, S.capD, sc);
-    hipLaunchKernelGGL(k_cross_term, dim3(grid_for(S.n_cols_ub * kWave)), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL(k_cross_term, dim3(std::max<int64_t>(1, (S.n_cols_ub + 255) / 256)),
+                       dim3(256), 0, st,
                        S.C, S.capD, Y, S.capD, sc);
     launch_cols(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total,
                 std::min<int64_t>(n_rows, S.d_ub + d), S.C, S.capD, &sc->n_cols_total);
