@@ -181,3 +181,34 @@ def test_error_paths(lib):
         h.sync()
     finally:
         h.close()
+
+
+@pytest.fixture(scope="module")
+def planted():
+    """The planted rank-20 tensor at full size: 5000 x 5000 x 500, 2M nonzeros of
+    dyadic factor products (exact in float32 and float64) plus 1% sparse noise at 1%
+    of the Frobenius norm; s = 500."""
+    return synth.planted_low_rank()
+
+
+def test_planted_rank20_full_size_exact(lib, planted):
+    _, clean = planted
+    g = run_gpu(lib, clean, 0, 500, 0)
+    assert g["s_tilde"] == 20
+    assert g["rel_err"] <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_planted_rank20_full_size_noisy(lib, planted, precision):
+    noisy, clean = planted
+    o = ora.ctd_s(noisy.dims, noisy.idx, noisy.val, 0, 500, 0)
+    g = run_gpu(lib, noisy, 0, 500, 0, precision=precision)
+    if precision == "fp64":
+        check_parity(g, o)
+    else:
+        assert np.array_equal(g["accepted"], o.accepted.astype(np.uint64))
+        assert abs(g["rel_err"] - o.rel_err) <= RTOL_MIXED * o.rel_err + 1e-8
+    # noise-floor sanity: the 20 planted directions are recovered, so what is left is
+    # at most the noise (plus what the noise contributes to the kept fibers)
+    noise2 = float(np.sum(noisy.val ** 2)) - float(np.sum(clean.val ** 2))
+    assert g["rel_err"] <= 1.5 * abs(noise2) / float(np.sum(noisy.val ** 2))
