@@ -74,7 +74,10 @@ def time_mode(ctd, dims, idx, val, precision, steps, warmup):
 STREAM_S, STREAM_D = 800, 8
 
 
-def time_stream(ctd, st, precision):
+STREAM_BATCH = 8
+
+
+def time_stream(ctd, st, precision, batch=1):
     """CTD-D over the whole stream: the initial CTD-S (s = 800) and then every slice
     (d = 8), slices resident on the device.  One untimed pass, then a timed one; the
     timed region is the slice updates (the initial decomposition is reported apart)."""
@@ -89,8 +92,12 @@ def time_stream(ctd, st, precision):
         h.decompose(dims0, idx0, val0, 0, STREAM_S, SEED)
         h.sync()
         t1 = time.perf_counter()
-        for sd, si, sv in slices:
-            h.update(sd, si, sv, STREAM_D)
+        if batch == 1:
+            for sd, si, sv in slices:
+                h.update(sd, si, sv, STREAM_D)
+        else:
+            for i in range(0, len(slices), batch):
+                h.update_batched(slices[i:i + batch], STREAM_D)
         h.sync()
         t2 = time.perf_counter()
         r = h.result(arrays=False)
@@ -185,13 +192,16 @@ def main():
         stream_line = {"workload": "ctd_d_stream_4000x4000x200_nnz1000000_zipf1.1_200slices_s800_d8",
                        "slices": len(st.slices), "slice_nnz": slice_nnz, "modes": {}}
         for mode in args.modes.split(","):
-            log(f"CTD-D stream, {mode}")
-            r = time_stream(ctd, st, mode)
-            r["slice_nnz_per_s"] = slice_nnz / (r["slices_ms"] * 1e-3)
-            r["slices_per_s"] = len(st.slices) / (r["slices_ms"] * 1e-3)
-            stream_line["modes"][mode] = r
-            log(f"  {mode}: initial {r['initial_ms']:.1f} ms, 200 slices {r['slices_ms']:.1f} ms, "
-                f"{r['slice_nnz_per_s']:.3e} nnz/s, rel_err {r['rel_err']:.6f}")
+            for batch in (1, STREAM_BATCH):
+                key = mode if batch == 1 else f"{mode}_batch{batch}"
+                log(f"CTD-D stream, {key}")
+                r = time_stream(ctd, st, mode, batch)
+                r["batch"] = batch
+                r["slice_nnz_per_s"] = slice_nnz / (r["slices_ms"] * 1e-3)
+                r["slices_per_s"] = len(st.slices) / (r["slices_ms"] * 1e-3)
+                stream_line["modes"][key] = r
+                log(f"  {key}: initial {r['initial_ms']:.1f} ms, 200 slices {r['slices_ms']:.1f} ms, "
+                    f"{r['slice_nnz_per_s']:.3e} nnz/s, rel_err {r['rel_err']:.6f}")
         del st
         if args.stream_only:
             print(json.dumps({"ctd_d_stream": stream_line}), flush=True)

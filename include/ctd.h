@@ -90,7 +90,7 @@ enum {
   CTD_STAGE_BASIS = 3,      /* independence filter and orthonormal basis */
   CTD_STAGE_PROJECT = 4,    /* projection of all nonzeros and the residual (Eq. 14) */
   CTD_STAGE_SPMM = 5,       /* the multi-nonzero fiber SpMM kernel alone (inside PROJECT) */
-  CTD_STAGE_CORE = 6,       /* C: CTD-S core if want_C; CTD-D cross term and new columns */
+  CTD_STAGE_CORE = 6,       /* C: CTD-S core if want_C; CTD-D: the cross-term passes after the slices */
   CTD_STAGE_TOTAL = 7,
   CTD_N_STAGES = 8
 };
@@ -155,6 +155,17 @@ ctd_status ctd_decompose_given(ctd_handle* h, const ctd_coo* X, int32_t mode,
  * Requires a prior ctd_decompose with want_C set and a non-time mode. */
 ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d);
 
+/* CTD-D on B consecutive slices (Algorithm 2 applied B times in order): the
+ * results equal B calls of ctd_update up to rounding.  `slices` is a host
+ * array of B slice descriptors (each as for ctd_update; their device arrays
+ * must stay valid until the stream passes the call).  Slice b draws with
+ * Philox step word t + 1 + b.  The rows of C for the fibers the batch keeps
+ * are formed after the batch: over the columns held before it in one pass
+ * over C (the projector onto the grown span leaves the earlier
+ * reconstructions unchanged, Eqs. 8-13), so C is streamed once per batch
+ * instead of once per slice.  1 <= B <= CTD_MAX_BATCH. */
+ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B, int64_t d);
+
 /* Wait for the stream and return the latched device status. */
 ctd_status ctd_sync(ctd_handle* h);
 
@@ -169,6 +180,7 @@ void ctd_destroy(ctd_handle* h);
 /* Limits of this build. */
 #define CTD_MAX_ORDER 8
 #define CTD_MAX_DRAWS 16384
+#define CTD_MAX_BATCH 256
 
 #ifdef __cplusplus
 }

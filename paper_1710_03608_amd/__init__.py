@@ -20,8 +20,8 @@ CTD_PREC_FP64, CTD_PREC_MIXED = 0, 1
 STATUS = {0: "CTD_OK", 1: "CTD_ERR_INVALID_ARG", 2: "CTD_ERR_EMPTY", 3: "CTD_ERR_INDEX_OOB",
           4: "CTD_ERR_DUPLICATE", 5: "CTD_ERR_NONFINITE", 6: "CTD_ERR_OOM", 7: "CTD_ERR_HIP",
           8: "CTD_ERR_STATE", 9: "CTD_ERR_CAPACITY"}
-EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update", "ctd_sync",
-           "ctd_get_result", "ctd_last_error", "ctd_destroy")
+EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
+           "ctd_update_batched", "ctd_sync", "ctd_get_result", "ctd_last_error", "ctd_destroy")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -73,14 +73,15 @@ def load_library():
     lib.ctd_decompose_given.argtypes = [c_vp, ctypes.POINTER(CooStruct), c_i32,
                                         ctypes.POINTER(c_u64), c_i64]
     lib.ctd_update.argtypes = [c_vp, ctypes.POINTER(CooStruct), c_i64]
+    lib.ctd_update_batched.argtypes = [c_vp, ctypes.POINTER(CooStruct), c_i32, c_i64]
     lib.ctd_sync.argtypes = [c_vp]
     lib.ctd_get_result.argtypes = [c_vp, ctypes.POINTER(ResultStruct)]
     lib.ctd_last_error.argtypes = [c_vp]
     lib.ctd_last_error.restype = ctypes.c_char_p
     lib.ctd_destroy.argtypes = [c_vp]
     lib.ctd_destroy.restype = None
-    for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update", "ctd_sync",
-                 "ctd_get_result"):
+    for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
+                 "ctd_update_batched", "ctd_sync", "ctd_get_result"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -202,6 +203,14 @@ class Ctd:
         coo = Coo(dims, idx, val)
         self._keep.append(coo)
         self._check(self.lib.ctd_update(self.h, ctypes.byref(coo.struct), int(d)))
+
+    def update_batched(self, slices, d):
+        """CTD-D on consecutive slices [(dims, idx, val), ...] in one call."""
+        coos = [Coo(dims, idx, val) for dims, idx, val in slices]
+        self._keep.extend(coos)
+        arr = (CooStruct * len(coos))(*[c.struct for c in coos])
+        self._keep.append(arr)
+        self._check(self.lib.ctd_update_batched(self.h, arr, len(coos), int(d)))
 
     def sync(self):
         self._check(self.lib.ctd_sync(self.h))

@@ -907,7 +907,7 @@ __global__ void k_blk_finish(const int32_t* __restrict__ pos, int64_t b0,
                              DevScalars* sc) {
   const int64_t k = sc->n_accept_total;
   const int na = sc->blk_na;
-  const int64_t base = k - sc->base_accept;   // kept so far in this call
+  const int64_t base = k - sc->wacc_base;     // row of the first new fiber in Wacc
   for (int a = threadIdx.x; a < na; a += blockDim.x) {
     const int64_t b = b0 + pos[a];
     acc_fid[k + a] = uniq_fid[b] + id_offset;

@@ -35,6 +35,7 @@ struct DevScalars {
   int32_t n_accept_total;// accepted fibers held in R
   int32_t allow_empty;   // CTD-D: an all-zero slice is not an error
   int32_t base_accept;   // fibers kept before the current call
+  int32_t wacc_base;     // CTD-D: fibers kept before the current batch of slices
   int32_t n_long;        // fibers listed for the workgroup-per-chunk gather
   int32_t blk_na;        // fibers kept by the current candidate block
   int32_t blk_reorth;    // the block's first Cholesky-QR pass left it non-orthonormal

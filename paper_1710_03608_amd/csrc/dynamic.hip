@@ -24,6 +24,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "gather.h"
 #include "state.h"
@@ -33,16 +34,33 @@ namespace ctd {
 namespace {
 constexpr int kBlock = 256;
 
+// Clear the per-call scalars.  With keep_stream the stream totals, the basis
+// size, the column count and the batch base stay in place: they are neither
+// read nor written here.  (A copy-then-restore would read fields through the
+// scalar cache and overwrite the same bytes with vector stores; the two are
+// not ordered, so the restore could pick up the zeros.)
 __global__ void k_reset(DevScalars* sc, bool keep_stream) {
   if (threadIdx.x != 0) return;
-  DevScalars old = *sc;
-  *sc = DevScalars{};
-  if (keep_stream) {
-    sc->total_norm2 = old.total_norm2;
-    sc->total_err2 = old.total_err2;
-    sc->n_accept_total = old.n_accept_total;
-    sc->n_cols_total = old.n_cols_total;
-    sc->allow_empty = 1;
+  sc->W = 0;
+  sc->vmax2_bits = 0;
+  sc->norm2 = 0.0;
+  sc->err2 = 0.0;
+  sc->status = 0;
+  sc->sigma = 0;
+  sc->n_f = 0;
+  sc->s_unique = 0;
+  sc->s_tilde = 0;
+  sc->base_accept = 0;
+  sc->n_long = 0;
+  sc->blk_na = 0;
+  sc->blk_reorth = 0;
+  sc->allow_empty = keep_stream ? 1 : 0;
+  if (!keep_stream) {
+    sc->total_norm2 = 0.0;
+    sc->total_err2 = 0.0;
+    sc->n_cols_total = 0;
+    sc->n_accept_total = 0;
+    sc->wacc_base = 0;
   }
 }
 
@@ -149,29 +167,66 @@ __global__ __launch_bounds__(kLongWaves * kWave) void k_spmm_long(
 
 __global__ void k_zero_long(DevScalars* sc) { sc->n_long = 0; }
 
-// Rows of ((dR^T R^(t)) U^(t)): Y[a][c] = sum_{c <= j < d} M[c][j] Wacc[a][j]
-// for c < d = d~_t (columns held before the slice); one wave per row c of M.
+// Batch bookkeeping.  info[2 b], info[2 b + 1]: fibers kept and columns held
+// when slice b of the batch starts (b = B: when the batch ends).
+__global__ void k_batch_mark(const DevScalars* sc, int64_t* info, int b) {
+  info[2 * b] = sc->n_accept_total;
+  info[2 * b + 1] = sc->n_cols_total;
+}
+__global__ void k_batch_begin(DevScalars* sc) { sc->wacc_base = sc->n_accept_total; }
+
+// Range of cross pass p (Eq. 13 over a batch of B slices): the fibers kept by
+// the batch that were not yet held when the columns were added get their rows
+// ((dR^T R) U) C over those columns, with R, U truncated to the rank K the
+// columns were created with.  Pass 0: columns held before the batch, K = the
+// rank at the batch start (one pass over C^(t) for all B slices, since
+// P_{t+b} P_t = P_t).  Pass b + 1: the columns of slice b, K = the rank after
+// slice b, rows of the fibers kept by later slices.  rng = {K, a_lo, na, c_lo,
+// c_hi}: rows a_lo .. a_lo + na of the batch's Wacc, C rows K .. K + na.
+__global__ void k_cross_setup(const int64_t* info, int B, int p, const DevScalars* sc,
+                              int64_t* rng) {
+  const int64_t base = info[0], total = info[2 * B] - base;
+  int64_t K, c_lo, c_hi;
+  if (p == 0) {
+    K = info[0];
+    c_lo = 0;
+    c_hi = info[1];
+  } else {
+    const int b = p - 1;
+    K = info[2 * (b + 1)];
+    c_lo = info[2 * b + 1];
+    c_hi = info[2 * (b + 1) + 1];
+  }
+  const int64_t a_lo = K - base;
+  rng[0] = K;
+  rng[1] = a_lo;
+  rng[2] = sc->status == 0 ? total - a_lo : 0;
+  rng[3] = c_lo;
+  rng[4] = c_hi;
+}
+
+// Rows of ((dR^T R) U): Y[a][c] = sum_{c <= j < K} M[c][j] Wacc[a_lo + a][j]
+// for c < K (with w = Q^T x the row x^T R U equals (M w)^T); one wave per c.
 __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict__ M, int64_t ldm,
                                                        const double* __restrict__ Wacc,
                                                        int64_t ldw, double* __restrict__ Y,
-                                                       int64_t ldy, const DevScalars* sc) {
-  const int64_t d = sc->base_accept;
-  const int64_t na = sc->s_tilde;
+                                                       int64_t ldy, const int64_t* rng) {
+  const int64_t K = rng[0], a_lo = rng[1], na = rng[2];
   const int lane = lane_id();
   const int64_t c = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  if (c >= d) return;
+  if (c >= K || na <= 0) return;
   const double* mr = M + c * ldm;
   for (int64_t a = 0; a < na; ++a) {
-    const double* w = Wacc + a * ldw;
+    const double* w = Wacc + (a_lo + a) * ldw;
     double s = 0.0;
-    for (int64_t j = c + lane; j < d; j += kWave) s += mr[j] * w[j];
+    for (int64_t j = c + lane; j < K; j += kWave) s += mr[j] * w[j];
     s = wave_sum(s);
     if (lane == 0) Y[a * ldy + c] = s;
   }
 }
 
-// Cross term: C[d + a][f] = sum_{k<d} Y[a][k] C[k][f] for the columns held
-// before this slice (the HBM-bound step of CTD-D: all of C^(t) is read).  A
+// Cross term: C[d + a][f] = sum_{k<d} Y[a][k] C[k][f] for f in [c_lo, c_hi)
+// (d = K of the pass; pass 0 reads all of C^(t): the HBM-bound step).  A
 // workgroup owns 256 columns and streams them in chunks of 32 rows: 32
 // threads read one column's 256 contiguous bytes into LDS, the next chunk is
 // prefetched into registers meanwhile, and thread t accumulates the new rows
@@ -179,14 +234,12 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 constexpr int kCrossCols = 256, kCrossK = 32, kCrossRows = 16;
 __global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ C, int64_t ldc,
                                                            const double* __restrict__ Y,
-                                                           int64_t ldy, const DevScalars* sc) {
+                                                           int64_t ldy, const int64_t* rng) {
   __shared__ double Cs[kCrossCols][kCrossK + 1];
   __shared__ __align__(16) double Ys[kCrossK][kCrossRows];   // [row k][new row a]
-  const int64_t d = sc->base_accept;
-  const int64_t na = sc->s_tilde;
-  const int64_t ncols = sc->n_cols_total;
-  const int64_t f0 = (int64_t)blockIdx.x * kCrossCols;
-  if (na == 0 || f0 >= ncols || sc->status != 0) return;
+  const int64_t d = rng[0], na = rng[2], ncols = rng[4];
+  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
+  if (na <= 0 || f0 >= ncols) return;
   const int t = threadIdx.x;
   const int64_t nch = (d + kCrossK - 1) / kCrossK;
   for (int64_t a0 = 0; a0 < na; a0 += kCrossRows) {
@@ -460,7 +513,7 @@ void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out) {
     out->stage_ms[CTD_STAGE_PROJECT] = span(MARK_PROJ0, MARK_PROJECTED);
     out->stage_ms[CTD_STAGE_SPMM] = span(MARK_SPMM0, MARK_SPMM1);
     out->stage_ms[CTD_STAGE_CORE] =
-        h->last_was_update ? span(MARK_BASIS, MARK_CORE) : span(MARK_PROJECTED, MARK_CORE);
+        h->last_was_update ? span(MARK_CROSS0, MARK_CORE) : span(MARK_PROJECTED, MARK_CORE);
     out->stage_ms[CTD_STAGE_TOTAL] = span(MARK_START, MARK_END);
   }
   out->s = h->s;
@@ -515,40 +568,47 @@ void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out) {
 
 using namespace ctd;
 
-extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d) {
+extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B,
+                                         int64_t d) {
   if (!h) return CTD_ERR_INVALID_ARG;
   h->last_error.clear();
   (void)hipGetLastError();
   if (h->failed) return fail(h, CTD_ERR_STATE, "handle is in a failed state; call ctd_decompose");
   if (!h->dyn_ready)
     return fail(h, CTD_ERR_STATE, "ctd_update needs a prior ctd_decompose with want_C on a non-time mode");
+  if (B < 1 || B > CTD_MAX_BATCH || !slices)
+    return fail(h, CTD_ERR_INVALID_ARG, "B must be in [1, CTD_MAX_BATCH]");
   const FiberLayout& full = h->layout;
-  if (!slice || slice->order != full.order)
-    return fail(h, CTD_ERR_STATE, "slice order differs from the stream's");
-  for (int m = 0; m < full.order - 1; ++m)
-    if (slice->dims[m] != full.dims[m]) return fail(h, CTD_ERR_STATE, "slice dims differ from the stream's");
-  if (slice->dims[full.order - 1] != 1) return fail(h, CTD_ERR_STATE, "slice time dim must be 1");
-  FiberLayout lay{};
-  uint64_t ncols = 0;
-  ctd_status rc = check_coo(h, slice, full.mode, &lay, &ncols);
-  if (rc != CTD_OK) return rc;
-  if (d < 1 || (uint64_t)d > ncols) return fail(h, CTD_ERR_INVALID_ARG, "d must be in [1, dN_alpha]");
+  std::vector<FiberLayout> lays(B);
+  int64_t nnz_max = 0, nnz_sum = 0;
+  for (int b = 0; b < B; ++b) {
+    const ctd_coo* slice = &slices[b];
+    if (slice->order != full.order) return fail(h, CTD_ERR_STATE, "slice order differs from the stream's");
+    for (int m = 0; m < full.order - 1; ++m)
+      if (slice->dims[m] != full.dims[m]) return fail(h, CTD_ERR_STATE, "slice dims differ from the stream's");
+    if (slice->dims[full.order - 1] != 1) return fail(h, CTD_ERR_STATE, "slice time dim must be 1");
+    uint64_t ncols = 0;
+    ctd_status rc = check_coo(h, slice, full.mode, &lays[b], &ncols);
+    if (rc != CTD_OK) return rc;
+    if (d < 1 || (uint64_t)d > ncols) return fail(h, CTD_ERR_INVALID_ARG, "d must be in [1, dN_alpha]");
+    nnz_max = std::max<int64_t>(nnz_max, slice->nnz);
+    nnz_sum += slice->nnz;
+  }
   if (d > CTD_MAX_DRAWS) return fail(h, CTD_ERR_CAPACITY, "d above CTD_MAX_DRAWS");
+  ctd_status rc = CTD_OK;
   hipStream_t st = h->stream;
   DynState& S = h->dyn;
-  const int64_t nnz = slice->nnz;
   const int64_t n_rows = h->n_rows;
   const bool mixed = h->opt.precision == CTD_PREC_MIXED;
-  const uint32_t step = (uint32_t)(h->step + 1);
   DevScalars* sc = h->d_sc;
   // capacities (host upper bounds; exact sizes only at a sync)
-  const int64_t need_d = std::min<int64_t>(n_rows, S.d_ub + d);
-  const int64_t need_n = S.n_cols_ub + nnz;
+  const int64_t need_d = std::min<int64_t>(n_rows, S.d_ub + (int64_t)B * d);
+  const int64_t need_n = S.n_cols_ub + nnz_sum;
   if (need_d > S.capD || need_n > S.capN) {
     rc = dyn_sync_sizes(h);
     if (rc != CTD_OK) return rc;
-    const int64_t nd = std::min<int64_t>(n_rows, S.d_tilde + d);
-    const int64_t nn = S.n_cols + nnz;
+    const int64_t nd = std::min<int64_t>(n_rows, S.d_tilde + (int64_t)B * d);
+    const int64_t nn = S.n_cols + nnz_sum;
     if (nd > S.capD || nn > S.capN) {
       rc = dyn_reserve(h, nd > S.capD ? std::max(nd, 2 * S.capD) : S.capD,
                        nn > S.capN ? std::max(nn, S.capN + S.capN / 2) : S.capN);
@@ -556,10 +616,13 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
     }
   }
   StaticBufs& b = h->sb;
-  rc = plan_static(h, nnz, d, n_rows, mixed, false, S.capD, &b);
+  rc = plan_static(h, nnz_max, d, n_rows, mixed, false, S.capD, &b);
   if (rc != CTD_OK) return rc;
-  // per-slice workspace: block-filter scratch, kept W rows, cross rows
-  const size_t ws_doubles = basis_scratch_doubles(n_rows, S.capD) + (size_t)2 * d * S.capD + 64;
+  // workspace: block-filter scratch, W rows of the batch's kept fibers, cross
+  // rows, slice records and pass ranges
+  const int64_t kept_max = std::min<int64_t>(n_rows, (int64_t)B * d);
+  const size_t ws_doubles = basis_scratch_doubles(n_rows, S.capD) +
+                            (size_t)2 * kept_max * S.capD + (size_t)2 * (B + 1) + 8 + 64;
   if (ws_doubles * 8 > S.ws_bytes) {
     if (S.ws) {
       HIP_CHECK(h, hipStreamSynchronize(st));
@@ -575,80 +638,105 @@ extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d)
   }
   double* scratch = (double*)S.ws;
   double* Wacc = scratch + basis_scratch_doubles(n_rows, S.capD);
-  double* Y = Wacc + (size_t)d * S.capD;
+  double* Y = Wacc + (size_t)kept_max * S.capD;
+  int64_t* info = (int64_t*)(Y + (size_t)kept_max * S.capD);
+  int64_t* rng = info + 2 * (B + 1);
 
   for (bool& u : h->ev_used) u = false;
   mark(h, MARK_START);
-  launch_reset_scalars(st, sc, true);
-  const uint64_t t_off = (uint64_t)S.T * (uint64_t)S.dN;
-  if (nnz > 0) {
-    rc = enqueue_input(h, slice, lay, d, h->seed, step, nullptr, b);
-    if (rc != CTD_OK) return rc;
-    // candidates against R^(t) and each other; kept ones extend R, Q, M
-    launch_panel(st, b.uniq_fi, d, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
-    mark(h, MARK_PANEL);
-    BasisArgs ba{};
-    ba.P = b.P;
-    ba.ldp = b.ld;
-    ba.n_rows = n_rows;
-    ba.s_max = d;
-    ba.uniq_fi = b.uniq_fi;
-    ba.uniq_fid = b.uniq_fid;
-    ba.fptr = b.fptr;
-    ba.row = b.row;
-    ba.val = b.val;
-    ba.Q = S.Q;
-    ba.ldq = S.capD;
-    ba.Qf = mixed ? S.Qf : nullptr;
-    ba.R = S.Rs;
-    ba.ldr = S.capD;
-    ba.M = S.Xt;
-    ba.ldm = S.capD;
-    ba.lev = S.lev;
-    ba.lev_accumulate = true;
-    ba.eps2 = h->opt.eps * h->opt.eps;
-    ba.accept = b.accept;
-    ba.acc_fid = S.acc_fid;
-    ba.acc_fi_local = nullptr;
-    ba.fiber_mark = b.fiber_mark;
-    ba.id_offset = t_off;
-    ba.Wacc = Wacc;
-    ba.ldwa = S.capD;
-    ba.scratch = scratch;
-    ba.cap = S.capD;
-    launch_basis(st, ba, sc);
-    mark(h, MARK_BASIS);
-    // C: cross term over the columns held (Eq. 13), then the new columns R^(t+1)T dX
-    hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave)), dim3(kBlock), 0, st, S.Xt,
-                       S.capD, Wacc, S.capD, Y, S.capD, sc);
-    hipLaunchKernelGGL(k_cross_term, dim3(std::max<int64_t>(1, (S.n_cols_ub + 255) / 256)),
-                       dim3(256), 0, st,
-                       S.C, S.capD, Y, S.capD, sc);
-    launch_cols(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total,
-                std::min<int64_t>(n_rows, S.d_ub + d), S.C, S.capD, &sc->n_cols_total);
-    hipLaunchKernelGGL(k_append_ids, dim3(grid_for(nnz)), dim3(kBlock), 0, st, b.fid, &sc->n_f,
-                       S.col_fid, nullptr, &sc->n_cols_total, t_off);
-    mark(h, MARK_CORE);
-    // slice residual against the grown basis
-    ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total,
-                                  std::min<int64_t>(n_rows, S.d_ub + d));
-    if (h->opt.profile) {
-      mark(h, MARK_PROJ0);
-      mark(h, MARK_SPMM0);
-      mark(h, MARK_SPMM1);
+  int64_t d_ub = S.d_ub;
+  for (int bi = 0; bi < B; ++bi) {
+    const ctd_coo* slice = &slices[bi];
+    const int64_t nnz = slice->nnz;
+    const uint32_t step = (uint32_t)(h->step + 1 + bi);
+    launch_reset_scalars(st, sc, true);
+    if (bi == 0) hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, st, sc);
+    hipLaunchKernelGGL(k_batch_mark, dim3(1), dim3(1), 0, st, sc, info, bi);
+    const uint64_t t_off = (uint64_t)(S.T + bi) * (uint64_t)S.dN;
+    const int64_t d_next = std::min<int64_t>(n_rows, d_ub + d);
+    if (nnz > 0) {
+      rc = enqueue_input(h, slice, lays[bi], d, h->seed, step, nullptr, b);
+      if (rc != CTD_OK) return rc;
+      // candidates against R^(t) and each other; kept ones extend R, Q, M
+      launch_panel(st, b.uniq_fi, d, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
+      mark(h, MARK_PANEL);
+      BasisArgs ba{};
+      ba.P = b.P;
+      ba.ldp = b.ld;
+      ba.n_rows = n_rows;
+      ba.s_max = d;
+      ba.uniq_fi = b.uniq_fi;
+      ba.uniq_fid = b.uniq_fid;
+      ba.fptr = b.fptr;
+      ba.row = b.row;
+      ba.val = b.val;
+      ba.Q = S.Q;
+      ba.ldq = S.capD;
+      ba.Qf = mixed ? S.Qf : nullptr;
+      ba.R = S.Rs;
+      ba.ldr = S.capD;
+      ba.M = S.Xt;
+      ba.ldm = S.capD;
+      ba.lev = S.lev;
+      ba.lev_accumulate = true;
+      ba.eps2 = h->opt.eps * h->opt.eps;
+      ba.accept = b.accept;
+      ba.acc_fid = S.acc_fid;
+      ba.acc_fi_local = nullptr;
+      ba.fiber_mark = b.fiber_mark;
+      ba.id_offset = t_off;
+      ba.Wacc = Wacc;
+      ba.ldwa = S.capD;
+      ba.scratch = scratch;
+      ba.cap = S.capD;
+      launch_basis(st, ba, sc);
+      mark(h, MARK_BASIS);
+      // the slice's own columns R^(t+1)T dX (rows held after its filter)
+      launch_cols(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total, d_next, S.C, S.capD,
+                  &sc->n_cols_total);
+      hipLaunchKernelGGL(k_append_ids, dim3(grid_for(nnz)), dim3(kBlock), 0, st, b.fid, &sc->n_f,
+                         S.col_fid, nullptr, &sc->n_cols_total, t_off);
+      // slice residual against the grown basis
+      ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total, d_next);
+      if (h->opt.profile) {
+        mark(h, MARK_PROJ0);
+        mark(h, MARK_SPMM0);
+        mark(h, MARK_SPMM1);
+      }
+      launch_project(st, pa, nnz, sc, h->opt.profile ? h->ev[MARK_SPMM0] : nullptr,
+                     h->opt.profile ? h->ev[MARK_SPMM1] : nullptr);
+      mark(h, MARK_PROJECTED);
     }
-    launch_project(st, pa, nnz, sc, h->opt.profile ? h->ev[MARK_SPMM0] : nullptr,
-                   h->opt.profile ? h->ev[MARK_SPMM1] : nullptr);
-    mark(h, MARK_PROJECTED);
+    hipLaunchKernelGGL(k_finish_slice, dim3(1), dim3(1), 0, st, sc);
+    d_ub = d_next;
   }
-  hipLaunchKernelGGL(k_finish_slice, dim3(1), dim3(1), 0, st, sc);
+  hipLaunchKernelGGL(k_batch_mark, dim3(1), dim3(1), 0, st, sc, info, B);
+  // C rows of the batch's kept fibers (Eq. 13): pass 0 over the columns held
+  // before the batch, pass b + 1 over the columns of slice b
+  mark(h, MARK_CROSS0);
+  for (int p = 0; p < B; ++p) {
+    const int64_t cols_ub = p == 0 ? S.n_cols_ub : slices[p - 1].nnz;
+    if (cols_ub == 0) continue;
+    hipLaunchKernelGGL(k_cross_setup, dim3(1), dim3(1), 0, st, info, B, p, sc, rng);
+    hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave)), dim3(kBlock), 0, st, S.Xt,
+                       S.capD, Wacc, S.capD, Y, S.capD, rng);
+    hipLaunchKernelGGL(k_cross_term, dim3(std::max<int64_t>(1, (cols_ub + kCrossCols - 1) / kCrossCols)),
+                       dim3(kCrossCols), 0, st, S.C, S.capD, Y, S.capD, rng);
+  }
+  mark(h, MARK_CORE);
   mark(h, MARK_END);
   HIP_CHECK(h, hipGetLastError());
   h->s = d;
-  h->step += 1;
+  h->step += B;
   h->last_was_update = true;
-  S.T += 1;
-  S.d_ub = std::min<int64_t>(n_rows, S.d_ub + d);
-  S.n_cols_ub += nnz;
+  S.T += B;
+  S.d_ub = d_ub;
+  S.n_cols_ub += nnz_sum;
   return CTD_OK;
+}
+
+extern "C" ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d) {
+  if (!h) return CTD_ERR_INVALID_ARG;
+  if (!slice) return fail(h, CTD_ERR_STATE, "null slice");
+  return ctd_update_batched(h, slice, 1, d);
 }

@@ -86,8 +86,8 @@ struct DynState {
 
 struct ctd_handle {
   hipStream_t stream = nullptr;
-  hipEvent_t ev[11] = {};   // profiling marks (MARK_COUNT)
-  bool ev_used[11] = {};
+  hipEvent_t ev[12] = {};   // profiling marks (MARK_COUNT)
+  bool ev_used[12] = {};
   ctd_options opt{};
   ctd::DevScalars* d_sc = nullptr;
   ctd::Arena arena;
@@ -112,7 +112,7 @@ namespace ctd {
 // event i on the handle's stream.  Stage times are differences of marks.
 enum { MARK_START = 0, MARK_SORTED = 1, MARK_SAMPLED = 2, MARK_PANEL = 3, MARK_BASIS = 4,
        MARK_SPMM0 = 5, MARK_SPMM1 = 6, MARK_PROJECTED = 7, MARK_CORE = 8, MARK_END = 9,
-       MARK_PROJ0 = 10, MARK_COUNT = 11 };
+       MARK_PROJ0 = 10, MARK_CROSS0 = 11, MARK_COUNT = 12 };
 void mark(ctd_handle* h, int i);
 int bits_for(uint64_t n);
 int64_t round8(int64_t x);

@@ -19,7 +19,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     assert names == sorted(["ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
-                            "ctd_sync", "ctd_get_result", "ctd_last_error", "ctd_destroy"])
+                            "ctd_update_batched", "ctd_sync", "ctd_get_result", "ctd_last_error",
+                            "ctd_destroy"])
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libctd.so not built")
@@ -38,3 +39,4 @@ def test_binding_struct_layout_matches_exports():
     # ctd_create rejects a NULL out pointer without touching the GPU
     assert lib.ctd_create(None, None, None) == 1
     assert lib.ctd_last_error(None) == b"null handle"
+    assert lib.ctd_update_batched(None, None, 1, 1) == 1

@@ -119,3 +119,57 @@ def test_update_argument_checks(lib):
         h2.update(sd, si, sv, 2)
     assert ei.value.name == "CTD_ERR_STATE"
     h2.close()
+
+
+@pytest.mark.parametrize("B", [2, 3, 8])
+def test_batched_update_equals_sequential(lib, B):
+    """ctd_update_batched over B slices gives what B calls of ctd_update give: the same
+    draws and kept fibers, errors to rounding, and C (the rows of the batch's kept
+    fibers over earlier columns come from one deferred pass)."""
+    st = _stream(5, dims=(60, 50, 12), n_slices=8)
+    o = ora.Dynamic(st.initial.dims, st.initial.idx, st.initial.val, 0, 50, 5)
+    seq_steps, seq_final = _run(lib, st, 50, 8, 5)
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, 50, 5)
+        slices = [lib.to_device(sl, "cuda") for sl in st.slices]
+        for i in range(0, len(slices), B):
+            h.update_batched(slices[i:i + B], 8)
+            r = h.result()
+            ref = seq_steps[min(i + B, len(slices))]
+            assert r["step"] == ref["step"]
+            assert np.array_equal(r["accepted"], ref["accepted"])
+            assert abs(r["rel_err"] - ref["rel_err"]) <= 1e-12 * ref["rel_err"] + 1e-15
+        final = h.result(factors=True)
+    finally:
+        h.close()
+    assert np.array_equal(final["col_ids"], seq_final["col_ids"])
+    C, Cs = final["C"], seq_final["C"]
+    assert C.shape == Cs.shape
+    for sl in st.slices:
+        o.update(sl.dims, sl.idx, sl.val, 8)
+    ref = reference_core(st, o)
+    cond = np.linalg.cond(final["R"])
+    tol = max(1e-12, 1e-15 * cond ** 2)
+    assert np.abs(C - ref).max() / np.abs(ref).max() <= tol
+    assert np.abs(C - Cs).max() / np.abs(ref).max() <= tol
+
+
+def test_batched_update_argument_checks(lib):
+    st = _stream(11, n_slices=2)
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, 20, 1)
+        sd, si, sv = lib.to_device(st.slices[0], "cuda")
+        with pytest.raises(lib.CtdError) as ei:
+            h.update_batched([(sd, si, sv), ((sd[0], sd[1], 2), si, sv)], 2)
+        assert ei.value.name == "CTD_ERR_STATE"
+        with pytest.raises(lib.CtdError) as ei:
+            h.update_batched([], 2)
+        assert ei.value.name == "CTD_ERR_INVALID_ARG"
+        h.update_batched([(sd, si, sv)], 2)      # the handle is still usable
+        assert h.result()["step"] == 1
+    finally:
+        h.close()

@@ -26,8 +26,8 @@ def _split(flat, lens):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_stream_full_size(precision):
+@pytest.mark.parametrize("precision,batch", [("fp64", 1), ("mixed", 1), ("fp64", 4)])
+def test_stream_full_size(precision, batch):
     import torch
     import paper_1710_03608_amd as ctd
     ctd.load_library()
@@ -51,11 +51,17 @@ def test_stream_full_size(precision):
         T0, J = X.dims[2], X.dims[1]
         held = list(g["init_accepted"])
         for t in range(n):
-            sd, si, sv = ctd.to_device(st.slices[t], "cuda")
-            h.update(sd, si, sv, 8)
+            if batch == 1:
+                sd, si, sv = ctd.to_device(st.slices[t], "cuda")
+                h.update(sd, si, sv, 8)
+            elif t % batch == 0:
+                h.update_batched([ctd.to_device(sl, "cuda") for sl in st.slices[t:t + batch]], 8)
+            if (t + 1) % batch:
+                held.extend(acc[t].tolist())
+                continue
             r = h.result()
             off = np.uint64((T0 + t) * J)
-            assert np.array_equal(r["draws"] + off, draws[t]), t
+            assert np.array_equal(r["draws"] + off, draws[t]), t      # draws of the last slice
             held.extend(acc[t].tolist())
             assert r["s_tilde"] == int(g["d_tilde"][t]), t
             assert np.array_equal(r["accepted"], np.array(held, dtype=np.uint64)), t
