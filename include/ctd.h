@@ -166,6 +166,24 @@ ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d);
  * instead of once per slice.  1 <= B <= CTD_MAX_BATCH. */
 ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B, int64_t d);
 
+/* Many independent tensors in one call (the batched execution form of
+ * CTD-S): tensor b of the host array Xs[0..B) gets Algorithm 1 with s[b]
+ * draws in mode `mode`, its draws using Philox counter word tensor = b
+ * (tensor 0 reproduces ctd_decompose).  Tensors run concurrently on internal
+ * streams of default priority, ordered after the caller's earlier work on
+ * the handle's stream; later work on that stream runs after all of them.
+ * Per-tensor results are read with ctd_get_batch_result; the handle's own
+ * CTD-S / CTD-D state is left as it was.  Host argument errors are returned
+ * at once; device errors are latched per tensor. */
+ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, int32_t B, int32_t mode,
+                                 const int64_t* s, uint64_t seed);
+
+/* Wait for the stream and fill `out` with tensor b of the last batched call:
+ * scalars and the index arrays (draws, unique, counts, prob, scale,
+ * accepted; device memory owned by the handle until the next batched call).
+ * Factor pointers are NULL.  Returns tensor b's latched device status. */
+ctd_status ctd_get_batch_result(ctd_handle* h, int32_t b, ctd_result* out);
+
 /* Wait for the stream and return the latched device status. */
 ctd_status ctd_sync(ctd_handle* h);
 
@@ -181,6 +199,7 @@ void ctd_destroy(ctd_handle* h);
 #define CTD_MAX_ORDER 8
 #define CTD_MAX_DRAWS 16384
 #define CTD_MAX_BATCH 256
+#define CTD_MAX_TENSORS 65536
 
 #ifdef __cplusplus
 }

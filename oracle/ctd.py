@@ -363,13 +363,17 @@ def ctd_s_given(u: Unfolding, draw_pos, eps=1e-6, want_C=False, residual="auto",
                         u.fids[uniq[kept]], np.array(rho), R, U, C, err2, u.norm2, proj, Qb)
 
 
-def ctd_s(dims, idx, val, mode, s, seed, eps=1e-6, want_C=False, residual="auto"):
-    """Algorithm 1 end to end with the Philox draw specification above."""
+def ctd_s(dims, idx, val, mode, s, seed, eps=1e-6, want_C=False, residual="auto", tensor=0):
+    """Algorithm 1 end to end with the Philox draw specification above.
+
+    `tensor` is the counter word that tells the tensors of one batched call
+    apart (0 for a single decomposition, b for the b-th tensor of a batch).
+    """
     u = unfold(dims, idx, val, mode)
     if not 1 <= s <= u.n_cols_total:
         raise ValueError("sample size out of range")
     w, W = quantized_weights(u)
-    draw_pos = sample_columns(w, W, s, seed, step=0, tensor=0)
+    draw_pos = sample_columns(w, W, s, seed, step=0, tensor=tensor)
     return ctd_s_given(u, draw_pos, eps, want_C, residual, w=w, W=W, s=s)
 
 

@@ -21,7 +21,8 @@ STATUS = {0: "CTD_OK", 1: "CTD_ERR_INVALID_ARG", 2: "CTD_ERR_EMPTY", 3: "CTD_ERR
           4: "CTD_ERR_DUPLICATE", 5: "CTD_ERR_NONFINITE", 6: "CTD_ERR_OOM", 7: "CTD_ERR_HIP",
           8: "CTD_ERR_STATE", 9: "CTD_ERR_CAPACITY"}
 EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
-           "ctd_update_batched", "ctd_sync", "ctd_get_result", "ctd_last_error", "ctd_destroy")
+           "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result", "ctd_sync",
+           "ctd_get_result", "ctd_last_error", "ctd_destroy")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -74,6 +75,9 @@ def load_library():
                                         ctypes.POINTER(c_u64), c_i64]
     lib.ctd_update.argtypes = [c_vp, ctypes.POINTER(CooStruct), c_i64]
     lib.ctd_update_batched.argtypes = [c_vp, ctypes.POINTER(CooStruct), c_i32, c_i64]
+    lib.ctd_decompose_batched.argtypes = [c_vp, ctypes.POINTER(CooStruct), c_i32, c_i32,
+                                          ctypes.POINTER(c_i64), c_u64]
+    lib.ctd_get_batch_result.argtypes = [c_vp, c_i32, ctypes.POINTER(ResultStruct)]
     lib.ctd_sync.argtypes = [c_vp]
     lib.ctd_get_result.argtypes = [c_vp, ctypes.POINTER(ResultStruct)]
     lib.ctd_last_error.argtypes = [c_vp]
@@ -81,7 +85,8 @@ def load_library():
     lib.ctd_destroy.argtypes = [c_vp]
     lib.ctd_destroy.restype = None
     for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
-                 "ctd_update_batched", "ctd_sync", "ctd_get_result"):
+                 "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
+                 "ctd_sync", "ctd_get_result"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -211,6 +216,29 @@ class Ctd:
         arr = (CooStruct * len(coos))(*[c.struct for c in coos])
         self._keep.append(arr)
         self._check(self.lib.ctd_update_batched(self.h, arr, len(coos), int(d)))
+
+    def decompose_batched(self, tensors, mode, s, seed):
+        """CTD-S of many tensors [(dims, idx, val), ...] with s[b] draws each."""
+        coos = [Coo(dims, idx, val) for dims, idx, val in tensors]
+        arr = (CooStruct * len(coos))(*[c.struct for c in coos])
+        sz = (c_i64 * len(coos))(*[int(x) for x in s])
+        self._keep = [coos, arr, sz]
+        self._check(self.lib.ctd_decompose_batched(self.h, arr, len(coos), int(mode), sz, int(seed)))
+
+    def batch_result(self, b, arrays=True):
+        """Scalars (and index arrays) of tensor b of the last batched call."""
+        r = ResultStruct()
+        self._check(self.lib.ctd_get_batch_result(self.h, int(b), ctypes.byref(r)))
+        out = {k: getattr(r, k) for k in ("s", "s_unique", "s_tilde", "n_f", "n_rows",
+                                          "weight_total", "norm2", "err2", "rel_err")}
+        if arrays:
+            out["draws"] = device_to_numpy(r.draws, r.s, np.uint64)
+            out["unique"] = device_to_numpy(r.unique, r.s_unique, np.uint64)
+            out["counts"] = device_to_numpy(r.counts, r.s_unique, np.int32)
+            out["prob"] = device_to_numpy(r.prob, r.s_unique, np.float64)
+            out["scale"] = device_to_numpy(r.scale, r.s_unique, np.float64)
+            out["accepted"] = device_to_numpy(r.accepted, r.s_tilde, np.uint64)
+        return out
 
     def sync(self):
         self._check(self.lib.ctd_sync(self.h))

@@ -191,7 +191,8 @@ namespace ctd {
 // A0-A3 on one COO input: keys, fiber-major layout, weights, draws (sampled
 // with Philox counter word `step`, or given) and the unique candidates.
 ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
-                         uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b) {
+                         uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b,
+                         uint32_t tensor) {
   hipStream_t st = h->stream;
   const bool mixed = h->opt.precision == CTD_PREC_MIXED;
   const int64_t nnz = X->nnz;
@@ -229,7 +230,7 @@ ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay
     HIP_TRY(h, hipMemcpyAsync(b.draw_fid, given, s * 8, hipMemcpyHostToDevice, st));
     launch_locate_given(st, b.fid, s, b.draw_fid, b.draw_fi, sc);
   } else {
-    launch_draws(st, b.qpref, b.fptr, b.fid, nnz, s, seed, step, 0u, b.draw_fi, b.draw_fid, sc);
+    launch_draws(st, b.qpref, b.fptr, b.fid, nnz, s, seed, step, tensor, b.draw_fi, b.draw_fid, sc);
   }
   // A3: unique
   launch_unique(st, b.draw_fi, s, b.qpref, b.fptr, b.fid, b.uniq_fi, b.uniq_fid, b.counts, b.prob,
@@ -271,11 +272,12 @@ ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const fl
 
 }  // namespace ctd
 
-namespace {
+namespace ctd {
 
-// Enqueue CTD-S on `lay`/`X`; draws either sampled (given == nullptr) or given.
+// Enqueue CTD-S on `lay`/`X`; draws either sampled (given == nullptr, Philox
+// counter word `tensor`) or given.
 ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
-                      uint64_t seed, const uint64_t* given) {
+                      uint64_t seed, const uint64_t* given, uint32_t tensor) {
   hipStream_t st = h->stream;
   const bool mixed = h->opt.precision == CTD_PREC_MIXED;
   const bool want_C = h->opt.want_C != 0;
@@ -288,7 +290,7 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   for (bool& u : h->ev_used) u = false;
   mark(h, MARK_START);
   launch_reset_scalars(st, sc, false);
-  rc = enqueue_input(h, X, lay, s, seed, 0u, given, b);
+  rc = enqueue_input(h, X, lay, s, seed, 0u, given, b, tensor);
   if (rc != CTD_OK) return rc;
   // A4: candidate panel
   launch_panel(st, b.uniq_fi, s, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
@@ -350,7 +352,7 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   return CTD_OK;
 }
 
-}  // namespace
+}  // namespace ctd
 
 extern "C" {
 
@@ -400,7 +402,7 @@ ctd_status ctd_decompose(ctd_handle* h, const ctd_coo* X, int32_t mode, int64_t 
   h->has_static = false;
   h->dyn_ready = false;
   h->seed = seed;
-  rc = run_static(h, X, lay, s, seed, nullptr);
+  rc = run_static(h, X, lay, s, seed, nullptr, 0u);
   if (rc == CTD_OK && h->opt.want_C) rc = dyn_begin(h, X);
   return rc;
 }
@@ -424,7 +426,7 @@ ctd_status ctd_decompose_given(ctd_handle* h, const ctd_coo* X, int32_t mode,
   h->dyn_ready = false;
   h->given.assign(draws, draws + s);
   h->seed = 0;
-  rc = run_static(h, X, lay, s, 0, h->given.data());
+  rc = run_static(h, X, lay, s, 0, h->given.data(), 0u);
   if (rc == CTD_OK && h->opt.want_C) rc = dyn_begin(h, X);
   return rc;
 }
@@ -461,11 +463,20 @@ const char* ctd_last_error(const ctd_handle* h) { return h ? h->last_error.c_str
 void ctd_destroy(ctd_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  if (h->batch) {
+    ctd::BatchState* B = h->batch;
+    for (ctd_handle* sub : B->subs) ctd_destroy(sub);
+    for (hipEvent_t e : B->done) (void)hipEventDestroy(e);
+    if (B->start) (void)hipEventDestroy(B->start);
+    ctd::batch_free_storage(B);
+    delete B;
+  }
   for (hipEvent_t& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   dyn_free(h);
   if (h->arena.base) (void)hipFree(h->arena.base);
   if (h->d_sc) (void)hipFree(h->d_sc);
+  if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
 

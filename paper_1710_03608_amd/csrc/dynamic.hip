@@ -183,8 +183,9 @@ __global__ void k_batch_begin(DevScalars* sc) { sc->wacc_base = sc->n_accept_tot
 // P_{t+b} P_t = P_t).  Pass b + 1: the columns of slice b, K = the rank after
 // slice b, rows of the fibers kept by later slices.  rng = {K, a_lo, na, c_lo,
 // c_hi}: rows a_lo .. a_lo + na of the batch's Wacc, C rows K .. K + na.
-__global__ void k_cross_setup(const int64_t* info, int B, int p, const DevScalars* sc,
-                              int64_t* rng) {
+__global__ void k_cross_setup(const int64_t* info, int B, const DevScalars* sc, int64_t* rng) {
+  const int p = threadIdx.x;
+  if (p >= B) return;
   const int64_t base = info[0], total = info[2 * B] - base;
   int64_t K, c_lo, c_hi;
   if (p == 0) {
@@ -198,19 +199,24 @@ __global__ void k_cross_setup(const int64_t* info, int B, int p, const DevScalar
     c_hi = info[2 * (b + 1) + 1];
   }
   const int64_t a_lo = K - base;
-  rng[0] = K;
-  rng[1] = a_lo;
-  rng[2] = sc->status == 0 ? total - a_lo : 0;
-  rng[3] = c_lo;
-  rng[4] = c_hi;
+  int64_t* r = rng + 5 * p;
+  r[0] = K;
+  r[1] = a_lo;
+  r[2] = sc->status == 0 ? total - a_lo : 0;
+  r[3] = c_lo;
+  r[4] = c_hi;
 }
 
 // Rows of ((dR^T R) U): Y[a][c] = sum_{c <= j < K} M[c][j] Wacc[a_lo + a][j]
-// for c < K (with w = Q^T x the row x^T R U equals (M w)^T); one wave per c.
+// for c < K (with w = Q^T x the row x^T R U equals (M w)^T); one wave per c,
+// pass p = blockIdx.y writing Y + p * ystride.
 __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict__ M, int64_t ldm,
                                                        const double* __restrict__ Wacc,
-                                                       int64_t ldw, double* __restrict__ Y,
-                                                       int64_t ldy, const int64_t* rng) {
+                                                       int64_t ldw, double* __restrict__ Yall,
+                                                       int64_t ldy, int64_t ystride,
+                                                       const int64_t* rng_all) {
+  const int64_t* rng = rng_all + 5 * blockIdx.y;
+  double* Y = Yall + blockIdx.y * ystride;
   const int64_t K = rng[0], a_lo = rng[1], na = rng[2];
   const int lane = lane_id();
   const int64_t c = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
@@ -226,39 +232,44 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 }
 
 // Cross term: C[d + a][f] = sum_{k<d} Y[a][k] C[k][f] for f in [c_lo, c_hi)
-// (d = K of the pass; pass 0 reads all of C^(t): the HBM-bound step).  A
-// workgroup owns 256 columns and streams them in chunks of 32 rows: 32
-// threads read one column's 256 contiguous bytes into LDS, the next chunk is
-// prefetched into registers meanwhile, and thread t accumulates the new rows
-// of column t from LDS.  Up to kCrossRows new rows per pass over C.
-constexpr int kCrossCols = 256, kCrossK = 32, kCrossRows = 16;
+// (d = K of the pass; pass 0 reads all of C^(t): the HBM-bound step).  Pass
+// p = blockIdx.y.  A workgroup owns 256 columns and streams them in chunks of
+// KCH rows: KCH threads read one column's contiguous rows into LDS, the next
+// chunk is prefetched into registers meanwhile, and thread t accumulates up
+// to ROWS new rows of column t from LDS, so C is read once per ROWS rows.
+constexpr int kCrossCols = 256;
+template <int ROWS, int KCH>
 __global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ C, int64_t ldc,
-                                                           const double* __restrict__ Y,
-                                                           int64_t ldy, const int64_t* rng) {
-  __shared__ double Cs[kCrossCols][kCrossK + 1];
-  __shared__ __align__(16) double Ys[kCrossK][kCrossRows];   // [row k][new row a]
+                                                           const double* __restrict__ Yall,
+                                                           int64_t ldy, int64_t ystride,
+                                                           const int64_t* rng_all) {
+  __shared__ double Cs[kCrossCols][KCH + 1];
+  __shared__ __align__(16) double Ys[KCH][ROWS];   // [row k][new row a]
+  const int64_t* rng = rng_all + 5 * blockIdx.y;
+  const double* Y = Yall + blockIdx.y * ystride;
   const int64_t d = rng[0], na = rng[2], ncols = rng[4];
   const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
   if (na <= 0 || f0 >= ncols) return;
   const int t = threadIdx.x;
-  const int64_t nch = (d + kCrossK - 1) / kCrossK;
-  for (int64_t a0 = 0; a0 < na; a0 += kCrossRows) {
-    const int nr = (int)min<int64_t>(kCrossRows, na - a0);
-    double acc[kCrossRows];
+  const int64_t nch = (d + KCH - 1) / KCH;
+  // thread t loads rows k0 + t % KCH of columns f0 + t / KCH + (256 / KCH) u
+  constexpr int kColStep = kCrossCols / KCH;
+  const int64_t fcol = f0 + t / KCH;
+  const int rr = t % KCH;
+  const double* base = C + fcol * ldc + rr;
+  const int64_t stride = (int64_t)kColStep * ldc;
+  for (int64_t a0 = 0; a0 < na; a0 += ROWS) {
+    const int nr = (int)min<int64_t>(ROWS, na - a0);
+    double acc[ROWS];
 #pragma unroll
-    for (int u = 0; u < kCrossRows; ++u) acc[u] = 0.0;
-    // thread t loads rows k0 + t % 32 of columns f0 + t / 32 + 8 u (u < 32)
-    double pre[kCrossK];
-    const int64_t fcol = f0 + t / kCrossK;
-    const int rr = t % kCrossK;
-    const double* base = C + fcol * ldc + rr;
-    const int64_t stride = (int64_t)(kCrossCols / kCrossK) * ldc;
+    for (int u = 0; u < ROWS; ++u) acc[u] = 0.0;
+    double pre[KCH];
     auto load = [&](int64_t ch) {
-      const int64_t k0 = ch * kCrossK;
+      const int64_t k0 = ch * KCH;
       const bool kin = ch < nch && k0 + rr < d;
 #pragma unroll
-      for (int u = 0; u < kCrossK; ++u) {
-        const bool in = kin && fcol + (kCrossCols / kCrossK) * u < ncols;
+      for (int u = 0; u < KCH; ++u) {
+        const bool in = kin && fcol + (int64_t)kColStep * u < ncols;
         pre[u] = in ? base[k0 + u * stride] : 0.0;
       }
     };
@@ -266,20 +277,20 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ 
     for (int64_t ch = 0; ch < nch; ++ch) {
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < kCrossK; ++u) Cs[t / kCrossK + (kCrossCols / kCrossK) * u][rr] = pre[u];
-      for (int i = t; i < kCrossRows * kCrossK; i += kCrossCols) {
-        const int a = i / kCrossK, r = i % kCrossK;
-        const int64_t k = ch * kCrossK + r;
+      for (int u = 0; u < KCH; ++u) Cs[t / KCH + kColStep * u][rr] = pre[u];
+      for (int i = t; i < ROWS * KCH; i += kCrossCols) {
+        const int a = i / KCH, r = i % KCH;
+        const int64_t k = ch * KCH + r;
         Ys[r][a] = (a < nr && k < d) ? Y[(a0 + a) * ldy + k] : 0.0;
       }
       __syncthreads();
       load(ch + 1);
-#pragma unroll 4
-      for (int r = 0; r < kCrossK; ++r) {
+#pragma unroll 2
+      for (int r = 0; r < KCH; ++r) {
         const double cv = Cs[t][r];
         const double2* yr = (const double2*)Ys[r];
 #pragma unroll
-        for (int u = 0; u < kCrossRows / 2; ++u) {
+        for (int u = 0; u < ROWS / 2; ++u) {
           const double2 y = yr[u];
           acc[2 * u] += y.x * cv;
           acc[2 * u + 1] += y.y * cv;
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ 
     if (f < ncols) {
       double* col = C + f * ldc + d + a0;
 #pragma unroll
-      for (int u = 0; u < kCrossRows; ++u)
+      for (int u = 0; u < ROWS; ++u)
         if (u < nr) col[u] = acc[u];
     }
   }
@@ -353,6 +364,8 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
   DynState N = S;
   N.capD = capD;
   N.capN = capN;
+  N.rows = n_rows;
+  N.mixed = mixed;
   auto alloc = [&](void** p, size_t bytes) -> bool {
     if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
       (void)hipGetLastError();
@@ -380,7 +393,7 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
     if (!S.lev) (void)hipFree(N.lev);
     return fail(h, CTD_ERR_OOM, "CTD-D state allocation failed");
   }
-  if (S.capD) {
+  if (S.capD && (S.d_tilde > 0 || S.n_cols > 0)) {
     const int64_t dr = S.d_tilde, nc = S.n_cols;
     HIP_CHECK(h, hipMemcpy2DAsync(N.Rs, capD * 8, S.Rs, S.capD * 8, dr * 8, n_rows,
                                   hipMemcpyDeviceToDevice, h->stream));
@@ -397,6 +410,8 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
     HIP_CHECK(h, hipMemcpyAsync(N.acc_fid, S.acc_fid, dr * 8, hipMemcpyDeviceToDevice, h->stream));
     if (nc > 0)
       HIP_CHECK(h, hipMemcpyAsync(N.col_fid, S.col_fid, nc * 8, hipMemcpyDeviceToDevice, h->stream));
+  }
+  if (S.capD) {
     HIP_CHECK(h, hipStreamSynchronize(h->stream));
     (void)hipFree(S.Rs);
     (void)hipFree(S.Q);
@@ -449,10 +464,19 @@ ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X) {
   if (sc.status != 0) return fail(h, (ctd_status)sc.status, "device reported an error");
   const int64_t st = sc.s_tilde, nf = sc.n_f;
   DynState& S = h->dyn;
-  dyn_free(h);
-  S = DynState{};
+  // a new stream: the buffers of an earlier stream on this handle are reused
+  // when they fit (same I_alpha and precision, enough capacity); nothing is
+  // copied from them
+  const bool mixed_now = h->opt.precision == CTD_PREC_MIXED;
+  if (S.capD && (S.rows != h->n_rows || S.mixed != mixed_now)) {
+    HIP_CHECK(h, hipStreamSynchronize(h->stream));
+    dyn_free(h);
+  }
+  S.d_tilde = S.d_ub = 0;
+  S.n_cols = S.n_cols_ub = 0;
+  S.T = 0;
   const int64_t capD = std::max<int64_t>(2 * h->s + 256, st + 64);
-  const int64_t capN = nf + std::max<int64_t>(nf, 1 << 16);
+  const int64_t capN = 2 * nf + (1 << 16);
   ctd_status rc = dyn_reserve(h, capD, capN);
   if (rc != CTD_OK) return rc;
   const bool mixed = h->opt.precision == CTD_PREC_MIXED;
@@ -611,7 +635,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
     const int64_t nn = S.n_cols + nnz_sum;
     if (nd > S.capD || nn > S.capN) {
       rc = dyn_reserve(h, nd > S.capD ? std::max(nd, 2 * S.capD) : S.capD,
-                       nn > S.capN ? std::max(nn, S.capN + S.capN / 2) : S.capN);
+                       nn > S.capN ? std::max(nn, 2 * S.capN) : S.capN);
       if (rc != CTD_OK) return rc;
     }
   }
@@ -622,7 +646,8 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
   // rows, slice records and pass ranges
   const int64_t kept_max = std::min<int64_t>(n_rows, (int64_t)B * d);
   const size_t ws_doubles = basis_scratch_doubles(n_rows, S.capD) +
-                            (size_t)2 * kept_max * S.capD + (size_t)2 * (B + 1) + 8 + 64;
+                            (size_t)(1 + B) * kept_max * S.capD + (size_t)2 * (B + 1) +
+                            (size_t)5 * B + 64;
   if (ws_doubles * 8 > S.ws_bytes) {
     if (S.ws) {
       HIP_CHECK(h, hipStreamSynchronize(st));
@@ -639,7 +664,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
   double* scratch = (double*)S.ws;
   double* Wacc = scratch + basis_scratch_doubles(n_rows, S.capD);
   double* Y = Wacc + (size_t)kept_max * S.capD;
-  int64_t* info = (int64_t*)(Y + (size_t)kept_max * S.capD);
+  int64_t* info = (int64_t*)(Y + (size_t)B * kept_max * S.capD);   // Y: one block per pass
   int64_t* rng = info + 2 * (B + 1);
 
   for (bool& u : h->ev_used) u = false;
@@ -655,7 +680,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
     const uint64_t t_off = (uint64_t)(S.T + bi) * (uint64_t)S.dN;
     const int64_t d_next = std::min<int64_t>(n_rows, d_ub + d);
     if (nnz > 0) {
-      rc = enqueue_input(h, slice, lays[bi], d, h->seed, step, nullptr, b);
+      rc = enqueue_input(h, slice, lays[bi], d, h->seed, step, nullptr, b, 0u);
       if (rc != CTD_OK) return rc;
       // candidates against R^(t) and each other; kept ones extend R, Q, M
       launch_panel(st, b.uniq_fi, d, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
@@ -714,14 +739,22 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
   // C rows of the batch's kept fibers (Eq. 13): pass 0 over the columns held
   // before the batch, pass b + 1 over the columns of slice b
   mark(h, MARK_CROSS0);
-  for (int p = 0; p < B; ++p) {
-    const int64_t cols_ub = p == 0 ? S.n_cols_ub : slices[p - 1].nnz;
-    if (cols_ub == 0) continue;
-    hipLaunchKernelGGL(k_cross_setup, dim3(1), dim3(1), 0, st, info, B, p, sc, rng);
-    hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave)), dim3(kBlock), 0, st, S.Xt,
-                       S.capD, Wacc, S.capD, Y, S.capD, rng);
-    hipLaunchKernelGGL(k_cross_term, dim3(std::max<int64_t>(1, (cols_ub + kCrossCols - 1) / kCrossCols)),
-                       dim3(kCrossCols), 0, st, S.C, S.capD, Y, S.capD, rng);
+  {
+    int64_t tiles = (S.n_cols_ub + kCrossCols - 1) / kCrossCols;
+    for (int p = 1; p < B; ++p)
+      tiles = std::max<int64_t>(tiles, (slices[p - 1].nnz + kCrossCols - 1) / kCrossCols);
+    const int64_t ystride = kept_max * S.capD;
+    hipLaunchKernelGGL(k_cross_setup, dim3(1), dim3(CTD_MAX_BATCH), 0, st, info, B, sc, rng);
+    hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave), B), dim3(kBlock), 0, st, S.Xt,
+                       S.capD, Wacc, S.capD, Y, S.capD, ystride, rng);
+    if (tiles > 0) {
+      if (kept_max <= 16)
+        hipLaunchKernelGGL((k_cross_term<16, 32>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
+                           S.capD, Y, S.capD, ystride, rng);
+      else
+        hipLaunchKernelGGL((k_cross_term<64, 16>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
+                           S.capD, Y, S.capD, ystride, rng);
+    }
   }
   mark(h, MARK_CORE);
   mark(h, MARK_END);

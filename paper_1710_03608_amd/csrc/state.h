@@ -70,16 +70,39 @@ struct DynState {
   int64_t n_cols_ub = 0;   // host upper bound of n_cols between syncs
   int64_t T = 0;           // time steps held
   int64_t dN = 0;          // columns per time step (N_alpha of a slice)
+  int64_t rows = 0;        // I_alpha the buffers were allocated for
+  bool mixed = false;      // whether Qf is held
   double* Rs = nullptr;    // n_rows x capD row-major: kept fibers
   double* Q = nullptr;     // n_rows x capD row-major: orthonormal basis
   float* Qf = nullptr;     // mixed precision copy of Q
-  double* Xt = nullptr;    // capD x capD row-major: (L^{-1})^T
+  double* Xt = nullptr;    // capD x capD row-major upper M with Q = R M
   double* lev = nullptr;   // n_rows: ||Q_i||^2
   double* C = nullptr;     // capD x capN column-major
   uint64_t* acc_fid = nullptr;  // capD kept fiber ids
   uint64_t* col_fid = nullptr;  // capN fiber ids of C's columns
   void* ws = nullptr;      // per-slice workspace
   size_t ws_bytes = 0;
+};
+
+// Many independent tensors in one call: tensors are spread over sub-handles
+// that own their streams; per-tensor results are copied into batch storage.
+struct BatchState {
+  std::vector<ctd_handle*> subs;
+  std::vector<hipEvent_t> done;
+  hipEvent_t start = nullptr;
+  int32_t B = 0;
+  std::vector<int64_t> s, off, rows;
+  DevScalars* scal = nullptr;      // [B] scalars of each tensor
+  size_t cap_t = 0;
+  uint64_t* draws = nullptr;       // per tensor at off[b]: s[b] entries each
+  uint64_t* unique = nullptr;
+  uint64_t* accepted = nullptr;
+  int32_t* counts = nullptr;
+  double* prob = nullptr;
+  double* scale = nullptr;
+  size_t cap_s = 0;
+  std::vector<DevScalars> host;
+  bool host_valid = false;
 };
 
 }  // namespace ctd
@@ -105,6 +128,8 @@ struct ctd_handle {
   bool has_static = false;
   bool dyn_ready = false;
   bool last_was_update = false;
+  bool own_stream = false;          // sub-handle of a batch: the stream is ours
+  ctd::BatchState* batch = nullptr;
 };
 
 namespace ctd {
@@ -122,7 +147,10 @@ ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout*
 ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
                        bool want_C, int64_t max_cols, StaticBufs* b);
 ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
-                         uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b);
+                         uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b,
+                         uint32_t tensor);
+ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
+                      uint64_t seed, const uint64_t* given, uint32_t tensor);
 int key_bits(const FiberLayout& lay);
 ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const float* Qf,
                          int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max);
@@ -133,4 +161,5 @@ void launch_core_static(hipStream_t st, StaticBufs& b, int64_t n_rows, int64_t n
 ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X);
 void dyn_free(ctd_handle* h);
 void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out);
+void batch_free_storage(BatchState* B);
 }  // namespace ctd

@@ -19,8 +19,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     assert names == sorted(["ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
-                            "ctd_update_batched", "ctd_sync", "ctd_get_result", "ctd_last_error",
-                            "ctd_destroy"])
+                            "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
+                            "ctd_sync", "ctd_get_result", "ctd_last_error", "ctd_destroy"])
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libctd.so not built")
@@ -40,3 +40,5 @@ def test_binding_struct_layout_matches_exports():
     assert lib.ctd_create(None, None, None) == 1
     assert lib.ctd_last_error(None) == b"null handle"
     assert lib.ctd_update_batched(None, None, 1, 1) == 1
+    assert lib.ctd_decompose_batched(None, None, 1, 0, None, 0) == 1
+    assert lib.ctd_get_batch_result(None, 0, None) == 1

@@ -1,0 +1,103 @@
+"""Batched CTD-S (many independent tensors in one call) against the CPU oracle:
+tensor b draws with Philox counter word tensor = b (oracle ctd_s(..., tensor=b))."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ctd as ora
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_1710_03608_amd as ctd
+    assert torch.cuda.is_available()
+    ctd.load_library()
+    return ctd
+
+
+def _tensors(n, seed):
+    """Uneven shapes and sizes shaped like the many-tensor workload, scaled down."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    out = []
+    for b in range(n):
+        I, J, K = (int(rng.integers(30, 200)), int(rng.integers(30, 200)), int(rng.integers(4, 20)))
+        nnz = int(rng.integers(300, 6000))
+        out.append(synth.power_law_tensor((I, J, K), min(nnz, I * J * K // 4), 1000 + b, zipf_a=1.2,
+                                          values="uniform"))
+    return out
+
+
+def _sizes(ts):
+    return [max(1, math.ceil(0.05 * synth.count_nonempty_fibers(t, 0))) for t in ts]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_matches_oracle_per_tensor(lib, precision):
+    ts = _tensors(19, 3)          # more tensors than internal streams
+    s = _sizes(ts)
+    h = lib.Ctd(precision=precision)
+    try:
+        h.decompose_batched([lib.to_device(t, "cuda") for t in ts], 0, s, 11)
+        for b, t in enumerate(ts):
+            o = ora.ctd_s(t.dims, t.idx, t.val, 0, s[b], 11, tensor=b)
+            g = h.batch_result(b)
+            assert np.array_equal(g["draws"], o.draws.astype(np.uint64)), b
+            assert np.array_equal(g["unique"], o.uniq.astype(np.uint64)), b
+            assert np.array_equal(g["counts"], o.counts.astype(np.int32)), b
+            assert np.array_equal(g["accepted"], o.accepted.astype(np.uint64)), b
+            assert np.allclose(g["scale"], o.omega, rtol=1e-13, atol=0)
+            tol = 1e-6 if precision == "fp64" else 1e-4
+            assert abs(g["rel_err"] - o.rel_err) <= tol * o.rel_err + 1e-12, (b, g["rel_err"], o.rel_err)
+    finally:
+        h.close()
+
+
+def test_tensor_zero_equals_single_and_state_is_kept(lib):
+    ts = _tensors(3, 5)
+    s = _sizes(ts)
+    h = lib.Ctd()
+    try:
+        dims, idx, val = lib.to_device(ts[0], "cuda")
+        h.decompose(dims, idx, val, 0, s[0], 2)
+        single = h.result()
+        h.decompose_batched([lib.to_device(t, "cuda") for t in ts], 0, s, 2)
+        g0 = h.batch_result(0)
+        assert np.array_equal(g0["accepted"], single["accepted"])
+        assert g0["err2"] == single["err2"]
+        again = h.result()                      # the handle's own CTD-S result is untouched
+        assert np.array_equal(again["accepted"], single["accepted"]) and again["err2"] == single["err2"]
+        # a second batched call with other sizes reuses the handle
+        h.decompose_batched([lib.to_device(t, "cuda") for t in ts[1:]], 0, s[1:], 2)
+        g = h.batch_result(1)
+        o = ora.ctd_s(ts[2].dims, ts[2].idx, ts[2].val, 0, s[2], 2, tensor=1)
+        assert np.array_equal(g["accepted"], o.accepted.astype(np.uint64))
+    finally:
+        h.close()
+
+
+def test_batched_argument_checks(lib):
+    ts = _tensors(2, 7)
+    h = lib.Ctd()
+    try:
+        dev = [lib.to_device(t, "cuda") for t in ts]
+        with pytest.raises(lib.CtdError) as ei:
+            h.decompose_batched(dev, 3, [5, 5], 0)
+        assert ei.value.name == "CTD_ERR_INVALID_ARG"
+        with pytest.raises(lib.CtdError) as ei:
+            h.decompose_batched(dev, 0, [5, 0], 0)
+        assert ei.value.name == "CTD_ERR_INVALID_ARG"
+        with pytest.raises(lib.CtdError) as ei:
+            h.batch_result(0)
+        assert ei.value.name == "CTD_ERR_STATE"
+        h.decompose_batched(dev, 0, [5, 5], 0)
+        with pytest.raises(lib.CtdError) as ei:
+            h.batch_result(2)
+        assert ei.value.name == "CTD_ERR_INVALID_ARG"
+        assert h.batch_result(1)["s"] == 5
+    finally:
+        h.close()

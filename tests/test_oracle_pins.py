@@ -292,3 +292,19 @@ def test_draws_use_documented_counter_layout():
     seed = (7 << 32) | 99
     x = philox4x32_10((5, 0, 3, 2), (99, 7))
     assert draw_u128(seed, 5, 3, 2) == x[0] | (x[1] << 32) | (x[2] << 64) | (x[3] << 96)
+
+
+def test_batched_tensor_word_selects_independent_draws():
+    """The b-th tensor of a batched call draws with counter word 3 = b (word 0 of a
+    single call), so equal tensors in one batch get different samples, and tensor 0
+    of a batch reproduces the single decomposition."""
+    t = synth.power_law_tensor((30, 20, 8), 600, 8, zipf_a=1.2)
+    u = ctd.unfold(t.dims, t.idx, t.val, 0)
+    w, W = ctd.quantized_weights(u)
+    single = ctd.ctd_s(t.dims, t.idx, t.val, 0, 40, 3)
+    b0 = ctd.ctd_s(t.dims, t.idx, t.val, 0, 40, 3, tensor=0)
+    b5 = ctd.ctd_s(t.dims, t.idx, t.val, 0, 40, 3, tensor=5)
+    assert np.array_equal(single.draws, b0.draws)
+    assert not np.array_equal(b0.draws, b5.draws)
+    want = ctd.sample_columns(w, W, 40, 3, step=0, tensor=5)
+    assert np.array_equal(b5.draws, u.fids[want])
