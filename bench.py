@@ -107,6 +107,24 @@ def time_stream(ctd, st, precision, batch=1):
     return out
 
 
+def time_many(ctd, tensors, sizes, precision):
+    """Batched CTD-S of all tensors in one call (tensors resident on the device)."""
+    import torch
+    dev = [ctd.to_device(t, "cuda") for t in tensors]
+    h = ctd.Ctd(precision=precision)
+    ms = 0.0
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.decompose_batched(dev, 0, sizes, SEED)
+        h.sync()
+        ms = (time.perf_counter() - t0) * 1e3
+    rel = [h.batch_result(b, arrays=False)["rel_err"] for b in range(len(tensors))]
+    kept = [h.batch_result(b, arrays=False)["s_tilde"] for b in range(len(tensors))]
+    h.close()
+    return {"ms": ms, "mean_rel_err": float(sum(rel) / len(rel)), "kept_total": int(sum(kept))}
+
+
 def calibrate_copy():
     """A plain device-to-device copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES), run
     three times, so that FETCH_SIZE / WRITE_SIZE of the same profiling pass can be scaled."""
@@ -168,6 +186,8 @@ def main():
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-stream", action="store_true", help="skip the CTD-D stream leg")
     ap.add_argument("--stream-only", action="store_true", help="run only the CTD-D stream leg")
+    ap.add_argument("--no-many", action="store_true", help="skip the many-tensor batched leg")
+    ap.add_argument("--many-only", action="store_true", help="run only the many-tensor batched leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -183,8 +203,30 @@ def main():
     import paper_1710_03608_amd as ctd
     from workloads import synth
 
+    many_line = None
+    if not args.no_many and not args.stream_only:
+        import math
+        log("generating 512 independent tensors ...")
+        ts = synth.many_tensors()
+        torch.cuda.set_device(0)
+        sizes = [max(1, math.ceil(0.05 * synth.count_nonempty_fibers(t, 0))) for t in ts]
+        nnz_all = int(sum(t.nnz for t in ts))
+        many_line = {"workload": "ctd_s_batched_512_tensors_IJ500-5000_K20-200_nnz10k-200k_zipf1.2_s5pct",
+                     "tensors": len(ts), "nnz": nnz_all, "draws": int(sum(sizes)), "modes": {}}
+        for mode in args.modes.split(","):
+            log(f"batched CTD-S of {len(ts)} tensors, {mode}")
+            r = time_many(ctd, ts, sizes, mode)
+            r["nnz_per_s"] = nnz_all / (r["ms"] * 1e-3)
+            r["tensors_per_s"] = len(ts) / (r["ms"] * 1e-3)
+            many_line["modes"][mode] = r
+            log(f"  {mode}: {r['ms']:.1f} ms, {r['nnz_per_s']:.3e} nnz/s, mean rel_err {r['mean_rel_err']:.5f}")
+        del ts
+        if args.many_only:
+            print(json.dumps({"ctd_s_batched": many_line}), flush=True)
+            return
+
     stream_line = None
-    if not args.no_stream:
+    if not args.no_stream and not args.many_only:
         log("generating the CTD-D traffic stream ...")
         st = synth.traffic_stream()
         torch.cuda.set_device(0)
@@ -270,6 +312,8 @@ def main():
     }
     if stream_line is not None:
         line["ctd_d_stream"] = stream_line
+    if many_line is not None:
+        line["ctd_s_batched"] = many_line
     if args.calibrate_copy:
         calibrate_copy()
     if not args.no_cpu_baseline:
