@@ -529,26 +529,34 @@ __device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, d
     ah[q] = Ah[i0 + kRowsPer * q][c];
     al[q] = kDD ? (*Al)[i0 + kRowsPer * q][c] : 0.0;
   }
-  if (tid == 0) {
-    piv[0] = ah[0];
-    piv[1] = al[0];
-  }
-  __syncthreads();
-  uint64_t mask = 0;
-  int kept = 0;
-  for (int j = 0; j < n; ++j) {
-    const double dh = piv[0], dl = piv[1];
+  // The owner of diagonal entry (j, j) decides candidate j and broadcasts
+  // piv = {keep, L[j][j] (hi, lo), 1 / L[j][j] (hi, lo)}.
+  auto publish = [&](double dh, double dl, int j, int kept) {
     const bool keep = !drop || (((dh - eps2 * gs[j]) + dl > 0.0) && kept < room);
+    double lh = 0.0, ll = 0.0, rh = 0.0, rl = 0.0;
     if (keep) {
-      double lh, ll, rh, rl;
       if (kDD) {
         dd_sqrt(dh, dl, lh, ll);
         dd_div(1.0, 0.0, lh, ll, rh, rl);
       } else {
         lh = sqrt(fmax(dh, 1e-300));
         rh = 1.0 / lh;
-        ll = rl = 0.0;
       }
+    }
+    piv[0] = keep ? 1.0 : 0.0;
+    piv[1] = lh;
+    piv[2] = ll;
+    piv[3] = rh;
+    piv[4] = rl;
+  };
+  if (tid == 0 && n > 0) publish(ah[0], al[0], 0, 0);
+  __syncthreads();
+  uint64_t mask = 0;
+  int kept = 0;
+  for (int j = 0; j < n; ++j) {
+    const bool keep = piv[0] != 0.0;
+    if (keep) {
+      const double lh = piv[1], ll = piv[2], rh = piv[3], rl = piv[4];
 #pragma unroll
       for (int q = 0; q < kSlots; ++q) {
         const int i = i0 + kRowsPer * q;
@@ -569,6 +577,8 @@ __device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, d
           xrow[c] = ah[q];
         }
       }
+      (void)lh;
+      (void)ll;
       __syncthreads();
       const double cch = ch[c], ccl = cl[c], xr = xrow[c < j ? c : j];
 #pragma unroll
@@ -601,10 +611,7 @@ __device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, d
     if (c == j + 1 && j + 1 < n) {
 #pragma unroll
       for (int q = 0; q < kSlots; ++q)
-        if (i0 + kRowsPer * q == j + 1) {
-          piv[0] = ah[q];
-          piv[1] = al[q];
-        }
+        if (i0 + kRowsPer * q == j + 1) publish(ah[q], al[q], j + 1, kept);
     }
     __syncthreads();
   }
@@ -627,7 +634,7 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__
                                                       double* __restrict__ Tacc,
                                                       DevScalars* sc) {
   __shared__ LdsMat Ah, Al, X;
-  __shared__ double ch[kB], cl[kB], xrow[kB], gs[kB], piv[2];
+  __shared__ double ch[kB], cl[kB], xrow[kB], gs[kB], piv[5];
   __shared__ int32_t ps[kB];
   const int64_t nb = blk_count(sc, b0);
   const int tid = threadIdx.x;
@@ -675,7 +682,7 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict_
                                                        double* __restrict__ Tacc,
                                                        DevScalars* sc) {
   __shared__ LdsMat L, X, Ta;
-  __shared__ double ch[kB], cl[kB], xrow[kB], piv[2];
+  __shared__ double ch[kB], cl[kB], xrow[kB], piv[5];
   __shared__ int any_off;
   const int na = sc->blk_na;
   const int tid = threadIdx.x;
