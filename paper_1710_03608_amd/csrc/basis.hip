@@ -1,21 +1,23 @@
-// Independence filter and orthonormal basis, block by block (Algorithm 1
-// the independence loops of Algorithms 1 and 2).
+// Independence filter and orthonormal basis, block by block (the
+// independence loops of Algorithms 1 and 2).
 //
-// Candidates are visited in order in blocks of 64.  For a block B with the
-// kept set so far spanned by the orthonormal columns of Q (k of them):
-//   W = Q^T X_B                 (sparse fibers times dense Q)
-//   M = X_B^T X_B - W W^T       (Gram of the residuals X_B - Q W: its
-//                                Schur complements are the squared residual
-//                                norms ||res||^2 of Algorithm 1's test)
-//   Cholesky of M in candidate order, dropping a candidate whose pivot is
-//   <= eps^2 ||x||^2 (the skip rule); the pivots are accurate to about u ||x||^2
-//   because Q is orthonormal, whatever the conditioning of R.
-// The kept candidates' residuals Y = X_A - Q W_A are formed explicitly and
-// orthonormalized by two Cholesky-QR passes (Y <- Y L1^{-T}, Y <- Y L2^{-T});
-// they become the next columns of Q.  With Q = R M (M upper triangular, so
-// U = (R^T R)^{-1} = M M^T) the new columns of M are
-//   M[:k, new] = -M W_A^T T,  M[new, new] = T,  T = L1^{-T} L2^{-T}.
-// One block is ~12 small launches; sizes are read on the device.
+// Candidates are visited in order in blocks of 64.  For a block B, with the
+// fibers kept so far spanned by the orthonormal columns of Q (k of them):
+//   W = Q^T X_B                       sparse: the fibers' rows of Q
+//   Y = X_B - Q W^T,  W2 = Q^T Y,
+//   Y <- Y - Q W2^T,  W <- W + W2     block Gram-Schmidt applied twice, so Y
+//                                     is orthogonal to Q to working accuracy
+//   G = Y^T Y in double-double        its Schur complements are the squared
+//                                     residual norms ||res||^2 of the test
+//   Cholesky of G in candidate order (double-double), dropping a candidate
+//   whose pivot is <= eps^2 ||x||^2 (the skip rule), with L^{-1} formed in
+//   place.
+// The kept residuals Y_A become the next columns of Q as Y_A L^{-T}, followed
+// by a second Cholesky-QR pass when the first leaves them non-orthonormal.
+// With Q = R M (M upper triangular, so U = (R^T R)^{-1} = M M^T) the new
+// columns of M are M[:k, new] = -M W_A^T T and M[new, new] = T, T being the
+// product of the inverse transposed Cholesky factors.  Sizes are read on the
+// device, so one block is a fixed sequence of launches.
 #include "kernels.h"
 
 namespace ctd {
@@ -804,102 +806,125 @@ __global__ __launch_bounds__(kBlock) void k_blk_apply(double* __restrict__ Q, in
 // triangular), split over j: workgroup (ct, js) covers rows 64 ct .. + 64 and
 // j in [256 js, 256 js + 256), writing Zp[js][a][c] (zero when the range is
 // empty); k_blk_zsum adds the splits in a fixed order.
-constexpr int kJSplit = 256;
-__global__ __launch_bounds__(kBlock) void k_blk_cross(const double* __restrict__ M, int64_t ldm,
-                                                      const double* __restrict__ W, int64_t ldw,
-                                                      const int32_t* __restrict__ pos,
-                                                      double* __restrict__ Zp, int64_t ldz,
-                                                      const DevScalars* sc) {
-  __shared__ double Ms[kB][kB + 1];   // [j][c]
-  __shared__ double Wsh[kB][kB + 1];  // [j][a]
+// New columns of M (Q = R M) for the block's kept fibers:
+//   M[c][k + a] = -sum_{b <= a} Z[c][b] T[b][a],  Z = M W_A^T  (c < k),
+//   M[k + b][k + a] = T[b][a] (b <= a), M[k + b][c] = 0 below the diagonal,
+// W_A the W rows of the kept candidates and T = L1^{-T} (L2^{-T}).  Workgroup
+// x covers rows 32 x .. + 32 of M: Z's tile comes from f64 MFMAs over
+// j >= 32 x (M is upper triangular) with two groups of four waves splitting
+// the j chunks, then the tile times T in LDS.  All workgroups first write the
+// diagonal block and the zero rows.
+__global__ __launch_bounds__(kGemm) void k_blk_newm(double* __restrict__ M, int64_t ldm,
+                                                    const double* __restrict__ W, int64_t ldw,
+                                                    const int32_t* __restrict__ pos,
+                                                    const double* __restrict__ T,
+                                                    const DevScalars* sc) {
+  constexpr int kR = 32;
+  // one LDS buffer: the main loop's tiles, then the epilogue's Z (32 x 65)
+  // and T (64 x 65) over the same space
+  constexpr int kAsz = 2 * kR * (kGK + 1), kBsz = 2 * kGK * (kB + 1);
+  static_assert(kR * (kB + 1) + kB * (kB + 1) <= kAsz + kBsz, "epilogue tiles fit");
+  __shared__ double smem[kAsz + kBsz];
   __shared__ int32_t ps[kB];
+  double(*As)[kR][kGK + 1] = (double(*)[kR][kGK + 1])smem;          // M tile [grp][row][j]
+  double(*Bs)[kGK][kB + 1] = (double(*)[kGK][kB + 1])(smem + kAsz); // W_A^T tile [grp][j][a]
   const int64_t k = sc->n_accept_total;
   const int na = sc->blk_na;
-  const int64_t c0 = (int64_t)blockIdx.x * kB;
-  const int64_t js = blockIdx.y;
-  if (c0 >= k || na == 0) return;
-  double* zp = Zp + js * kB * ldz;
-  const int64_t jlo = max(c0, js * kJSplit), jhi = min(k, (js + 1) * kJSplit);
-  if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
-  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  double acc[4][4] = {};
-  for (int64_t j0 = jlo; j0 < jhi; j0 += kB) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
-      const int a = t / kB, jj = t % kB;
-      const bool jin = j0 + jj < jhi;
-      Ms[jj][a] = (jin && c0 + a < k) ? M[(c0 + a) * ldm + j0 + jj] : 0.0;
-      Wsh[jj][a] = (jin && a < na) ? W[(int64_t)ps[a] * ldw + j0 + jj] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int jj = 0; jj < kB; ++jj) {
-      double x[4], y[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        x[u] = Ms[jj][ty * 4 + u];
-        y[u] = Wsh[jj][tx * 4 + u];
+  if (na == 0 || sc->status != 0) return;
+  // diagonal block and zero rows (grid-stride over all workgroups)
+  {
+    const int64_t tot = (int64_t)na * (k + na);
+    for (int64_t t = (int64_t)blockIdx.x * kGemm + threadIdx.x; t < tot;
+         t += (int64_t)gridDim.x * kGemm) {
+      const int64_t b = t / (k + na), c = t % (k + na);
+      double v = 0.0;
+      if (c >= k) {
+        const int64_t a = c - k;
+        v = b <= a ? T[b * kB + a] : 0.0;
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += x[u] * y[v];
+      M[(k + b) * ldm + c] = v;
     }
   }
+  const int64_t r0 = (int64_t)blockIdx.x * kR;
+  if (r0 >= k) return;
+  if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
+  __syncthreads();
+  const int grp = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
+  const int w = t / kWave, l = lane_id();
+  const int rb = (w / 2) * 16, cb = (w % 2) * 32;
+  const int64_t jbeg = r0;                       // M[c][j] = 0 for j < c
+  const int64_t nch = (k - jbeg + kGK - 1) / kGK;
+  const int64_t iters = (nch + 1) / 2;
+  double ra[kR * kGK / kBlock], rw[kB * kGK / kBlock];
+  auto load = [&](int64_t ch) {
+    const int64_t j0 = jbeg + ch * kGK;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t c = c0 + ty * 4 + u;
-    if (c >= k) continue;
+    for (int u = 0; u < kR * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t, r = idx / kGK, jj = idx % kGK;
+      ra[u] = (ch < nch && j0 + jj < k && r0 + r < k) ? M[(r0 + r) * ldm + j0 + jj] : 0.0;
+    }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = tx * 4 + v;
-      if (a < na) zp[(int64_t)a * ldz + c] = acc[u][v];
+    for (int u = 0; u < kB * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t, a = idx / kGK, jj = idx % kGK;
+      rw[u] = (ch < nch && j0 + jj < k && a < na) ? W[(int64_t)ps[a] * ldw + j0 + jj] : 0.0;
+    }
+  };
+  dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  load(grp);
+  for (int64_t it = 0; it < iters; ++it) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kR * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t;
+      As[grp][idx / kGK][idx % kGK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kB * kGK / kBlock; ++u) {
+      const int idx = u * kBlock + t;
+      Bs[grp][idx % kGK][idx / kGK] = rw[u];
+    }
+    __syncthreads();
+    load(grp + 2 * (it + 1));
+#pragma unroll
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const double av = As[grp][rb + l % 16][ks * 4 + l / 16];
+      const double b0v = Bs[grp][ks * 4 + l / 16][cb + l % 16];
+      const double b1v = Bs[grp][ks * 4 + l / 16][cb + 16 + l % 16];
+      acc0 = mfma16(av, b0v, acc0);
+      acc1 = mfma16(av, b1v, acc1);
     }
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_blk_zsum(const double* __restrict__ Zp, int njs,
-                                                     double* __restrict__ Z, int64_t ldz,
-                                                     const DevScalars* sc) {
-  const int64_t k = sc->n_accept_total;
-  const int na = sc->blk_na;
-  const int64_t total = (int64_t)na * k;
-  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * kBlock) {
-    const int64_t a = t / k, c = t % k;
-    const int js_hi = (int)min((int64_t)njs, (k + kJSplit - 1) / kJSplit);
-    double s = 0.0;
-    for (int js = (int)(c / kJSplit); js < js_hi; ++js) s += Zp[(int64_t)js * kB * ldz + a * ldz + c];
-    Z[a * ldz + c] = s;
-  }
-}
-
-// New columns of M: M[c][k + a] = -sum_{a' <= a} Z[a'][c] T[a'][a] (c < k),
-// M[k + a'][k + a] = T[a'][a] (a' <= a), M[k + a'][c] = 0 below the diagonal.
-__global__ void k_blk_extend_m(double* __restrict__ M, int64_t ldm, const double* __restrict__ Z,
-                               int64_t ldz, const double* __restrict__ T, const DevScalars* sc) {
-  const int64_t k = sc->n_accept_total;
-  const int64_t na = sc->blk_na;
-  if (na == 0) return;
-  const int64_t rows = k + na;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < rows * na;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = t / na, a = t % na;
-    double v;
-    if (c < k) {
-      double s = 0.0;
-      for (int64_t ap = 0; ap <= a; ++ap) s += Z[ap * ldz + c] * T[ap * kB + a];
-      v = -s;
-    } else {
-      const int64_t ap = c - k;
-      v = ap <= a ? T[ap * kB + a] : 0.0;
+  // Z tile = both groups' sums (32 x 64 in LDS), T in LDS, then out = -Z T
+  double(*Zs)[kB + 1] = (double(*)[kB + 1])smem;                         // 32 x 65
+  double(*Ts)[kB + 1] = (double(*)[kB + 1])(smem + kR * (kB + 1));       // 64 x 65
+  __syncthreads();
+  if (grp == 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Zs[rb + l / 16 + 4 * r][cb + l % 16] = acc0[r];
+      Zs[rb + l / 16 + 4 * r][cb + 16 + l % 16] = acc1[r];
     }
-    M[c * ldm + k + a] = v;
   }
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na * k;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ap = t / k, c = t % k;
-    M[(k + ap) * ldm + c] = 0.0;
+  __syncthreads();
+  if (grp == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Zs[rb + l / 16 + 4 * r][cb + l % 16] += acc0[r];
+      Zs[rb + l / 16 + 4 * r][cb + 16 + l % 16] += acc1[r];
+    }
+  }
+  for (int e = threadIdx.x; e < kB * kB; e += kGemm) {
+    const int b = e / kB, a = e % kB;
+    Ts[b][a] = (b < na && a < na) ? T[e] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kR * kB; e += kGemm) {
+    const int r = e / kB, a = e % kB;
+    const int64_t c = r0 + r;
+    if (c >= k || a >= na) continue;
+    double s2 = 0.0;
+    for (int b = 0; b <= a; ++b) s2 += Zs[r][b] * Ts[b][a];
+    M[c * ldm + k + a] = -s2;
   }
 }
 
@@ -961,26 +986,21 @@ __global__ __launch_bounds__(kBlock) void k_lev(const double* __restrict__ Q, in
 }  // namespace
 
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
-  const int64_t njs = (cap + kJSplit - 1) / kJSplit;
   return (size_t)kB * cap            // W
          + (size_t)kSplitW * kB * cap + (size_t)kB * cap   // W2p, W2
-         + (size_t)njs * kB * cap    // Zp
          + (size_t)kSplit * kB * kB  // part
          + (size_t)kSplitDD * kB * kB * 2 + (size_t)kB * kB  // part_hi/lo, G_lo
          + (size_t)kB * kB * 3       // G, Tcur, Tacc
          + kB                        // g
-         + (size_t)kB * cap          // Z
          + (size_t)kB * n_rows       // Ybuf
          + 64;                       // pos
 }
 
 void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
-  const int njs = div_up(a.cap, kJSplit);
   double* W = a.scratch;
   double* W2p = W + (size_t)kB * a.cap;
   double* W2 = W2p + (size_t)kSplitW * kB * a.cap;
-  double* Zp = W2 + (size_t)kB * a.cap;
-  double* part = Zp + (size_t)njs * kB * a.cap;
+  double* part = W2 + (size_t)kB * a.cap;
   double* part_hi = part + (size_t)kSplit * kB * kB;
   double* part_lo = part_hi + (size_t)kSplitDD * kB * kB;
   double* Glo = part_lo + (size_t)kSplitDD * kB * kB;
@@ -988,14 +1008,11 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
   double* Tcur = G + kB * kB;
   double* Tacc = Tcur + kB * kB;
   double* g = Tacc + kB * kB;
-  double* Z = g + kB;
-  double* Ybuf = Z + (size_t)kB * a.cap;
+  double* Ybuf = g + kB;
   int32_t* pos = (int32_t*)(Ybuf + (size_t)kB * a.n_rows);
   const int wchunks = std::max(1, div_up(a.cap, kWCols));
   const int rows_tiles32 = div_up(a.n_rows, 32);
   const int rows4 = div_up(a.n_rows, kB);
-  const int cross_tiles = div_up(a.cap, kB);
-  const int ext_grid = std::max(1, std::min(4096, div_up((a.cap + kB) * kB, 256)));
   hipLaunchKernelGGL(k_begin_basis, dim3(1), dim3(1), 0, st, sc);
   for (int64_t b0 = 0; b0 < a.s_max; b0 += kB) {
     hipLaunchKernelGGL(k_blk_w, dim3(wchunks, kB), dim3(kWWaves * kWave), 0, st, a.Q, a.ldq,
@@ -1024,12 +1041,8 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
     hipLaunchKernelGGL(k_blk_cholinv, dim3(1), dim3(kChol), 0, st, G, Tcur, Tacc, sc);
     hipLaunchKernelGGL(k_blk_apply, dim3(rows4), dim3(kBlock), 0, st, a.Q, a.ldq, a.n_rows, Tcur,
                        sc);
-    hipLaunchKernelGGL(k_blk_cross, dim3(cross_tiles, njs), dim3(kBlock), 0, st, a.M, a.ldm, W,
-                       a.cap, pos, Zp, a.cap, sc);
-    hipLaunchKernelGGL(k_blk_zsum, dim3(std::max(1, std::min(1024, div_up((int64_t)kB * a.cap, kBlock)))),
-                       dim3(kBlock), 0, st, Zp, njs, Z, a.cap, sc);
-    hipLaunchKernelGGL(k_blk_extend_m, dim3(ext_grid), dim3(256), 0, st, a.M, a.ldm, Z, a.cap, Tacc,
-                       sc);
+    hipLaunchKernelGGL(k_blk_newm, dim3(std::max(1, div_up(a.cap, 32))), dim3(kGemm), 0, st, a.M,
+                       a.ldm, W, a.cap, pos, Tacc, sc);
     hipLaunchKernelGGL(k_blk_finish, dim3(1), dim3(256), 0, st, pos, b0, a.uniq_fi, a.uniq_fid,
                        a.id_offset, a.acc_fid, a.acc_fi_local, a.fiber_mark, W, a.cap, a.Wacc,
                        a.ldwa, sc);
