@@ -31,7 +31,8 @@ S_DRAWS = 2000
 SEED = 0
 GOLD = os.path.join(ROOT, "tests", "golden", "traffic_5m_s2000_seed0.npz")
 TRAFFIC = os.path.join(ROOT, "profiles", "k_proj_multi_traffic5m_s2000_pmc.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1710_03608_amd", "csrc", "project.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1710_03608_amd", "csrc", "project.hip"),
+              os.path.join(ROOT, "paper_1710_03608_amd", "csrc", "gather.h")]
 COPY_BYTES = 512 << 20   # plain device copy used to calibrate the HBM byte counters
 
 
@@ -137,12 +138,13 @@ def calibrate_copy():
 
 
 def measured_traffic():
-    """HBM bytes per k_proj_multi launch from the committed rocprofv3 counter summary, or None
-    when the summary is missing or the kernel source changed since the counters were taken."""
+    """HBM bytes of one projection SpMM (k_proj_multi + k_proj_long + k_proj_long_fin) from the
+    committed rocprofv3 counter summary, or None when the summary is missing or the kernel
+    sources changed since the counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC).read()
-        digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        digest = hashlib.sha256(b"".join(open(p, "rb").read() for p in KERNEL_SRC)).hexdigest()
     except OSError:
         return None
     vals = {}
@@ -282,7 +284,8 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak,
                 "traffic": measured_traffic() if main_mode == "fp64" else None,
-                "kernel": "k_proj_multi (A8: z_f = Q^T x_f over fibers with >= 2 nonzeros)",
+                "kernel": ("projection SpMM: k_proj_multi + k_proj_long + k_proj_long_fin "
+                           "(z_f = Q^T x_f over fibers with >= 2 nonzeros)"),
                 "work": f"2 * s~ ({s_t}) * nnz in multi-nonzero fibers ({stats['nnz_multi']})",
                 "kernel_ms": spmm_ms}
     # end-to-end algorithmic HBM bytes of one decomposition (float64): COO read
