@@ -24,7 +24,7 @@ namespace ctd {
 
 namespace {
 constexpr int kB = 64;        // candidates per block
-constexpr int kSplit = 64;    // row splits of the 64 x 64 Gram products
+constexpr int kTakeParts = 256;   // workgroups of k_blk_take: partial Grams of the new columns
 constexpr int kBlock = 256;
 
 
@@ -69,22 +69,19 @@ __device__ inline void dd_fnma(double& ah, double& al, double bh, double bl, dou
   se += al - pe;
   quick_two_sum(s, se, ah, al);
 }
-__device__ inline void dd_sqrt(double ah, double al, double& sh, double& sl) {
+// (rh, rl) = 1 / sqrt(ah + al) for ah > 0: one Newton step in double-double
+// from the double estimate r0, r = r0 + r0 (1 - a r0^2) / 2, with a r0^2
+// formed exactly enough that 1 - a r0^2 is accurate to about u^2.
+__device__ inline void dd_rsqrt(double ah, double al, double& rh, double& rl) {
 #pragma clang fp contract(off)
-  const double s = sqrt(ah);
-  double p, pe;
-  two_prod(s, s, p, pe);
-  const double r = ((ah - p) - pe) + al;
-  quick_two_sum(s, r / (2.0 * s), sh, sl);
-}
-__device__ inline void dd_div(double ah, double al, double bh, double bl, double& qh, double& ql) {
-#pragma clang fp contract(off)
-  const double q1 = ah / bh;
-  double p, pe;
-  two_prod(q1, bh, p, pe);
-  pe = fma(q1, bl, pe);
-  const double r = ((ah - p) - pe) + al;
-  quick_two_sum(q1, r / bh, qh, ql);
+  const double r0 = rsqrt(ah);
+  double t, te, p, pe;
+  two_prod(r0, r0, t, te);
+  two_prod(ah, t, p, pe);
+  pe = fma(ah, te, pe);
+  pe = fma(al, t, pe);
+  const double e = (1.0 - p) - pe;
+  quick_two_sum(r0, r0 * e * 0.5, rh, rl);
 }
 
 __device__ inline int64_t blk_count(const DevScalars* sc, int64_t b0) {
@@ -357,53 +354,13 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const double* __restrict_
   }
 }
 
-// 64 x 64 Gram of the columns of Y, partial over kSplit row ranges:
-//   part[s][i][j] = sum_{r in range s} Y[r][col0 + i] Y[r][col0 + j]
-// mode 0: Y = the block buffer (col0 = 0, width = candidates of the block)
-// mode 1: Y = Q[:, k : k + na]   (the kept block after its first pass)
-// Wave w computes rows 16 w .. + 16 of the 64 x 64 result (four MFMA tiles).
-__global__ __launch_bounds__(kBlock) void k_blk_gram_part(const double* __restrict__ A, int64_t lda,
-                                                          int64_t K, int mode, int64_t b0,
-                                                          double* __restrict__ part,
-                                                          const DevScalars* sc) {
-  constexpr int kK = 64;
-  __shared__ double Ys[kK][kB + 1];   // [row][col]
-  const int64_t col0 = mode == 0 ? 0 : (int64_t)sc->n_accept_total;
-  const int64_t width = mode == 0 ? blk_count(sc, b0) : (int64_t)sc->blk_na;
-  if (width == 0) return;  // nothing downstream reads part for an empty block
-  const int64_t chunk = (K + kSplit - 1) / kSplit;
-  const int64_t k0 = blockIdx.x * chunk;
-  const int64_t k1 = min(K, k0 + chunk);
-  const int w = threadIdx.x / kWave, l = lane_id();
-  dbl4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int64_t kk0 = k0; kk0 < k1; kk0 += kK) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < kK * kB; t += kBlock) {
-      const int kk = t / kB, i = t % kB;
-      Ys[kk][i] = (kk0 + kk < k1 && i < width) ? A[(kk0 + kk) * lda + col0 + i] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kK / 4; ++ks) {
-      const double a = Ys[ks * 4 + l / 16][w * 16 + l % 16];   // A = Y^T: A[i][kk] = Y[kk][i]
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = mfma16(a, Ys[ks * 4 + l / 16][q * 16 + l % 16], acc[q]);
-    }
-  }
-  double* p = part + (int64_t)blockIdx.x * kB * kB;
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) p[(w * 16 + l / 16 + 4 * r) * kB + q * 16 + l % 16] = acc[q][r];
-}
-
 // Double-double Gram of the block buffer, partial over kSplitDD row ranges:
 // (hi, lo)[s][i][j] = sum_{r in range s} Y[r][i] Y[r][j], each product split
 // exactly by an FMA and accumulated with two_sum.  The independence decisions
 // need the block Gram to about u^2: rounding it to float64 alone moves the
 // Schur complement of an exactly dependent candidate to ~u * cond^2 ||x||^2,
 // which can reach eps^2 ||x||^2.
-constexpr int kSplitDD = 128;
+constexpr int kSplitDD = 256;
 __global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const double* __restrict__ Y,
                                                         int64_t n_rows, int64_t b0,
                                                         double* __restrict__ part_hi,
@@ -457,44 +414,69 @@ __global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const double* __restrict
     }
 }
 
+// G = sum over the kSplitDD partial Grams in double-double: a workgroup takes
+// kBlock / kSumWays consecutive elements, kSumWays threads per element each
+// summing every kSumWays-th partial (neighbouring lanes read neighbouring
+// elements), and the kSumWays sums are added in a fixed order.
+constexpr int kSumWays = 16;
 __global__ __launch_bounds__(kBlock) void k_blk_sum_dd(const double* __restrict__ part_hi,
                                                        const double* __restrict__ part_lo,
                                                        double* __restrict__ G_hi,
                                                        double* __restrict__ G_lo, int64_t b0,
                                                        const DevScalars* sc) {
+  __shared__ double sh[kBlock], sl[kBlock];
   if (blk_count(sc, b0) == 0) return;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= kB * kB) return;
+  constexpr int kPer = kBlock / kSumWays;
+  const int e = threadIdx.x % kPer, q = threadIdx.x / kPer;
+  const int t = blockIdx.x * kPer + e;
   double h = 0.0, l = 0.0;
-  for (int p = 0; p < kSplitDD; ++p) {
-    double s2, e;
-    two_sum(h, part_hi[(int64_t)p * kB * kB + t], s2, e);
-    h = s2;
-    l += e + part_lo[(int64_t)p * kB * kB + t];
+  if (t < kB * kB) {
+    for (int p = q; p < kSplitDD; p += kSumWays) {
+      double s2, er;
+      two_sum(h, part_hi[(int64_t)p * kB * kB + t], s2, er);
+      h = s2;
+      l += er + part_lo[(int64_t)p * kB * kB + t];
+    }
   }
-  quick_two_sum(h, l, G_hi[t], G_lo[t]);
+  sh[threadIdx.x] = h;
+  sl[threadIdx.x] = l;
+  __syncthreads();
+  if (q == 0 && t < kB * kB) {
+    for (int j = 1; j < kSumWays; ++j) {
+      double s2, er;
+      two_sum(h, sh[j * kPer + e], s2, er);
+      h = s2;
+      l += er + sl[j * kPer + e];
+    }
+    quick_two_sum(h, l, G_hi[t], G_lo[t]);
+  }
 }
 
 // G[i][j] = sum_s part[s][i][j] in a fixed order (deterministic).
 __global__ __launch_bounds__(kBlock) void k_blk_sum_parts(const double* __restrict__ part,
-                                                          double* __restrict__ G, int mode,
-                                                          int64_t b0, const DevScalars* sc) {
-  const int64_t width = mode == 0 ? blk_count(sc, b0) : (int64_t)sc->blk_na;
-  if (width == 0) return;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= kB * kB) return;
+                                                          int nparts, double* __restrict__ G,
+                                                          const DevScalars* sc) {
+  __shared__ double sh[kBlock];
+  if (sc->blk_na == 0) return;
+  constexpr int kPer = kBlock / kSumWays;
+  const int e = threadIdx.x % kPer, q = threadIdx.x / kPer;
+  const int t = blockIdx.x * kPer + e;
   double s = 0.0;
-  for (int p = 0; p < kSplit; ++p) s += part[(int64_t)p * kB * kB + t];
-  G[t] = s;
+  if (t < kB * kB)
+    for (int p = q; p < nparts; p += kSumWays) s += part[(int64_t)p * kB * kB + t];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (q == 0 && t < kB * kB) {
+    for (int j = 1; j < kSumWays; ++j) s += sh[j * kPer + e];
+    G[t] = s;
+  }
 }
 
-// The 64 x 64 factorizations run in one workgroup of kChol threads with the
-// matrix in LDS: a right-looking Cholesky (step j scales column j, then every
-// thread updates its share of the trailing triangle) and a forward sweep for
-// L^{-1}.  Loops stay rolled so that the code fits the instruction cache.
+// The 64 x 64 factorizations run in one workgroup of kChol threads: a
+// right-looking Cholesky that builds L^{-1} in the same sweep, the matrix held
+// in registers (kSlots columns per wave, one row per lane).
 constexpr int kChol = 1024;
-constexpr int kRowsPer = kChol / kB;   // rows per thread slot group
-constexpr int kSlots = kB / kRowsPer;   // elements held per thread
+constexpr int kSlots = kB / (kChol / kWave);   // columns held per wave
 typedef double LdsMat[kB][kB + 1];
 
 // (ah, al) *= (bh, bl)
@@ -509,95 +491,100 @@ __device__ inline void dd_mul(double& ah, double& al, double bh, double bl) {
 
 // Cholesky of the leading n x n block of A (lower triangle, A[i][c] for
 // c <= i, zeros above; double-double when Al != nullptr) in candidate order,
-// producing X = L^{-1} in place of A.  Thread t holds column t % 64 of rows
-// t / 64 + 16 q (q < 4) in registers.  Step j (right-looking): the pivot and
-// the scaled column j of L are broadcast through LDS together with row j of
-// X (scaled by 1 / L[j][j]); entries right of column j take the Schur update
-// A[i][c] -= L[i][j] L[c][j], entries at or left of it take the elimination
-// X[i][c] -= L[i][j] X[j][c].  Entry (i, j) turns from A into X at step j.
-// With drop set, candidate j is kept iff its pivot exceeds eps2 * gs[j] and
-// fewer than `room` are kept so far; a dropped candidate gets an identity row
-// and a zero column in X, so X restricted to the kept set is the inverse of
-// the kept factor.  X goes to LDS; returns the kept mask (same in every
-// thread).
+// producing X = L^{-1} in place of A.  Lane i of wave w holds row i of
+// columns w + 16 q (q < 4) in registers, so whether a held column is left of,
+// at or right of the step's column is the same for the whole wave.  Step j
+// (right-looking): column j of A below the diagonal, row j of X left of it and
+// the pivot decision with 1 / L[j][j] arrive through LDS from the end of step
+// j - 1; each lane scales what it needs itself (L[i][j] = A[i][j] / L[j][j],
+// and per held column L[c][j] or X[j][c] = X'[j][c] / L[j][j]), so each step
+// needs a single barrier.  Columns right of j take the Schur update A[i][c] -=
+// L[i][j] L[c][j] (i >= c), columns at or left of it the elimination X[i][c]
+// -= L[i][j] X[j][c]; entry (i, j) turns from A into X at step j.  The owners
+// of column j + 1, row j + 1 and entry (j + 1, j + 1) then publish them into
+// the other half of the double-buffered exchange arrays (ch, cl, xrow:
+// 2 x 64; piv: 2 x 4).  With drop set, candidate j is kept iff its pivot
+// exceeds eps2 * gs[j] and fewer than `room` are kept so far; a dropped
+// candidate gets an identity row and a zero column in X, so X restricted to
+// the kept set is the inverse of the kept factor.  X goes to LDS; returns the
+// kept mask (same in every thread).
 template <bool kDD>
 __device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, double* ch,
                                 double* cl, double* xrow, double* piv, const double* gs, int n,
                                 bool drop, double eps2, int64_t room) {
-  const int tid = threadIdx.x, c = tid % kB, i0 = tid / kB;
+  constexpr int kWaves = kChol / kWave;
+  const int i = threadIdx.x % kWave, w = threadIdx.x / kWave;
   double ah[kSlots], al[kSlots];
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {
-    ah[q] = Ah[i0 + kRowsPer * q][c];
-    al[q] = kDD ? (*Al)[i0 + kRowsPer * q][c] : 0.0;
+    ah[q] = Ah[i][w + kWaves * q];
+    al[q] = kDD ? (*Al)[i][w + kWaves * q] : 0.0;
   }
-  // The owner of diagonal entry (j, j) decides candidate j and broadcasts
-  // piv = {keep, L[j][j] (hi, lo), 1 / L[j][j] (hi, lo)}.
-  auto publish = [&](double dh, double dl, int j, int kept) {
+  // The owner of diagonal entry (j, j) decides candidate j and publishes
+  // {keep, 1 / L[j][j] (hi, lo)}.
+  auto publish = [&](double dh, double dl, int j, int kept, double* pv) {
     const bool keep = !drop || (((dh - eps2 * gs[j]) + dl > 0.0) && kept < room);
-    double lh = 0.0, ll = 0.0, rh = 0.0, rl = 0.0;
+    double rh = 0.0, rl = 0.0;
     if (keep) {
-      if (kDD) {
-        dd_sqrt(dh, dl, lh, ll);
-        dd_div(1.0, 0.0, lh, ll, rh, rl);
-      } else {
-        lh = sqrt(fmax(dh, 1e-300));
-        rh = 1.0 / lh;
-      }
+      if (kDD)
+        dd_rsqrt(dh, dl, rh, rl);
+      else
+        rh = 1.0 / sqrt(fmax(dh, 1e-300));
     }
-    piv[0] = keep ? 1.0 : 0.0;
-    piv[1] = lh;
-    piv[2] = ll;
-    piv[3] = rh;
-    piv[4] = rl;
+    pv[0] = keep ? 1.0 : 0.0;
+    pv[1] = rh;
+    pv[2] = rl;
   };
-  if (tid == 0 && n > 0) publish(ah[0], al[0], 0, 0);
+  if (n > 0 && w == 0) {   // column 0 is slot 0 of wave 0
+    if (i > 0 && i < n) {
+      ch[i] = ah[0];
+      cl[i] = al[0];
+    }
+    if (i == 0) publish(ah[0], al[0], 0, 0, piv);
+  }
   __syncthreads();
   uint64_t mask = 0;
   int kept = 0;
   for (int j = 0; j < n; ++j) {
-    const bool keep = piv[0] != 0.0;
+    const int pb = (j & 1) * kB, nb = kB - pb;
+    const double* pv = piv + (j & 1) * 4;
+    const bool keep = pv[0] != 0.0;
     if (keep) {
-      const double lh = piv[1], ll = piv[2], rh = piv[3], rl = piv[4];
-#pragma unroll
-      for (int q = 0; q < kSlots; ++q) {
-        const int i = i0 + kRowsPer * q;
-        if (c == j) {
-          if (i > j && i < n) {          // L[i][j]
-            if (kDD)
-              dd_mul(ah[q], al[q], rh, rl);
-            else
-              ah[q] *= rh;
-            ch[i] = ah[q];
-            cl[i] = al[q];
-          } else if (i == j) {           // X[j][j]
-            ah[q] = rh;
-            xrow[j] = rh;
-          }
-        } else if (c < j && i == j) {    // row j of X
-          ah[q] *= rh;
-          xrow[c] = ah[q];
-        }
+      const double rh = pv[1], rl = pv[2];
+      double lih = 0.0, lil = 0.0;   // L[i][j]
+      if (i > j && i < n) {
+        lih = ch[pb + i];
+        lil = cl[pb + i];
+        if (kDD)
+          dd_mul(lih, lil, rh, rl);
+        else
+          lih *= rh;
       }
-      (void)lh;
-      (void)ll;
-      __syncthreads();
-      const double cch = ch[c], ccl = cl[c], xr = xrow[c < j ? c : j];
 #pragma unroll
       for (int q = 0; q < kSlots; ++q) {
-        const int i = i0 + kRowsPer * q;
-        if (i >= n || i <= j) continue;
-        if (c > j) {
-          if (i >= c) {
-            if (kDD)
-              dd_fnma(ah[q], al[q], ch[i], cl[i], cch, ccl);
-            else
-              ah[q] -= ch[i] * cch;
+        const int c = w + kWaves * q;
+        if (c >= n) continue;
+        if (c > j) {                     // Schur update of A, rows i >= c
+          if (i >= c && i < n) {
+            double lch = ch[pb + c], lcl = cl[pb + c];   // L[c][j]
+            if (kDD) {
+              dd_mul(lch, lcl, rh, rl);
+              dd_fnma(ah[q], al[q], lih, lil, lch, lcl);
+            } else {
+              ah[q] -= lih * (lch * rh);
+            }
           }
         } else if (c == j) {
-          ah[q] = -ah[q] * xr;           // X[i][j] = -L[i][j] X[j][j]
+          if (i == j)
+            ah[q] = rh;                  // X[j][j]
+          else if (i > j && i < n)
+            ah[q] = -lih * rh;           // X[i][j] = -L[i][j] X[j][j]
         } else {
-          ah[q] -= ch[i] * xr;           // X[i][c] -= L[i][j] X[j][c]
+          const double xr = xrow[pb + c] * rh;   // X[j][c]
+          if (i == j)
+            ah[q] = xr;
+          else if (i > j && i < n)
+            ah[q] -= lih * xr;           // X[i][c] -= L[i][j] X[j][c]
         }
       }
       ++kept;
@@ -605,20 +592,31 @@ __device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, d
     } else {
 #pragma unroll
       for (int q = 0; q < kSlots; ++q) {
-        const int i = i0 + kRowsPer * q;
+        const int c = w + kWaves * q;
         if ((c == j && i >= j) || (c < j && i == j)) ah[q] = (i == c) ? 1.0 : 0.0;
       }
-      __syncthreads();   // every thread has read piv
     }
-    if (c == j + 1 && j + 1 < n) {
+    const int j1 = j + 1;
+    if (j1 < n) {
 #pragma unroll
-      for (int q = 0; q < kSlots; ++q)
-        if (i0 + kRowsPer * q == j + 1) publish(ah[q], al[q], j + 1, kept);
+      for (int q = 0; q < kSlots; ++q) {
+        const int c = w + kWaves * q;
+        if (c == j1) {
+          if (i > j1 && i < n) {
+            ch[nb + i] = ah[q];
+            cl[nb + i] = al[q];
+          } else if (i == j1) {
+            publish(ah[q], al[q], j1, kept, piv + (j1 & 1) * 4);
+          }
+        } else if (c < j1 && i == j1) {
+          xrow[nb + c] = ah[q];
+        }
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < kSlots; ++q) X[i0 + kRowsPer * q][c] = ah[q];
+  for (int q = 0; q < kSlots; ++q) X[i][w + kWaves * q] = ah[q];
   __syncthreads();
   return mask;
 }
@@ -636,7 +634,7 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__
                                                       double* __restrict__ Tacc,
                                                       DevScalars* sc) {
   __shared__ LdsMat Ah, Al, X;
-  __shared__ double ch[kB], cl[kB], xrow[kB], gs[kB], piv[5];
+  __shared__ double ch[2 * kB], cl[2 * kB], xrow[2 * kB], gs[kB], piv[8];
   __shared__ int32_t ps[kB];
   const int64_t nb = blk_count(sc, b0);
   const int tid = threadIdx.x;
@@ -684,7 +682,7 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict_
                                                        double* __restrict__ Tacc,
                                                        DevScalars* sc) {
   __shared__ LdsMat L, X, Ta;
-  __shared__ double ch[kB], cl[kB], xrow[kB], piv[5];
+  __shared__ double ch[2 * kB], cl[2 * kB], xrow[2 * kB], piv[8];
   __shared__ int any_off;
   const int na = sc->blk_na;
   const int tid = threadIdx.x;
@@ -722,49 +720,73 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict_
 
 // Kept residuals times the first-pass factor: Q[r][k + a] = sum_{a' <= a}
 // Ybuf[r][pos[a']] T[a'][a]; R[r][k + a] = P[r][b0 + pos[a]].  A workgroup
-// stages 64 rows of Ybuf in LDS; four threads per row, 16 outputs each.
+// walks 64-row tiles with a stride of the grid (four threads per row, 16
+// outputs each) and accumulates the Gram of its new rows of Q with f64 MFMAs
+// (wave w: Gram rows 16 w .. + 16); the sum over its tiles goes to
+// part[blockIdx.x] for the orthogonality check of the block.
 __global__ __launch_bounds__(kBlock) void k_blk_take(const double* __restrict__ Ybuf,
                                                      const double* __restrict__ P, int64_t ldp,
                                                      int64_t n_rows, const int32_t* __restrict__ pos,
                                                      const double* __restrict__ T, int64_t b0,
                                                      double* __restrict__ Q, int64_t ldq,
                                                      double* __restrict__ R, int64_t ldr,
+                                                     double* __restrict__ part,
                                                      const DevScalars* sc) {
   __shared__ double Ts[kB][kB + 1];
-  __shared__ double Ys[kB][kB + 1];
+  __shared__ double Ys[kB][kB + 1];   // Ybuf rows, then the new Q rows
   __shared__ int32_t ps[kB];
   const int na = sc->blk_na;
   if (na == 0) return;
   const int64_t k = sc->n_accept_total;
-  const int64_t r0 = (int64_t)blockIdx.x * kB;
-  for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
-    Ts[t / kB][t % kB] = T[t];
-    const int64_t rr = r0 + t / kB;
-    Ys[t / kB][t % kB] = rr < n_rows ? Ybuf[rr * kB + t % kB] : 0.0;
-  }
+  for (int t = threadIdx.x; t < kB * kB; t += kBlock) Ts[t / kB][t % kB] = T[t];
   if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
-  __syncthreads();
   const int rl = threadIdx.x / 4;
-  const int64_t r = r0 + rl;
   const int a_lo = (threadIdx.x % 4) * 16;
-  if (r >= n_rows || a_lo >= na) return;
-  double out[16];
+  const int w = threadIdx.x / kWave, l = lane_id();
+  dbl4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < n_rows; r0 += (int64_t)gridDim.x * kB) {
+    __syncthreads();   // previous tile's Gram reads of Ys done (and Ts, ps written)
+    for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
+      const int64_t rr = r0 + t / kB;
+      Ys[t / kB][t % kB] = rr < n_rows ? Ybuf[rr * kB + t % kB] : 0.0;
+    }
+    __syncthreads();
+    const int64_t r = r0 + rl;
+    double out[16];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) out[u] = 0.0;
-  for (int ap = 0; ap < na; ++ap) {
-    const double y = Ys[rl][ps[ap]];
+    for (int u = 0; u < 16; ++u) out[u] = 0.0;
+    for (int ap = 0; ap < na; ++ap) {
+      const double y = Ys[rl][ps[ap]];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) out[u] += y * Ts[ap][a_lo + u];
-  }
-  double* q = Q + r * ldq + k;
+      for (int u = 0; u < 16; ++u) out[u] += y * Ts[ap][a_lo + u];
+    }
+    const bool live = r < n_rows;
+    double* q = Q + r * ldq + k;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int a = a_lo + u;
-    if (a < na) {
-      q[a] = out[u];
-      if (R) R[r * ldr + k + a] = P[r * ldp + b0 + ps[a]];
+    for (int u = 0; u < 16; ++u) {
+      const int a = a_lo + u;
+      if (live && a < na) {
+        q[a] = out[u];
+        if (R) R[r * ldr + k + a] = P[r * ldp + b0 + ps[a]];
+      }
+    }
+    __syncthreads();   // all reads of Ys done
+#pragma unroll
+    for (int u = 0; u < 16; ++u) Ys[rl][a_lo + u] = (live && a_lo + u < na) ? out[u] : 0.0;
+    __syncthreads();
+    // acc[i][j] += sum_r Qn[r][i] Qn[r][j] over this tile
+#pragma unroll
+    for (int ks = 0; ks < kB / 4; ++ks) {
+      const double av = Ys[ks * 4 + l / 16][w * 16 + l % 16];   // A[i][r] = Qn[r][i]
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) acc[qq] = mfma16(av, Ys[ks * 4 + l / 16][qq * 16 + l % 16], acc[qq]);
     }
   }
+  double* pp = part + (int64_t)blockIdx.x * kB * kB;
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) pp[(w * 16 + l / 16 + 4 * rr) * kB + qq * 16 + l % 16] = acc[qq][rr];
 }
 
 // Q[r][k + a] <- sum_{a' <= a} Q[r][k + a'] T[a'][a]; rows staged in LDS.
@@ -988,7 +1010,7 @@ __global__ __launch_bounds__(kBlock) void k_lev(const double* __restrict__ Q, in
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
   return (size_t)kB * cap            // W
          + (size_t)kSplitW * kB * cap + (size_t)kB * cap   // W2p, W2
-         + (size_t)kSplit * kB * kB  // part
+         + (size_t)kTakeParts * kB * kB  // part
          + (size_t)kSplitDD * kB * kB * 2 + (size_t)kB * kB  // part_hi/lo, G_lo
          + (size_t)kB * kB * 3       // G, Tcur, Tacc
          + kB                        // g
@@ -1001,7 +1023,7 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
   double* W2p = W + (size_t)kB * a.cap;
   double* W2 = W2p + (size_t)kSplitW * kB * a.cap;
   double* part = W2 + (size_t)kB * a.cap;
-  double* part_hi = part + (size_t)kSplit * kB * kB;
+  double* part_hi = part + (size_t)kTakeParts * kB * kB;
   double* part_lo = part_hi + (size_t)kSplitDD * kB * kB;
   double* Glo = part_lo + (size_t)kSplitDD * kB * kB;
   double* G = Glo + kB * kB;
@@ -1013,6 +1035,7 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
   const int wchunks = std::max(1, div_up(a.cap, kWCols));
   const int rows_tiles32 = div_up(a.n_rows, 32);
   const int rows4 = div_up(a.n_rows, kB);
+  const int ntake = std::max(1, std::min(kTakeParts, rows4));
   hipLaunchKernelGGL(k_begin_basis, dim3(1), dim3(1), 0, st, sc);
   for (int64_t b0 = 0; b0 < a.s_max; b0 += kB) {
     hipLaunchKernelGGL(k_blk_w, dim3(wchunks, kB), dim3(kWWaves * kWave), 0, st, a.Q, a.ldq,
@@ -1028,16 +1051,14 @@ void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
                        a.Q, a.ldq, W2, a.cap, b0, Ybuf, true, sc);
     hipLaunchKernelGGL(k_blk_gram_dd, dim3(kSplitDD), dim3(kBlock), 0, st, Ybuf, a.n_rows, b0,
                        part_hi, part_lo, sc);
-    hipLaunchKernelGGL(k_blk_sum_dd, dim3(kB * kB / kBlock), dim3(kBlock), 0, st, part_hi, part_lo,
+    hipLaunchKernelGGL(k_blk_sum_dd, dim3(kB * kB * kSumWays / kBlock), dim3(kBlock), 0, st, part_hi, part_lo,
                        G, Glo, b0, sc);
     hipLaunchKernelGGL(k_blk_decide, dim3(1), dim3(kChol), 0, st, G, Glo, g, a.eps2, b0, a.n_rows,
                        pos, a.accept, Tacc, sc);
-    hipLaunchKernelGGL(k_blk_take, dim3(rows4), dim3(kBlock), 0, st, Ybuf, a.P, a.ldp, a.n_rows,
-                       pos, Tacc, b0, a.Q, a.ldq, a.R, a.ldr, sc);
-    hipLaunchKernelGGL(k_blk_gram_part, dim3(kSplit), dim3(kBlock), 0, st, a.Q, a.ldq, a.n_rows,
-                       1, b0, part, sc);
-    hipLaunchKernelGGL(k_blk_sum_parts, dim3(kB * kB / kBlock), dim3(kBlock), 0, st, part, G, 1, b0,
-                       sc);
+    hipLaunchKernelGGL(k_blk_take, dim3(ntake), dim3(kBlock), 0, st, Ybuf, a.P, a.ldp, a.n_rows,
+                       pos, Tacc, b0, a.Q, a.ldq, a.R, a.ldr, part, sc);
+    hipLaunchKernelGGL(k_blk_sum_parts, dim3(kB * kB * kSumWays / kBlock), dim3(kBlock), 0, st, part,
+                       ntake, G, sc);
     hipLaunchKernelGGL(k_blk_cholinv, dim3(1), dim3(kChol), 0, st, G, Tcur, Tacc, sc);
     hipLaunchKernelGGL(k_blk_apply, dim3(rows4), dim3(kBlock), 0, st, a.Q, a.ldq, a.n_rows, Tcur,
                        sc);
