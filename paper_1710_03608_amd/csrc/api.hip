@@ -113,16 +113,17 @@ ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout*
 // row segment (4 float64 or 8 float32 columns) never crosses a row end.
 int64_t round8(int64_t x) { return (x + 7) & ~int64_t(7); }
 
-// Plan the workspace of one CTD-S call (or one CTD-D slice) and bind pointers.
-ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
-                       bool want_C, int64_t max_cols, StaticBufs* b) {
-  Arena& A = h->arena;
-  A.reset();
+namespace {
+struct PlanItem {
+  void** p;
+  size_t bytes;
+};
+// The workspace of one CTD-S call (or one CTD-D slice), as a list of buffers.
+void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C,
+                  int64_t max_cols, StaticBufs* b, std::vector<PlanItem>& items) {
   const int64_t n = std::max<int64_t>(nnz, 1);
   const int64_t ld = round8(s);
   const int64_t nb = (int64_t)segment_blocks(nnz);
-  struct Item { void** p; size_t bytes; };
-  std::vector<Item> items;
   auto add = [&](void* pp, size_t bytes) { items.push_back({(void**)pp, bytes}); };
   add(&b->keys, 2 * n * 8);
   add(&b->perm, 2 * n * 4);
@@ -160,6 +161,28 @@ ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bo
   add(&b->partial, ((n + 8191) / 8192 + 1) * 8);
   add(&b->Rs, n_rows * ld * 8);
   add(&b->C, want_C ? (size_t)ld * n * 8 : 8);
+}
+}  // namespace
+
+size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C,
+                    int64_t max_cols) {
+  StaticBufs tmp{};
+  std::vector<PlanItem> items;
+  static_items(nnz, s, n_rows, mixed, want_C, max_cols, &tmp, items);
+  Arena A;
+  for (auto& it : items) (void)A.take(it.bytes);
+  return A.off;
+}
+
+// Plan the workspace of one CTD-S call (or one CTD-D slice) and bind pointers.
+ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
+                       bool want_C, int64_t max_cols, StaticBufs* b) {
+  Arena& A = h->arena;
+  A.reset();
+  const int64_t ld = round8(s);
+  const int64_t long_ld = std::max<int64_t>(1, (std::max(max_cols, ld) + kChunkCols - 1) / kChunkCols);
+  std::vector<PlanItem> items;
+  static_items(nnz, s, n_rows, mixed, want_C, max_cols, b, items);
   std::vector<size_t> offs;
   for (auto& it : items) offs.push_back((size_t)A.take(it.bytes));
   if (A.off > A.cap) {
@@ -274,10 +297,28 @@ ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const fl
 
 namespace ctd {
 
-// Enqueue CTD-S on `lay`/`X`; draws either sampled (given == nullptr, Philox
-// counter word `tensor`) or given.
-ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
-                      uint64_t seed, const uint64_t* given, uint32_t tensor) {
+// Device array of basis arguments for up to `count` inputs.
+ctd_status ensure_bdev(ctd_handle* h, int count) {
+  if (h->bdev && h->bdev_cap >= count) return CTD_OK;
+  if (h->bdev) {
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    (void)hipFree(h->bdev);
+    h->bdev = nullptr;
+    h->bdev_cap = 0;
+  }
+  if (hipMalloc(&h->bdev, basis_dev_bytes(count)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, CTD_ERR_OOM, "basis argument array allocation failed");
+  }
+  h->bdev_cap = count;
+  return CTD_OK;
+}
+
+// CTD-S up to the basis: workspace, A0-A3 (draws either sampled with Philox
+// counter word `tensor`, or given) and the candidate panel (A4); *ba receives
+// the arguments of the basis construction.
+ctd_status static_front(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
+                        uint64_t seed, const uint64_t* given, uint32_t tensor, BasisArgs* ba) {
   hipStream_t st = h->stream;
   const bool mixed = h->opt.precision == CTD_PREC_MIXED;
   const bool want_C = h->opt.want_C != 0;
@@ -296,38 +337,46 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   launch_panel(st, b.uniq_fi, s, b.fptr, b.row, b.val, n_rows, b.P, b.ld, sc);
   mark(h, MARK_PANEL);
   // A5-A7: independence filter and orthonormal basis, block by block
-  BasisArgs ba{};
-  ba.P = b.P;
-  ba.ldp = b.ld;
-  ba.n_rows = n_rows;
-  ba.s_max = s;
-  ba.uniq_fi = b.uniq_fi;
-  ba.uniq_fid = b.uniq_fid;
-  ba.fptr = b.fptr;
-  ba.row = b.row;
-  ba.val = b.val;
-  ba.Q = b.Q;
-  ba.ldq = b.ld;
-  ba.Qf = mixed ? b.Qf : nullptr;
-  ba.R = b.Rs;
-  ba.ldr = b.ld;
-  ba.M = b.M;
-  ba.ldm = b.ld;
-  ba.lev = b.lev;
-  ba.lev_accumulate = false;
-  ba.eps2 = h->opt.eps * h->opt.eps;
-  ba.accept = b.accept;
-  ba.acc_fid = b.acc_fid;
-  ba.acc_fi_local = nullptr;
-  ba.fiber_mark = b.fiber_mark;
-  ba.id_offset = 0;
-  ba.Wacc = nullptr;
-  ba.ldwa = 0;
-  ba.scratch = b.scratch;
-  ba.cap = b.ld;
-  launch_basis(st, ba, sc);
-  mark(h, MARK_BASIS);
-  // A8: projection and residual
+  *ba = BasisArgs{};
+  ba->P = b.P;
+  ba->ldp = b.ld;
+  ba->n_rows = n_rows;
+  ba->s_max = s;
+  ba->k0_max = 0;
+  ba->uniq_fi = b.uniq_fi;
+  ba->uniq_fid = b.uniq_fid;
+  ba->fptr = b.fptr;
+  ba->row = b.row;
+  ba->val = b.val;
+  ba->Q = b.Q;
+  ba->ldq = b.ld;
+  ba->Qf = mixed ? b.Qf : nullptr;
+  ba->R = b.Rs;
+  ba->ldr = b.ld;
+  ba->M = b.M;
+  ba->ldm = b.ld;
+  ba->lev = b.lev;
+  ba->lev_accumulate = false;
+  ba->eps2 = h->opt.eps * h->opt.eps;
+  ba->accept = b.accept;
+  ba->acc_fid = b.acc_fid;
+  ba->acc_fi_local = nullptr;
+  ba->fiber_mark = b.fiber_mark;
+  ba->id_offset = 0;
+  ba->Wacc = nullptr;
+  ba->ldwa = 0;
+  ba->scratch = b.scratch;
+  ba->cap = b.ld;
+  return CTD_OK;
+}
+
+// CTD-S after the basis: A8 projection and residual, C when asked for, totals.
+ctd_status static_back(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s) {
+  hipStream_t st = h->stream;
+  const int64_t nnz = X->nnz;
+  const int64_t n_rows = lay.n_rows;
+  StaticBufs& b = h->sb;
+  DevScalars* sc = h->d_sc;
   ProjectArgs pa = project_args(h, b, b.Q, b.Qf, b.ld, b.lev, &sc->s_tilde, s);
   if (h->opt.profile) {
     mark(h, MARK_PROJ0);
@@ -337,7 +386,7 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   launch_project(st, pa, nnz, sc, h->opt.profile ? h->ev[MARK_SPMM0] : nullptr,
                  h->opt.profile ? h->ev[MARK_SPMM1] : nullptr);
   mark(h, MARK_PROJECTED);
-  if (want_C) launch_core_static(st, b, n_rows, nnz, sc);
+  if (h->opt.want_C) launch_core_static(st, b, n_rows, nnz, sc);
   mark(h, MARK_CORE);
   launch_static_totals(st, sc);
   mark(h, MARK_END);
@@ -350,6 +399,21 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   h->mode = lay.mode;
   h->layout = lay;
   return CTD_OK;
+}
+
+// Enqueue CTD-S on `lay`/`X`; draws either sampled (given == nullptr, Philox
+// counter word `tensor`) or given.
+ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
+                      uint64_t seed, const uint64_t* given, uint32_t tensor) {
+  BasisArgs ba{};
+  ctd_status rc = static_front(h, X, lay, s, seed, given, tensor, &ba);
+  if (rc != CTD_OK) return rc;
+  rc = ensure_bdev(h, 1);
+  if (rc != CTD_OK) return rc;
+  DevScalars* sc = h->d_sc;
+  launch_basis(h->stream, &ba, &sc, 1, h->bdev);
+  mark(h, MARK_BASIS);
+  return static_back(h, X, lay, s);
 }
 
 }  // namespace ctd
@@ -465,18 +529,21 @@ void ctd_destroy(ctd_handle* h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->batch) {
     ctd::BatchState* B = h->batch;
-    for (ctd_handle* sub : B->subs) ctd_destroy(sub);
+    for (hipStream_t st : B->pool) (void)hipStreamSynchronize(st);
+    for (ctd_handle* sub : B->subs) ctd_destroy(sub);   // their streams belong to the pool
     for (hipEvent_t e : B->done) (void)hipEventDestroy(e);
     if (B->start) (void)hipEventDestroy(B->start);
+    if (B->based) (void)hipEventDestroy(B->based);
+    for (hipStream_t st : B->pool) (void)hipStreamDestroy(st);
     ctd::batch_free_storage(B);
     delete B;
   }
   for (hipEvent_t& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   dyn_free(h);
+  if (h->bdev) (void)hipFree(h->bdev);
   if (h->arena.base) (void)hipFree(h->arena.base);
   if (h->d_sc) (void)hipFree(h->d_sc);
-  if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
 

@@ -18,6 +18,9 @@
 // columns of M are M[:k, new] = -M W_A^T T and M[new, new] = T, T being the
 // product of the inverse transposed Cholesky factors.  Sizes are read on the
 // device, so one block is a fixed sequence of launches.
+#include <algorithm>
+#include <vector>
+
 #include "kernels.h"
 
 namespace ctd {
@@ -26,9 +29,37 @@ namespace {
 constexpr int kB = 64;        // candidates per block
 constexpr int kTakeParts = 256;   // workgroups of k_blk_take: partial Grams of the new columns
 constexpr int kBlock = 256;
+constexpr int kSplitW = 16;     // row splits of W2 = Q^T Y (at most)
+constexpr int kSplitDD = 256;   // row splits of the double-double Gram (at most)
 
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One input's arguments and scratch, in device memory: every kernel below
+// serves a set of independent inputs at once, input blockIdx.z reading entry
+// blockIdx.z of the array, so a block step of many inputs is one sequence of
+// launches.  Grids are sized for the largest input; workgroups beyond an
+// input's own sizes return at once.
+struct BasisDev {
+  BasisArgs a;
+  DevScalars* sc;
+  double* W;        // 64 x cap: Q^T x rows of the block's candidates
+  double* W2p;      // nsplit_w x 64 x cap partial second-pass coefficients
+  double* W2;       // 64 x cap
+  double* part;     // ntake x 64 x 64 partial Grams of the new columns
+  double* part_hi;  // nsplit_dd x 64 x 64 partial double-double Grams
+  double* part_lo;
+  double* Glo;
+  double* G;
+  double* Tcur;
+  double* Tacc;
+  double* g;        // 64 squared candidate norms
+  double* Ybuf;     // n_rows x 64 block residuals
+  int32_t* pos;     // 64 kept positions
+  int32_t nsplit_w, nsplit_dd, ntake;
+  int32_t pad;
+};
+static_assert(sizeof(BasisDev) % 8 == 0, "BasisDev is copied as 64-bit words");
 
 // v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the 16 x 16 result D[i][j] sits in lane j + 16 (i % 4)
@@ -88,6 +119,12 @@ __device__ inline int64_t blk_count(const DevScalars* sc, int64_t b0) {
   const int64_t sp = sc->status == 0 ? sc->s_unique : 0;
   return b0 < sp ? min((int64_t)kB, sp - b0) : 0;
 }
+// Candidates of the block that need work: none once the kept fibers span all
+// n_rows rows, since every later residual is then zero and every later
+// candidate is skipped.
+__device__ inline int64_t blk_work(const DevScalars* sc, int64_t b0, int64_t n_rows) {
+  return sc->n_accept_total >= n_rows ? 0 : blk_count(sc, b0);
+}
 
 // W[j][c] = sum_e v_e Q[r_e][c] for c < k, and g[j] = ||x_{b0+j}||^2.
 // Workgroup (chunk, j) covers columns 128 chunk .. + 128 of candidate j (two
@@ -96,15 +133,22 @@ __device__ inline int64_t blk_count(const DevScalars* sc, int64_t b0) {
 // added in LDS in wave order.  Chunk 0 also forms the squared norm.
 constexpr int kWWaves = 8;
 constexpr int kWCols = 2 * kWave;
-__global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(
-    const double* __restrict__ Q, int64_t ldq, const int32_t* __restrict__ uniq_fi,
-    const int32_t* __restrict__ fptr, const int32_t* __restrict__ row,
-    const double* __restrict__ val, int64_t b0, double* __restrict__ W, int64_t ldw,
-    double* __restrict__ g, const DevScalars* sc) {
+__global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(const BasisDev* __restrict__ bd,
+                                                            int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ Q = d.a.Q;
+  const int64_t ldq = d.a.ldq, ldw = d.a.cap;
+  const int32_t* __restrict__ uniq_fi = d.a.uniq_fi;
+  const int32_t* __restrict__ fptr = d.a.fptr;
+  const int32_t* __restrict__ row = d.a.row;
+  const double* __restrict__ val = d.a.val;
+  double* __restrict__ W = d.W;
+  double* __restrict__ g = d.g;
+  const DevScalars* sc = d.sc;
   constexpr int kU = 16;
   __shared__ double part[kWWaves][kWCols];
   __shared__ double gpart[kWWaves];
-  const int64_t nb = blk_count(sc, b0);
+  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
   const int64_t k = sc->n_accept_total;
   const int j = blockIdx.y;
   const int64_t cbase = (int64_t)blockIdx.x * kWCols;
@@ -174,20 +218,24 @@ constexpr int kGK = 32;       // reduction chunk
 // and candidates 32 (w % 2) .. + 32 with two f64 MFMA accumulators.
 // With reproject set, the base is Ybuf itself (second projection pass):
 // Ybuf[r][j] -= sum_c Q[r][c] W2[j][c].
-__global__ __launch_bounds__(kGemm) void k_blk_form_y(const double* __restrict__ P, int64_t ldp,
-                                                      int64_t n_rows, const double* __restrict__ Q,
-                                                      int64_t ldq, const double* __restrict__ W,
-                                                      int64_t ldw, int64_t b0,
-                                                      double* __restrict__ Ybuf, bool reproject,
-                                                      const DevScalars* sc) {
+__global__ __launch_bounds__(kGemm) void k_blk_form_y(const BasisDev* __restrict__ bd, int64_t b0,
+                                                      bool reproject) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ P = d.a.P;
+  const double* __restrict__ Q = d.a.Q;
+  const double* __restrict__ W = reproject ? d.W2 : d.W;
+  const int64_t ldp = d.a.ldp, n_rows = d.a.n_rows, ldq = d.a.ldq, ldw = d.a.cap;
+  double* __restrict__ Ybuf = d.Ybuf;
+  const DevScalars* sc = d.sc;
   constexpr int kR = 32;
   __shared__ double As[2][kR][kGK + 1];   // Q tile [row][c]
   __shared__ double Bs[2][kGK][kB + 1];   // W^T tile [c][j]
-  const int64_t nb = blk_count(sc, b0);
+  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
   if (nb == 0) return;
   const int64_t k = sc->n_accept_total;
   if (reproject && k == 0) return;
   const int64_t r0 = (int64_t)blockIdx.x * kR;
+  if (r0 >= n_rows) return;
   const int grp = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
   const int w = t / kWave, l = lane_id();
   const int rb = (w / 2) * 16, cb = (w % 2) * 32;
@@ -265,19 +313,22 @@ __global__ __launch_bounds__(kGemm) void k_blk_form_y(const double* __restrict__
 // partial over kSplitW row ranges: workgroup (ct, s) covers c in
 // [64 ct, 64 ct + 64); wave w of a group computes c rows 16 w .. + 16 against
 // all 64 j with four f64 MFMA tiles.
-constexpr int kSplitW = 16;
-__global__ __launch_bounds__(kGemm) void k_blk_w2_part(const double* __restrict__ Q, int64_t ldq,
-                                                       int64_t n_rows,
-                                                       const double* __restrict__ Y,
-                                                       double* __restrict__ W2p, int64_t ldw,
-                                                       int64_t b0, const DevScalars* sc) {
+__global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restrict__ bd,
+                                                       int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ Q = d.a.Q;
+  const double* __restrict__ Y = d.Ybuf;
+  double* __restrict__ W2p = d.W2p;
+  const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows, ldw = d.a.cap;
+  const int nsplit = d.nsplit_w;
+  const DevScalars* sc = d.sc;
   __shared__ double Qs[2][kGK][kB + 1];   // [r][c]
   __shared__ double Ys[2][kGK][kB + 1];   // [r][j]
-  const int64_t nb = blk_count(sc, b0);
+  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
   const int64_t k = sc->n_accept_total;
   const int64_t c0 = (int64_t)blockIdx.x * kB;
-  if (nb == 0 || c0 >= k) return;
-  const int64_t chunk = (n_rows + kSplitW - 1) / kSplitW;
+  if (nb == 0 || c0 >= k || (int)blockIdx.y >= nsplit) return;
+  const int64_t chunk = (n_rows + nsplit - 1) / nsplit;
   const int64_t r0 = blockIdx.y * chunk, r1 = min(n_rows, r0 + chunk);
   const int grp = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
   const int w = t / kWave, l = lane_id();
@@ -337,18 +388,23 @@ __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const double* __restrict_
 }
 
 // W2[j][c] = sum_s W2p[s][j][c] (fixed order); W[j][c] += W2[j][c].
-__global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const double* __restrict__ W2p,
-                                                       double* __restrict__ W2,
-                                                       double* __restrict__ W, int64_t ldw,
-                                                       int64_t b0, const DevScalars* sc) {
-  const int64_t nb = blk_count(sc, b0);
+__global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restrict__ bd,
+                                                       int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ W2p = d.W2p;
+  double* __restrict__ W2 = d.W2;
+  double* __restrict__ W = d.W;
+  const int64_t ldw = d.a.cap;
+  const int nsplit = d.nsplit_w;
+  const DevScalars* sc = d.sc;
+  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
   const int64_t k = sc->n_accept_total;
   const int64_t total = nb * k;
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * kBlock) {
     const int64_t j = t / k, c = t % k;
     double s = 0.0;
-    for (int p = 0; p < kSplitW; ++p) s += W2p[(int64_t)p * kB * ldw + j * ldw + c];
+    for (int p = 0; p < nsplit; ++p) s += W2p[(int64_t)p * kB * ldw + j * ldw + c];
     W2[j * ldw + c] = s;
     W[j * ldw + c] += s;
   }
@@ -360,16 +416,19 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const double* __restrict_
 // need the block Gram to about u^2: rounding it to float64 alone moves the
 // Schur complement of an exactly dependent candidate to ~u * cond^2 ||x||^2,
 // which can reach eps^2 ||x||^2.
-constexpr int kSplitDD = 256;
-__global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const double* __restrict__ Y,
-                                                        int64_t n_rows, int64_t b0,
-                                                        double* __restrict__ part_hi,
-                                                        double* __restrict__ part_lo,
-                                                        const DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const BasisDev* __restrict__ bd,
+                                                        int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ Y = d.Ybuf;
+  double* __restrict__ part_hi = d.part_hi;
+  double* __restrict__ part_lo = d.part_lo;
+  const int64_t n_rows = d.a.n_rows;
+  const int nsplit = d.nsplit_dd;
+  const DevScalars* sc = d.sc;
   __shared__ double Ys[kB][kB + 1];   // [row][col]
-  const int64_t width = blk_count(sc, b0);
-  if (width == 0) return;
-  const int64_t chunk = (n_rows + kSplitDD - 1) / kSplitDD;
+  const int64_t width = blk_work(sc, b0, n_rows);
+  if (width == 0 || (int)blockIdx.x >= nsplit) return;
+  const int64_t chunk = (n_rows + nsplit - 1) / nsplit;
   const int64_t k0 = blockIdx.x * chunk;
   const int64_t k1 = min(n_rows, k0 + chunk);
   const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
@@ -419,19 +478,23 @@ __global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const double* __restrict
 // summing every kSumWays-th partial (neighbouring lanes read neighbouring
 // elements), and the kSumWays sums are added in a fixed order.
 constexpr int kSumWays = 16;
-__global__ __launch_bounds__(kBlock) void k_blk_sum_dd(const double* __restrict__ part_hi,
-                                                       const double* __restrict__ part_lo,
-                                                       double* __restrict__ G_hi,
-                                                       double* __restrict__ G_lo, int64_t b0,
-                                                       const DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_blk_sum_dd(const BasisDev* __restrict__ bd,
+                                                       int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ part_hi = d.part_hi;
+  const double* __restrict__ part_lo = d.part_lo;
+  double* __restrict__ G_hi = d.G;
+  double* __restrict__ G_lo = d.Glo;
+  const int nsplit = d.nsplit_dd;
+  const DevScalars* sc = d.sc;
   __shared__ double sh[kBlock], sl[kBlock];
-  if (blk_count(sc, b0) == 0) return;
+  if (blk_work(sc, b0, d.a.n_rows) == 0) return;
   constexpr int kPer = kBlock / kSumWays;
   const int e = threadIdx.x % kPer, q = threadIdx.x / kPer;
   const int t = blockIdx.x * kPer + e;
   double h = 0.0, l = 0.0;
   if (t < kB * kB) {
-    for (int p = q; p < kSplitDD; p += kSumWays) {
+    for (int p = q; p < nsplit; p += kSumWays) {
       double s2, er;
       two_sum(h, part_hi[(int64_t)p * kB * kB + t], s2, er);
       h = s2;
@@ -453,9 +516,12 @@ __global__ __launch_bounds__(kBlock) void k_blk_sum_dd(const double* __restrict_
 }
 
 // G[i][j] = sum_s part[s][i][j] in a fixed order (deterministic).
-__global__ __launch_bounds__(kBlock) void k_blk_sum_parts(const double* __restrict__ part,
-                                                          int nparts, double* __restrict__ G,
-                                                          const DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_blk_sum_parts(const BasisDev* __restrict__ bd) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ part = d.part;
+  double* __restrict__ G = d.G;
+  const int nparts = d.ntake;
+  const DevScalars* sc = d.sc;
   __shared__ double sh[kBlock];
   if (sc->blk_na == 0) return;
   constexpr int kPer = kBlock / kSumWays;
@@ -625,21 +691,27 @@ __device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, d
 // candidate order (pivot vs eps^2 ||x||^2); kept positions compacted into
 // pos[0..na), na into sc->blk_na; Tacc = L_A^{-T} over the kept rows/columns
 // (first Cholesky-QR pass of the kept residuals).
-__global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__ G,
-                                                      const double* __restrict__ Glo,
-                                                      const double* __restrict__ g, double eps2,
-                                                      int64_t b0, int64_t n_rows,
-                                                      int32_t* __restrict__ pos,
-                                                      int32_t* __restrict__ accept_all,
-                                                      double* __restrict__ Tacc,
-                                                      DevScalars* sc) {
+__global__ __launch_bounds__(kChol) void k_blk_decide(const BasisDev* __restrict__ bd, int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ G = d.G;
+  const double* __restrict__ Glo = d.Glo;
+  const double* __restrict__ g = d.g;
+  const double eps2 = d.a.eps2;
+  const int64_t n_rows = d.a.n_rows;
+  int32_t* __restrict__ pos = d.pos;
+  int32_t* __restrict__ accept_all = d.a.accept;
+  double* __restrict__ Tacc = d.Tacc;
+  DevScalars* sc = d.sc;
   __shared__ LdsMat Ah, Al, X;
   __shared__ double ch[2 * kB], cl[2 * kB], xrow[2 * kB], gs[kB], piv[8];
   __shared__ int32_t ps[kB];
-  const int64_t nb = blk_count(sc, b0);
+  const int64_t nb_all = blk_count(sc, b0);
+  const int64_t nb = blk_work(sc, b0, n_rows);
   const int tid = threadIdx.x;
   if (nb == 0) {
     if (tid == 0) sc->blk_na = 0;
+    if (accept_all)
+      for (int t = tid; t < nb_all; t += kChol) accept_all[b0 + t] = 0;
     return;
   }
   const int64_t room = n_rows - (int64_t)sc->n_accept_total;   // at most n_rows independent fibers
@@ -677,10 +749,12 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const double* __restrict__
 // orthonormal to working accuracy and Tacc stays as it is (blk_reorth = 0).
 // Otherwise Cholesky (no drop) of that Gram, Tcur = L^{-T}, Tacc <- Tacc Tcur.
 constexpr double kOrthTol = 1e-12;
-__global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict__ G,
-                                                       double* __restrict__ Tcur,
-                                                       double* __restrict__ Tacc,
-                                                       DevScalars* sc) {
+__global__ __launch_bounds__(kChol) void k_blk_cholinv(const BasisDev* __restrict__ bd) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ G = d.G;
+  double* __restrict__ Tcur = d.Tcur;
+  double* __restrict__ Tacc = d.Tacc;
+  DevScalars* sc = d.sc;
   __shared__ LdsMat L, X, Ta;
   __shared__ double ch[2 * kB], cl[2 * kB], xrow[2 * kB], piv[8];
   __shared__ int any_off;
@@ -724,19 +798,23 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const double* __restrict_
 // outputs each) and accumulates the Gram of its new rows of Q with f64 MFMAs
 // (wave w: Gram rows 16 w .. + 16); the sum over its tiles goes to
 // part[blockIdx.x] for the orthogonality check of the block.
-__global__ __launch_bounds__(kBlock) void k_blk_take(const double* __restrict__ Ybuf,
-                                                     const double* __restrict__ P, int64_t ldp,
-                                                     int64_t n_rows, const int32_t* __restrict__ pos,
-                                                     const double* __restrict__ T, int64_t b0,
-                                                     double* __restrict__ Q, int64_t ldq,
-                                                     double* __restrict__ R, int64_t ldr,
-                                                     double* __restrict__ part,
-                                                     const DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_blk_take(const BasisDev* __restrict__ bd, int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ Ybuf = d.Ybuf;
+  const double* __restrict__ P = d.a.P;
+  const int32_t* __restrict__ pos = d.pos;
+  const double* __restrict__ T = d.Tacc;
+  double* __restrict__ Q = d.a.Q;
+  double* __restrict__ R = d.a.R;
+  double* __restrict__ part = d.part;
+  const int64_t ldp = d.a.ldp, n_rows = d.a.n_rows, ldq = d.a.ldq, ldr = d.a.ldr;
+  const int ntake = d.ntake;
+  const DevScalars* sc = d.sc;
   __shared__ double Ts[kB][kB + 1];
   __shared__ double Ys[kB][kB + 1];   // Ybuf rows, then the new Q rows
   __shared__ int32_t ps[kB];
   const int na = sc->blk_na;
-  if (na == 0) return;
+  if (na == 0 || (int)blockIdx.x >= ntake) return;
   const int64_t k = sc->n_accept_total;
   for (int t = threadIdx.x; t < kB * kB; t += kBlock) Ts[t / kB][t % kB] = T[t];
   if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
@@ -744,7 +822,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_take(const double* __restrict__ 
   const int a_lo = (threadIdx.x % 4) * 16;
   const int w = threadIdx.x / kWave, l = lane_id();
   dbl4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < n_rows; r0 += (int64_t)gridDim.x * kB) {
+  for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < n_rows; r0 += (int64_t)ntake * kB) {
     __syncthreads();   // previous tile's Gram reads of Ys done (and Ts, ps written)
     for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
       const int64_t rr = r0 + t / kB;
@@ -790,15 +868,19 @@ __global__ __launch_bounds__(kBlock) void k_blk_take(const double* __restrict__ 
 }
 
 // Q[r][k + a] <- sum_{a' <= a} Q[r][k + a'] T[a'][a]; rows staged in LDS.
-__global__ __launch_bounds__(kBlock) void k_blk_apply(double* __restrict__ Q, int64_t ldq,
-                                                      int64_t n_rows, const double* __restrict__ T,
-                                                      const DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_blk_apply(const BasisDev* __restrict__ bd) {
+  const BasisDev& d = bd[blockIdx.z];
+  double* __restrict__ Q = d.a.Q;
+  const double* __restrict__ T = d.Tcur;
+  const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows;
+  const DevScalars* sc = d.sc;
   __shared__ double Ts[kB][kB + 1];
   __shared__ double Ys[kB][kB + 1];
   const int na = sc->blk_na;
   if (na == 0 || !sc->blk_reorth) return;
   const int64_t k = sc->n_accept_total;
   const int64_t r0 = (int64_t)blockIdx.x * kB;
+  if (r0 >= n_rows) return;
   for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
     Ts[t / kB][t % kB] = T[t];
     const int64_t rr = r0 + t / kB;
@@ -836,11 +918,14 @@ __global__ __launch_bounds__(kBlock) void k_blk_apply(double* __restrict__ Q, in
 // j >= 32 x (M is upper triangular) with two groups of four waves splitting
 // the j chunks, then the tile times T in LDS.  All workgroups first write the
 // diagonal block and the zero rows.
-__global__ __launch_bounds__(kGemm) void k_blk_newm(double* __restrict__ M, int64_t ldm,
-                                                    const double* __restrict__ W, int64_t ldw,
-                                                    const int32_t* __restrict__ pos,
-                                                    const double* __restrict__ T,
-                                                    const DevScalars* sc) {
+__global__ __launch_bounds__(kGemm) void k_blk_newm(const BasisDev* __restrict__ bd) {
+  const BasisDev& d = bd[blockIdx.z];
+  double* __restrict__ M = d.a.M;
+  const double* __restrict__ W = d.W;
+  const int32_t* __restrict__ pos = d.pos;
+  const double* __restrict__ T = d.Tacc;
+  const int64_t ldm = d.a.ldm, ldw = d.a.cap;
+  const DevScalars* sc = d.sc;
   constexpr int kR = 32;
   // one LDS buffer: the main loop's tiles, then the epilogue's Z (32 x 65)
   // and T (64 x 65) over the same space
@@ -952,13 +1037,19 @@ __global__ __launch_bounds__(kGemm) void k_blk_newm(double* __restrict__ M, int6
 
 // Book-keeping of one block: ids and marks of the kept fibers, saved W rows,
 // and k += na.
-__global__ void k_blk_finish(const int32_t* __restrict__ pos, int64_t b0,
-                             const int32_t* __restrict__ uniq_fi,
-                             const uint64_t* __restrict__ uniq_fid, uint64_t id_offset,
-                             uint64_t* __restrict__ acc_fid, int32_t* __restrict__ acc_fi_local,
-                             uint8_t* __restrict__ fiber_mark, const double* __restrict__ W,
-                             int64_t ldw, double* __restrict__ Wacc, int64_t ldwa,
-                             DevScalars* sc) {
+__global__ void k_blk_finish(const BasisDev* __restrict__ bd, int64_t b0) {
+  const BasisDev& d = bd[blockIdx.z];
+  const int32_t* __restrict__ pos = d.pos;
+  const int32_t* __restrict__ uniq_fi = d.a.uniq_fi;
+  const uint64_t* __restrict__ uniq_fid = d.a.uniq_fid;
+  const uint64_t id_offset = d.a.id_offset;
+  uint64_t* __restrict__ acc_fid = d.a.acc_fid;
+  int32_t* __restrict__ acc_fi_local = d.a.acc_fi_local;
+  uint8_t* __restrict__ fiber_mark = d.a.fiber_mark;
+  const double* __restrict__ W = d.W;
+  double* __restrict__ Wacc = d.a.Wacc;
+  const int64_t ldw = d.a.cap, ldwa = d.a.ldwa;
+  DevScalars* sc = d.sc;
   const int64_t k = sc->n_accept_total;
   const int na = sc->blk_na;
   const int64_t base = k - sc->wacc_base;     // row of the first new fiber in Wacc
@@ -980,16 +1071,21 @@ __global__ void k_blk_finish(const int32_t* __restrict__ pos, int64_t b0,
   }
 }
 
-__global__ void k_begin_basis(DevScalars* sc) {
+__global__ void k_begin_basis(const BasisDev* __restrict__ bd) {
+  DevScalars* sc = bd[blockIdx.z].sc;
   sc->base_accept = sc->n_accept_total;   // kept before this call
   sc->s_tilde = 0;
 }
 
 // lev[i] = sum_{c in [c0, k)} Q[i][c]^2 (+= when accumulating); Qf copy of those columns.
-__global__ __launch_bounds__(kBlock) void k_lev(const double* __restrict__ Q, int64_t ldq,
-                                                int64_t n_rows, float* __restrict__ Qf,
-                                                double* __restrict__ lev, bool from_base,
-                                                const DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_lev(const BasisDev* __restrict__ bd) {
+  const BasisDev& d = bd[blockIdx.z];
+  const double* __restrict__ Q = d.a.Q;
+  float* __restrict__ Qf = d.a.Qf;
+  double* __restrict__ lev = d.a.lev;
+  const bool from_base = d.a.lev_accumulate;
+  const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows;
+  const DevScalars* sc = d.sc;
   const int64_t k = sc->n_accept_total;
   const int64_t c0 = from_base ? sc->base_accept : 0;
   const int lane = lane_id();
@@ -1005,71 +1101,136 @@ __global__ __launch_bounds__(kBlock) void k_lev(const double* __restrict__ Q, in
   s = wave_sum(s);
   if (lane == 0) lev[r] = (from_base ? lev[r] : 0.0) + s;
 }
+
+struct Splits {
+  int w, dd, take;
+};
+// Row splits of one input: enough rows per split that small inputs do not
+// write (and sum) mostly empty partials.
+Splits splits_for(int64_t n_rows) {
+  Splits sp;
+  sp.w = (int)std::max<int64_t>(1, std::min<int64_t>(kSplitW, div_up(n_rows, 256)));
+  sp.dd = (int)std::max<int64_t>(1, std::min<int64_t>(kSplitDD, div_up(n_rows, 32)));
+  sp.take = (int)std::max<int64_t>(1, std::min<int64_t>(kTakeParts, div_up(n_rows, kB)));
+  return sp;
+}
+
+// Up to kPutPack entries of the argument array, passed by value.
+constexpr int kPutPack = 8;
+struct BasisPack {
+  BasisDev d[kPutPack];
+};
+__global__ void k_put_dev(BasisDev* __restrict__ out, BasisPack pk, int n) {
+  constexpr int kWords = sizeof(BasisDev) / 8;
+  const uint64_t* src = (const uint64_t*)pk.d;
+  uint64_t* dst = (uint64_t*)out;
+  for (int t = threadIdx.x; t < n * kWords; t += blockDim.x) dst[t] = src[t];
+}
 }  // namespace
 
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
-  return (size_t)kB * cap            // W
-         + (size_t)kSplitW * kB * cap + (size_t)kB * cap   // W2p, W2
-         + (size_t)kTakeParts * kB * kB  // part
-         + (size_t)kSplitDD * kB * kB * 2 + (size_t)kB * kB  // part_hi/lo, G_lo
-         + (size_t)kB * kB * 3       // G, Tcur, Tacc
-         + kB                        // g
-         + (size_t)kB * n_rows       // Ybuf
-         + 64;                       // pos
+  const Splits sp = splits_for(n_rows);
+  return (size_t)kB * cap                           // W
+         + (size_t)sp.w * kB * cap + (size_t)kB * cap   // W2p, W2
+         + (size_t)sp.take * kB * kB                // part
+         + (size_t)sp.dd * kB * kB * 2 + (size_t)kB * kB   // part_hi/lo, G_lo
+         + (size_t)kB * kB * 3                      // G, Tcur, Tacc
+         + kB                                       // g
+         + (size_t)kB * n_rows                      // Ybuf
+         + 64;                                      // pos
 }
 
-void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc) {
-  double* W = a.scratch;
-  double* W2p = W + (size_t)kB * a.cap;
-  double* W2 = W2p + (size_t)kSplitW * kB * a.cap;
-  double* part = W2 + (size_t)kB * a.cap;
-  double* part_hi = part + (size_t)kTakeParts * kB * kB;
-  double* part_lo = part_hi + (size_t)kSplitDD * kB * kB;
-  double* Glo = part_lo + (size_t)kSplitDD * kB * kB;
-  double* G = Glo + kB * kB;
-  double* Tcur = G + kB * kB;
-  double* Tacc = Tcur + kB * kB;
-  double* g = Tacc + kB * kB;
-  double* Ybuf = g + kB;
-  int32_t* pos = (int32_t*)(Ybuf + (size_t)kB * a.n_rows);
-  const int wchunks = std::max(1, div_up(a.cap, kWCols));
-  const int rows_tiles32 = div_up(a.n_rows, 32);
-  const int rows4 = div_up(a.n_rows, kB);
-  const int ntake = std::max(1, std::min(kTakeParts, rows4));
-  hipLaunchKernelGGL(k_begin_basis, dim3(1), dim3(1), 0, st, sc);
-  for (int64_t b0 = 0; b0 < a.s_max; b0 += kB) {
-    hipLaunchKernelGGL(k_blk_w, dim3(wchunks, kB), dim3(kWWaves * kWave), 0, st, a.Q, a.ldq,
-                       a.uniq_fi, a.fptr, a.row, a.val, b0, W, a.cap, g, sc);
-    hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kGemm), 0, st, a.P, a.ldp, a.n_rows,
-                       a.Q, a.ldq, W, a.cap, b0, Ybuf, false, sc);
-    // second projection against Q (block classical Gram-Schmidt, twice)
-    hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(a.cap, kB), kSplitW), dim3(kGemm), 0, st, a.Q,
-                       a.ldq, a.n_rows, Ybuf, W2p, a.cap, b0, sc);
-    hipLaunchKernelGGL(k_blk_w2_sum, dim3(std::max(1, std::min(1024, div_up((int64_t)kB * a.cap, kBlock)))),
-                       dim3(kBlock), 0, st, W2p, W2, W, a.cap, b0, sc);
-    hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32), dim3(kGemm), 0, st, a.P, a.ldp, a.n_rows,
-                       a.Q, a.ldq, W2, a.cap, b0, Ybuf, true, sc);
-    hipLaunchKernelGGL(k_blk_gram_dd, dim3(kSplitDD), dim3(kBlock), 0, st, Ybuf, a.n_rows, b0,
-                       part_hi, part_lo, sc);
-    hipLaunchKernelGGL(k_blk_sum_dd, dim3(kB * kB * kSumWays / kBlock), dim3(kBlock), 0, st, part_hi, part_lo,
-                       G, Glo, b0, sc);
-    hipLaunchKernelGGL(k_blk_decide, dim3(1), dim3(kChol), 0, st, G, Glo, g, a.eps2, b0, a.n_rows,
-                       pos, a.accept, Tacc, sc);
-    hipLaunchKernelGGL(k_blk_take, dim3(ntake), dim3(kBlock), 0, st, Ybuf, a.P, a.ldp, a.n_rows,
-                       pos, Tacc, b0, a.Q, a.ldq, a.R, a.ldr, part, sc);
-    hipLaunchKernelGGL(k_blk_sum_parts, dim3(kB * kB * kSumWays / kBlock), dim3(kBlock), 0, st, part,
-                       ntake, G, sc);
-    hipLaunchKernelGGL(k_blk_cholinv, dim3(1), dim3(kChol), 0, st, G, Tcur, Tacc, sc);
-    hipLaunchKernelGGL(k_blk_apply, dim3(rows4), dim3(kBlock), 0, st, a.Q, a.ldq, a.n_rows, Tcur,
-                       sc);
-    hipLaunchKernelGGL(k_blk_newm, dim3(std::max(1, div_up(a.cap, 32))), dim3(kGemm), 0, st, a.M,
-                       a.ldm, W, a.cap, pos, Tacc, sc);
-    hipLaunchKernelGGL(k_blk_finish, dim3(1), dim3(256), 0, st, pos, b0, a.uniq_fi, a.uniq_fid,
-                       a.id_offset, a.acc_fid, a.acc_fi_local, a.fiber_mark, W, a.cap, a.Wacc,
-                       a.ldwa, sc);
+size_t basis_dev_bytes(int count) { return (size_t)std::max(count, 1) * sizeof(BasisDev); }
+
+void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs, int count,
+                  void* dev) {
+  if (count <= 0) return;
+  // inputs in order of decreasing candidate bound, so the inputs still
+  // working at a block step are a prefix of the array
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return args[x].s_max > args[y].s_max; });
+  std::vector<BasisDev> hd(count);
+  for (int i = 0; i < count; ++i) {
+    const BasisArgs& a = args[order[i]];
+    const Splits sp = splits_for(a.n_rows);
+    BasisDev& d = hd[i];
+    d = BasisDev{};
+    d.a = a;
+    d.sc = scs[order[i]];
+    d.W = a.scratch;
+    d.W2p = d.W + (size_t)kB * a.cap;
+    d.W2 = d.W2p + (size_t)sp.w * kB * a.cap;
+    d.part = d.W2 + (size_t)kB * a.cap;
+    d.part_hi = d.part + (size_t)sp.take * kB * kB;
+    d.part_lo = d.part_hi + (size_t)sp.dd * kB * kB;
+    d.Glo = d.part_lo + (size_t)sp.dd * kB * kB;
+    d.G = d.Glo + kB * kB;
+    d.Tcur = d.G + kB * kB;
+    d.Tacc = d.Tcur + kB * kB;
+    d.g = d.Tacc + kB * kB;
+    d.Ybuf = d.g + kB;
+    d.pos = (int32_t*)(d.Ybuf + (size_t)kB * a.n_rows);
+    d.nsplit_w = sp.w;
+    d.nsplit_dd = sp.dd;
+    d.ntake = sp.take;
   }
-  hipLaunchKernelGGL(k_lev, dim3(div_up(a.n_rows * kWave, kBlock)), dim3(kBlock), 0, st, a.Q, a.ldq,
-                     a.n_rows, a.Qf, a.lev, a.lev_accumulate, sc);
+  BasisDev* dd = (BasisDev*)dev;
+  for (int i0 = 0; i0 < count; i0 += kPutPack) {
+    BasisPack pk;
+    const int n = std::min(kPutPack, count - i0);
+    for (int u = 0; u < n; ++u) pk.d[u] = hd[i0 + u];
+    hipLaunchKernelGGL(k_put_dev, dim3(1), dim3(256), 0, st, dd + i0, pk, n);
+  }
+  const int sums = kB * kB * kSumWays / kBlock;
+  constexpr int kMaxZ = 65535;
+  for (int z0 = 0; z0 < count; z0 += kMaxZ) {
+    const int nz_all = std::min(kMaxZ, count - z0);
+    const BasisDev* bd = dd + z0;
+    int64_t rows_all = 1;
+    for (int i = z0; i < z0 + nz_all; ++i) rows_all = std::max(rows_all, hd[i].a.n_rows);
+    hipLaunchKernelGGL(k_begin_basis, dim3(1, 1, nz_all), dim3(1), 0, st, bd);
+    for (int64_t b0 = 0; b0 < hd[z0].a.s_max; b0 += kB) {
+      // inputs with candidates left at b0, and host bounds over them of the
+      // columns held (k <= min(n_rows, k0 + b0)) and of the row splits
+      int nz = 0;
+      int64_t rows = 1, kub = 0;
+      int w_max = 1, dd_max = 1, take_max = 1;
+      while (nz < nz_all && hd[z0 + nz].a.s_max > b0) {
+        const BasisDev& d = hd[z0 + nz];
+        rows = std::max(rows, d.a.n_rows);
+        kub = std::max(kub, std::min(std::min(d.a.n_rows, d.a.k0_max + b0), d.a.cap));
+        w_max = std::max(w_max, d.nsplit_w);
+        dd_max = std::max(dd_max, d.nsplit_dd);
+        take_max = std::max(take_max, d.ntake);
+        ++nz;
+      }
+      const int rows_tiles32 = div_up(rows, 32);
+      const int rows4 = div_up(rows, kB);
+      const int64_t k1 = std::max<int64_t>(kub, 1);
+      hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nz), dim3(kWWaves * kWave), 0, st,
+                         bd, b0);
+      hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0, false);
+      // second projection against Q (block classical Gram-Schmidt, twice)
+      hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(k1, kB), w_max, nz), dim3(kGemm), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_w2_sum,
+                         dim3(std::max(1, std::min(1024, div_up((int64_t)kB * k1, kBlock))), 1, nz),
+                         dim3(kBlock), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0, true);
+      hipLaunchKernelGGL(k_blk_gram_dd, dim3(dd_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_sum_dd, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_decide, dim3(1, 1, nz), dim3(kChol), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_take, dim3(take_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_sum_parts, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd);
+      hipLaunchKernelGGL(k_blk_cholinv, dim3(1, 1, nz), dim3(kChol), 0, st, bd);
+      hipLaunchKernelGGL(k_blk_apply, dim3(rows4, 1, nz), dim3(kBlock), 0, st, bd);
+      hipLaunchKernelGGL(k_blk_newm, dim3(div_up(k1, 32), 1, nz), dim3(kGemm), 0, st, bd);
+      hipLaunchKernelGGL(k_blk_finish, dim3(1, 1, nz), dim3(256), 0, st, bd, b0);
+    }
+    hipLaunchKernelGGL(k_lev, dim3(div_up(rows_all * kWave, kBlock), 1, nz_all), dim3(kBlock), 0, st,
+                       bd);
+  }
 }
 
 }  // namespace ctd

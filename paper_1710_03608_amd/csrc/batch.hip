@@ -1,11 +1,15 @@
 // Many independent tensors in one call (the batched execution form): every
 // tensor gets the CTD-S path of Algorithm 1, its draws using Philox counter
-// word tensor = b.  Tensors are spread over kBatchStreams sub-handles, each
-// with a stream of its own (default priority), so the small per-block
-// kernels of different tensors overlap on the GPU.  The caller's stream is
-// joined with events at entry and exit.  After each tensor its scalars and
-// index arrays are copied (on the tensor's stream) into storage owned by the
-// batch, so a sub-handle's workspace can take the next tensor at once.
+// word tensor = b.  Tensors go in groups that fit a device-memory budget, one
+// sub-handle (own workspace and scalars) per tensor of a group.  The
+// per-tensor stages before and after the basis (keys, sort, weights, draws,
+// unique, panel; projection and residual) run on a pool of kBatchStreams
+// streams (default priority); the independence filter and basis of the whole
+// group, the long sequential part, is one sequence of launches whose grids
+// span all tensors of the group.  The caller's stream is joined with events
+// at entry and exit.  After each tensor its scalars and index arrays are
+// copied into storage owned by the batch.
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -15,6 +19,8 @@ namespace ctd {
 
 namespace {
 constexpr int kBatchStreams = 8;
+constexpr int kMaxGroup = 4096;                      // tensors per group
+constexpr size_t kGroupBytes = size_t(32) << 30;     // workspace budget per group
 
 #define BATCH_HIP(h, expr)                                                              \
   do {                                                                                  \
@@ -26,21 +32,11 @@ constexpr int kBatchStreams = 8;
 ctd_status new_sub(ctd_handle* h, ctd_handle** out) {
   ctd_handle* sub = new ctd_handle();
   sub->opt = h->opt;
-  sub->opt.want_C = 0;
-  sub->opt.profile = 0;
-  if (hipStreamCreateWithFlags(&sub->stream, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipGetLastError();
-    delete sub;
-    return fail(h, CTD_ERR_HIP, "stream creation for a batch failed");
-  }
-  sub->own_stream = true;
   if (hipMalloc(&sub->d_sc, sizeof(DevScalars)) != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipStreamDestroy(sub->stream);
     delete sub;
     return fail(h, CTD_ERR_OOM, "batch scalar allocation failed");
   }
-  (void)hipMemsetAsync(sub->d_sc, 0, sizeof(DevScalars), sub->stream);
   *out = sub;
   return CTD_OK;
 }
@@ -48,7 +44,7 @@ ctd_status new_sub(ctd_handle* h, ctd_handle** out) {
 ctd_status sync_all(ctd_handle* h) {
   BATCH_HIP(h, hipStreamSynchronize(h->stream));
   if (h->batch)
-    for (ctd_handle* sub : h->batch->subs) BATCH_HIP(h, hipStreamSynchronize(sub->stream));
+    for (hipStream_t st : h->batch->pool) BATCH_HIP(h, hipStreamSynchronize(st));
   return CTD_OK;
 }
 }  // namespace
@@ -94,24 +90,17 @@ extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, in
   }
   if (!h->batch) h->batch = new BatchState();
   BatchState& B = *h->batch;
-  const int K = std::min(kBatchStreams, (int)nb);
-  while ((int)B.subs.size() < K) {
-    ctd_handle* sub = nullptr;
-    ctd_status rc = new_sub(h, &sub);
-    if (rc != CTD_OK) return rc;
-    B.subs.push_back(sub);
+  while ((int)B.pool.size() < kBatchStreams) {
+    hipStream_t st = nullptr;
+    BATCH_HIP(h, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    B.pool.push_back(st);
     hipEvent_t e = nullptr;
     BATCH_HIP(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     B.done.push_back(e);
   }
-  for (ctd_handle* sub : B.subs) {
-    if (sub->opt.precision != h->opt.precision || sub->opt.eps != h->opt.eps) {
-      BATCH_HIP(h, hipStreamSynchronize(sub->stream));
-      sub->opt.precision = h->opt.precision;
-      sub->opt.eps = h->opt.eps;
-    }
-  }
   if (!B.start) BATCH_HIP(h, hipEventCreateWithFlags(&B.start, hipEventDisableTiming));
+  if (!B.based) BATCH_HIP(h, hipEventCreateWithFlags(&B.based, hipEventDisableTiming));
+  const int K = kBatchStreams;
   // per-tensor result storage
   if ((size_t)nb > B.cap_t || (size_t)total_s > B.cap_s) {
     ctd_status rc = sync_all(h);
@@ -144,29 +133,77 @@ extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, in
     o += s[b];
   }
   B.host_valid = false;
+  const bool mixed = h->opt.precision == CTD_PREC_MIXED;
   // tensors start after the caller's earlier work on its stream
   BATCH_HIP(h, hipEventRecord(B.start, h->stream));
-  for (int k = 0; k < K; ++k) BATCH_HIP(h, hipStreamWaitEvent(B.subs[k]->stream, B.start, 0));
-  for (int b = 0; b < nb; ++b) {
-    ctd_handle* sub = B.subs[b % K];
-    sub->failed = false;
-    ctd_status rc = run_static(sub, &Xs[b], lays[b], s[b], seed, nullptr, (uint32_t)b);
-    if (rc != CTD_OK)
-      return fail(h, rc, "tensor " + std::to_string(b) + ": " + sub->last_error);
-    const StaticBufs& sb = sub->sb;
-    hipStream_t st = sub->stream;
-    const size_t n = (size_t)s[b], off = (size_t)B.off[b];
-    BATCH_HIP(h, hipMemcpyAsync(B.scal + b, sub->d_sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, st));
-    BATCH_HIP(h, hipMemcpyAsync(B.draws + off, sb.draw_fid, n * 8, hipMemcpyDeviceToDevice, st));
-    BATCH_HIP(h, hipMemcpyAsync(B.unique + off, sb.uniq_fid, n * 8, hipMemcpyDeviceToDevice, st));
-    BATCH_HIP(h, hipMemcpyAsync(B.accepted + off, sb.acc_fid, n * 8, hipMemcpyDeviceToDevice, st));
-    BATCH_HIP(h, hipMemcpyAsync(B.counts + off, sb.counts, n * 4, hipMemcpyDeviceToDevice, st));
-    BATCH_HIP(h, hipMemcpyAsync(B.prob + off, sb.prob, n * 8, hipMemcpyDeviceToDevice, st));
-    BATCH_HIP(h, hipMemcpyAsync(B.scale + off, sb.scale, n * 8, hipMemcpyDeviceToDevice, st));
+  for (int k = 0; k < K; ++k) BATCH_HIP(h, hipStreamWaitEvent(B.pool[k], B.start, 0));
+  std::vector<BasisArgs> args;
+  std::vector<DevScalars*> scs;
+  for (int g0 = 0; g0 < nb;) {
+    // the group: consecutive tensors within the workspace budget
+    int g1 = g0;
+    size_t bytes = 0;
+    while (g1 < nb && g1 - g0 < kMaxGroup) {
+      const size_t t = static_bytes(Xs[g1].nnz, s[g1], lays[g1].n_rows, mixed, false, round8(s[g1]));
+      if (g1 > g0 && bytes + t > kGroupBytes) break;
+      bytes += t;
+      ++g1;
+    }
+    const int n = g1 - g0;
+    while ((int)B.subs.size() < n) {
+      ctd_handle* sub = nullptr;
+      ctd_status rc = new_sub(h, &sub);
+      if (rc != CTD_OK) return rc;
+      sub->stream = B.pool[B.subs.size() % K];
+      B.subs.push_back(sub);
+    }
+    args.assign(n, BasisArgs{});
+    scs.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+      const int b = g0 + i;
+      ctd_handle* sub = B.subs[i];   // always on stream pool[i % K]
+      sub->opt = h->opt;
+      sub->opt.want_C = 0;
+      sub->opt.profile = 0;
+      sub->failed = false;
+      ctd_status rc = static_front(sub, &Xs[b], lays[b], s[b], seed, nullptr, (uint32_t)b, &args[i]);
+      if (rc != CTD_OK)
+        return fail(h, rc, "tensor " + std::to_string(b) + ": " + sub->last_error);
+      scs[i] = sub->d_sc;
+    }
+    // the group's basis on the caller's stream, after every tensor's panel
+    for (int k = 0; k < K; ++k) {
+      BATCH_HIP(h, hipEventRecord(B.done[k], B.pool[k]));
+      BATCH_HIP(h, hipStreamWaitEvent(h->stream, B.done[k], 0));
+    }
+    ctd_status rc = ensure_bdev(h, n);
+    if (rc != CTD_OK) return rc;
+    launch_basis(h->stream, args.data(), scs.data(), n, h->bdev);
+    BATCH_HIP(h, hipGetLastError());
+    BATCH_HIP(h, hipEventRecord(B.based, h->stream));
+    for (int k = 0; k < K; ++k) BATCH_HIP(h, hipStreamWaitEvent(B.pool[k], B.based, 0));
+    for (int i = 0; i < n; ++i) {
+      const int b = g0 + i;
+      ctd_handle* sub = B.subs[i];
+      rc = static_back(sub, &Xs[b], lays[b], s[b]);
+      if (rc != CTD_OK)
+        return fail(h, rc, "tensor " + std::to_string(b) + ": " + sub->last_error);
+      const StaticBufs& sb = sub->sb;
+      hipStream_t st = sub->stream;
+      const size_t ns = (size_t)s[b], off = (size_t)B.off[b];
+      BATCH_HIP(h, hipMemcpyAsync(B.scal + b, sub->d_sc, sizeof(DevScalars), hipMemcpyDeviceToDevice, st));
+      BATCH_HIP(h, hipMemcpyAsync(B.draws + off, sb.draw_fid, ns * 8, hipMemcpyDeviceToDevice, st));
+      BATCH_HIP(h, hipMemcpyAsync(B.unique + off, sb.uniq_fid, ns * 8, hipMemcpyDeviceToDevice, st));
+      BATCH_HIP(h, hipMemcpyAsync(B.accepted + off, sb.acc_fid, ns * 8, hipMemcpyDeviceToDevice, st));
+      BATCH_HIP(h, hipMemcpyAsync(B.counts + off, sb.counts, ns * 4, hipMemcpyDeviceToDevice, st));
+      BATCH_HIP(h, hipMemcpyAsync(B.prob + off, sb.prob, ns * 8, hipMemcpyDeviceToDevice, st));
+      BATCH_HIP(h, hipMemcpyAsync(B.scale + off, sb.scale, ns * 8, hipMemcpyDeviceToDevice, st));
+    }
+    g0 = g1;
   }
   // the caller's stream continues after every tensor
   for (int k = 0; k < K; ++k) {
-    BATCH_HIP(h, hipEventRecord(B.done[k], B.subs[k]->stream));
+    BATCH_HIP(h, hipEventRecord(B.done[k], B.pool[k]));
     BATCH_HIP(h, hipStreamWaitEvent(h->stream, B.done[k], 0));
   }
   return CTD_OK;

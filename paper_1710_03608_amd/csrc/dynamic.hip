@@ -690,6 +690,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       ba.ldp = b.ld;
       ba.n_rows = n_rows;
       ba.s_max = d;
+      ba.k0_max = d_ub;
       ba.uniq_fi = b.uniq_fi;
       ba.uniq_fid = b.uniq_fid;
       ba.fptr = b.fptr;
@@ -714,7 +715,9 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       ba.ldwa = S.capD;
       ba.scratch = scratch;
       ba.cap = S.capD;
-      launch_basis(st, ba, sc);
+      rc = ensure_bdev(h, 1);
+      if (rc != CTD_OK) return rc;
+      launch_basis(st, &ba, &sc, 1, h->bdev);
       mark(h, MARK_BASIS);
       // the slice's own columns R^(t+1)T dX (rows held after its filter)
       launch_cols(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total, d_next, S.C, S.capD,

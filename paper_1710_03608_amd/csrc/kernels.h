@@ -83,6 +83,7 @@ struct BasisArgs {
   int64_t ldp;
   int64_t n_rows;
   int64_t s_max;             // host bound of s'
+  int64_t k0_max;            // host bound of the basis columns held before this call
   const int32_t* uniq_fi;    // candidate fiber positions (ascending)
   const uint64_t* uniq_fid;  // candidate fiber ids
   const int32_t* fptr;
@@ -109,7 +110,13 @@ struct BasisArgs {
   int64_t cap;               // column capacity of Q, M, W (>= final k + 64)
 };
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap);
-void launch_basis(hipStream_t st, const BasisArgs& a, DevScalars* sc);
+// Device bytes of the argument array for `count` inputs.
+size_t basis_dev_bytes(int count);
+// The basis of `count` independent inputs (args[i] with scalars scs[i]) in one
+// sequence of launches on st; dev holds basis_dev_bytes(count) device bytes
+// that stay untouched by others until the launches have run.
+void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs, int count,
+                  void* dev);
 
 // ---- project.hip -----------------------------------------------------------
 // A8: per-fiber residual ||x_f||^2 - ||Q^T x_f||^2 (0 for marked fibers) and

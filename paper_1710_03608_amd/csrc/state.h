@@ -84,12 +84,16 @@ struct DynState {
   size_t ws_bytes = 0;
 };
 
-// Many independent tensors in one call: tensors are spread over sub-handles
-// that own their streams; per-tensor results are copied into batch storage.
+// Many independent tensors in one call: tensors go in groups, one sub-handle
+// (own workspace) per tensor of a group; their per-tensor stages run on a
+// pool of streams and the basis of the whole group in one launch sequence;
+// per-tensor results are copied into batch storage.
 struct BatchState {
-  std::vector<ctd_handle*> subs;
-  std::vector<hipEvent_t> done;
+  std::vector<hipStream_t> pool;
+  std::vector<hipEvent_t> done;    // one per pool stream
+  std::vector<ctd_handle*> subs;   // one per tensor slot of a group
   hipEvent_t start = nullptr;
+  hipEvent_t based = nullptr;
   int32_t B = 0;
   std::vector<int64_t> s, off, rows;
   DevScalars* scal = nullptr;      // [B] scalars of each tensor
@@ -128,7 +132,8 @@ struct ctd_handle {
   bool has_static = false;
   bool dyn_ready = false;
   bool last_was_update = false;
-  bool own_stream = false;          // sub-handle of a batch: the stream is ours
+  void* bdev = nullptr;             // device array of basis arguments
+  int bdev_cap = 0;
   ctd::BatchState* batch = nullptr;
 };
 
@@ -151,6 +156,12 @@ ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay
                          uint32_t tensor);
 ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
                       uint64_t seed, const uint64_t* given, uint32_t tensor);
+ctd_status static_front(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
+                        uint64_t seed, const uint64_t* given, uint32_t tensor, BasisArgs* ba);
+ctd_status static_back(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s);
+ctd_status ensure_bdev(ctd_handle* h, int count);
+size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C,
+                    int64_t max_cols);
 int key_bits(const FiberLayout& lay);
 ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const float* Qf,
                          int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max);

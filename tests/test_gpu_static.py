@@ -83,6 +83,22 @@ def test_other_modes(lib, mode):
     check_parity(g, o)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rank_saturation(lib, precision):
+    """Far more candidates than rows: once the kept fibers span all 12 rows
+    every later candidate has a zero residual and is skipped, and the
+    reconstruction is exact."""
+    X = synth.power_law_tensor((12, 60, 30), 5000, 21, zipf_a=1.1)
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 400, 3)
+    assert len(o.accepted) == 12 and len(o.uniq) > 100
+    g = run_gpu(lib, X, 0, 400, 3, precision=precision)
+    if precision == "fp64":
+        check_parity(g, o)
+    else:
+        check_parity(g, o, rtol=RTOL_MIXED, atol=1e-6)
+    assert g["rel_err"] < 1e-6
+
+
 def test_float32_values_give_identical_draws(lib):
     X = synth.tiny_uniform()
     g64 = run_gpu(lib, X, 0, 100, 5)
