@@ -119,7 +119,7 @@ struct PlanItem {
   size_t bytes;
 };
 // The workspace of one CTD-S call (or one CTD-D slice), as a list of buffers.
-void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C,
+void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C, bool want_R,
                   int64_t max_cols, StaticBufs* b, std::vector<PlanItem>& items) {
   const int64_t n = std::max<int64_t>(nnz, 1);
   const int64_t ld = round8(s);
@@ -159,16 +159,16 @@ void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_
   add(&b->long_list, n_long * 4);
   add(&b->long_part, n_long * long_ld * 8);
   add(&b->partial, ((n + 8191) / 8192 + 1) * 8);
-  add(&b->Rs, n_rows * ld * 8);
+  add(&b->Rs, want_R ? n_rows * ld * 8 : 8);
   add(&b->C, want_C ? (size_t)ld * n * 8 : 8);
 }
 }  // namespace
 
-size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C,
+size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C, bool want_R,
                     int64_t max_cols) {
   StaticBufs tmp{};
   std::vector<PlanItem> items;
-  static_items(nnz, s, n_rows, mixed, want_C, max_cols, &tmp, items);
+  static_items(nnz, s, n_rows, mixed, want_C, want_R, max_cols, &tmp, items);
   Arena A;
   for (auto& it : items) (void)A.take(it.bytes);
   return A.off;
@@ -176,13 +176,13 @@ size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool wan
 
 // Plan the workspace of one CTD-S call (or one CTD-D slice) and bind pointers.
 ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
-                       bool want_C, int64_t max_cols, StaticBufs* b) {
+                       bool want_C, bool want_R, int64_t max_cols, StaticBufs* b) {
   Arena& A = h->arena;
   A.reset();
   const int64_t ld = round8(s);
   const int64_t long_ld = std::max<int64_t>(1, (std::max(max_cols, ld) + kChunkCols - 1) / kChunkCols);
   std::vector<PlanItem> items;
-  static_items(nnz, s, n_rows, mixed, want_C, max_cols, b, items);
+  static_items(nnz, s, n_rows, mixed, want_C, want_R, max_cols, b, items);
   std::vector<size_t> offs;
   for (auto& it : items) offs.push_back((size_t)A.take(it.bytes));
   if (A.off > A.cap) {
@@ -325,7 +325,7 @@ ctd_status static_front(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay,
   const int64_t nnz = X->nnz;
   const int64_t n_rows = lay.n_rows;
   StaticBufs& b = h->sb;
-  ctd_status rc = plan_static(h, nnz, s, n_rows, mixed, want_C, round8(s), &b);
+  ctd_status rc = plan_static(h, nnz, s, n_rows, mixed, want_C, h->keep_R, round8(s), &b);
   if (rc != CTD_OK) return rc;
   DevScalars* sc = h->d_sc;
   for (bool& u : h->ev_used) u = false;
@@ -351,7 +351,7 @@ ctd_status static_front(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay,
   ba->Q = b.Q;
   ba->ldq = b.ld;
   ba->Qf = mixed ? b.Qf : nullptr;
-  ba->R = b.Rs;
+  ba->R = h->keep_R ? b.Rs : nullptr;
   ba->ldr = b.ld;
   ba->M = b.M;
   ba->ldm = b.ld;

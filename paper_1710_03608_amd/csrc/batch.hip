@@ -20,7 +20,7 @@ namespace ctd {
 namespace {
 constexpr int kBatchStreams = 8;
 constexpr int kMaxGroup = 4096;                      // tensors per group
-constexpr size_t kGroupBytes = size_t(32) << 30;     // workspace budget per group
+constexpr size_t kGroupBytes = size_t(64) << 30;     // workspace budget per group
 
 #define BATCH_HIP(h, expr)                                                              \
   do {                                                                                  \
@@ -32,6 +32,7 @@ constexpr size_t kGroupBytes = size_t(32) << 30;     // workspace budget per gro
 ctd_status new_sub(ctd_handle* h, ctd_handle** out) {
   ctd_handle* sub = new ctd_handle();
   sub->opt = h->opt;
+  sub->keep_R = false;
   if (hipMalloc(&sub->d_sc, sizeof(DevScalars)) != hipSuccess) {
     (void)hipGetLastError();
     delete sub;
@@ -144,7 +145,8 @@ extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, in
     int g1 = g0;
     size_t bytes = 0;
     while (g1 < nb && g1 - g0 < kMaxGroup) {
-      const size_t t = static_bytes(Xs[g1].nnz, s[g1], lays[g1].n_rows, mixed, false, round8(s[g1]));
+      const size_t t = static_bytes(Xs[g1].nnz, s[g1], lays[g1].n_rows, mixed, false, false,
+                                    round8(s[g1]));
       if (g1 > g0 && bytes + t > kGroupBytes) break;
       bytes += t;
       ++g1;

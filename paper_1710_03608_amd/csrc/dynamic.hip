@@ -640,7 +640,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
     }
   }
   StaticBufs& b = h->sb;
-  rc = plan_static(h, nnz_max, d, n_rows, mixed, false, S.capD, &b);
+  rc = plan_static(h, nnz_max, d, n_rows, mixed, false, false, S.capD, &b);
   if (rc != CTD_OK) return rc;
   // workspace: block-filter scratch, W rows of the batch's kept fibers, cross
   // rows, slice records and pass ranges

@@ -132,6 +132,7 @@ struct ctd_handle {
   bool has_static = false;
   bool dyn_ready = false;
   bool last_was_update = false;
+  bool keep_R = true;               // keep the dense kept fibers R (not needed inside a batch)
   void* bdev = nullptr;             // device array of basis arguments
   int bdev_cap = 0;
   ctd::BatchState* batch = nullptr;
@@ -150,7 +151,7 @@ ctd_status fail(ctd_handle* h, ctd_status st, const std::string& msg);
 ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout* lay,
                      uint64_t* n_cols_total);
 ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
-                       bool want_C, int64_t max_cols, StaticBufs* b);
+                       bool want_C, bool want_R, int64_t max_cols, StaticBufs* b);
 ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
                          uint64_t seed, uint32_t step, const uint64_t* given, StaticBufs& b,
                          uint32_t tensor);
@@ -160,7 +161,7 @@ ctd_status static_front(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay,
                         uint64_t seed, const uint64_t* given, uint32_t tensor, BasisArgs* ba);
 ctd_status static_back(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s);
 ctd_status ensure_bdev(ctd_handle* h, int count);
-size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C,
+size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C, bool want_R,
                     int64_t max_cols);
 int key_bits(const FiberLayout& lay);
 ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const float* Qf,
