@@ -169,9 +169,12 @@ ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B, i
 /* Many independent tensors in one call (the batched execution form of
  * CTD-S): tensor b of the host array Xs[0..B) gets Algorithm 1 with s[b]
  * draws in mode `mode`, its draws using Philox counter word tensor = b
- * (tensor 0 reproduces ctd_decompose).  Tensors run concurrently on internal
- * streams of default priority, ordered after the caller's earlier work on
- * the handle's stream; later work on that stream runs after all of them.
+ * (tensor 0 reproduces ctd_decompose).  Tensors go in groups within a
+ * workspace budget: the per-tensor stages run concurrently on internal
+ * streams of default priority, and the independence filter and basis of a
+ * whole group run as one sequence of launches on the handle's stream.  All
+ * of it is ordered after the caller's earlier work on that stream, and later
+ * work on it runs after all of them.
  * Per-tensor results are read with ctd_get_batch_result; the handle's own
  * CTD-S / CTD-D state is left as it was.  Host argument errors are returned
  * at once; device errors are latched per tensor. */
@@ -183,6 +186,23 @@ ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, int32_t B, in
  * accepted; device memory owned by the handle until the next batched call).
  * Factor pointers are NULL.  Returns tensor b's latched device status. */
 ctd_status ctd_get_batch_result(ctd_handle* h, int32_t b, ctd_result* out);
+
+/* Attack candidates read off R (the online detection of the paper's
+ * application section, Section 5).  The kept fibers, in order of acceptance,
+ * are grouped by their coordinate in mode `group_mode` (the destination host
+ * of a source x destination x time tensor decomposed along the source mode;
+ * for the last mode of a CTD-D stream the time index counts the slices too);
+ * the earliest kept fiber of a group represents it, and representatives
+ * whose norm ||x_f|| is strictly above the mean norm of all representatives
+ * are the candidates.  Writes up to `cap` candidate fiber ids and norms, in
+ * order of acceptance, to the host arrays `fids` / `norms` (may be NULL when
+ * cap == 0), the number of candidates to *n_out (it may exceed cap) and the
+ * number of groups to *n_groups.  Needs the dense R of the last
+ * ctd_decompose / ctd_update; waits for the handle's stream.  group_mode must
+ * differ from the decomposition mode (CTD_ERR_INVALID_ARG); without a
+ * decomposition CTD_ERR_STATE. */
+ctd_status ctd_attack_candidates(ctd_handle* h, int32_t group_mode, uint64_t* fids, double* norms,
+                                 int64_t cap, int64_t* n_out, int64_t* n_groups);
 
 /* Wait for the stream and return the latched device status. */
 ctd_status ctd_sync(ctd_handle* h);

@@ -22,7 +22,7 @@ STATUS = {0: "CTD_OK", 1: "CTD_ERR_INVALID_ARG", 2: "CTD_ERR_EMPTY", 3: "CTD_ERR
           8: "CTD_ERR_STATE", 9: "CTD_ERR_CAPACITY"}
 EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
            "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result", "ctd_sync",
-           "ctd_get_result", "ctd_last_error", "ctd_destroy")
+           "ctd_get_result", "ctd_last_error", "ctd_destroy", "ctd_attack_candidates")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -84,9 +84,11 @@ def load_library():
     lib.ctd_last_error.restype = ctypes.c_char_p
     lib.ctd_destroy.argtypes = [c_vp]
     lib.ctd_destroy.restype = None
+    lib.ctd_attack_candidates.argtypes = [c_vp, c_i32, c_vp, c_vp, c_i64,
+                                          ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
                  "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
-                 "ctd_sync", "ctd_get_result"):
+                 "ctd_sync", "ctd_get_result", "ctd_attack_candidates"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -242,6 +244,20 @@ class Ctd:
 
     def sync(self):
         self._check(self.lib.ctd_sync(self.h))
+
+    def attack_candidates(self, group_mode, cap=4096):
+        """Candidates read off R: fiber ids and norms (host arrays), plus the
+        number of groups (representatives)."""
+        fids = np.zeros(max(cap, 1), dtype=np.uint64)
+        norms = np.zeros(max(cap, 1), dtype=np.float64)
+        n = c_i64(0)
+        g = c_i64(0)
+        self._check(self.lib.ctd_attack_candidates(
+            self.h, int(group_mode), fids.ctypes.data_as(c_vp), norms.ctypes.data_as(c_vp),
+            int(cap), ctypes.byref(n), ctypes.byref(g)))
+        m = min(n.value, cap)
+        return {"fids": fids[:m].copy(), "norms": norms[:m].copy(), "count": n.value,
+                "n_groups": g.value}
 
     def raw_result(self):
         r = ResultStruct()

@@ -1,0 +1,96 @@
+"""Attack candidates read off R on the GPU (ctd_attack_candidates) against the
+oracle's readout (Section 5), on the GPU's own kept fibers with norms taken
+from the input data."""
+import numpy as np
+import pytest
+
+from oracle import ctd as ora
+from oracle.anomaly import attack_candidates, group_coordinate
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_1710_03608_amd as ctd
+    assert torch.cuda.is_available()
+    ctd.load_library()
+    return ctd
+
+
+def fiber_norms(tensors, mode, offsets):
+    """||x_f|| of every fiber id of the given inputs (a stream's slices carry
+    their column offset), straight from the nonzeros."""
+    out = {}
+    for X, off in zip(tensors, offsets):
+        f = ora.fiber_ids(X.dims, X.idx, mode) + off
+        order = np.argsort(f, kind="stable")
+        fs, vs = f[order], X.val[order]
+        starts = np.flatnonzero(np.r_[True, fs[1:] != fs[:-1]])
+        sums = np.add.reduceat(vs * vs, starts)
+        for fid, s2 in zip(fs[starts].tolist(), sums.tolist()):
+            out[int(fid)] = np.sqrt(s2)
+    return out
+
+
+def check_against_oracle(g, accepted, norm_of, dims, group_mode):
+    norms = np.array([norm_of[int(f)] for f in accepted])
+    c, reps, _ = attack_candidates(accepted.tolist(), norms, dims, 0, group_mode)
+    assert g["n_groups"] == len(reps)
+    assert g["count"] == len(c)
+    assert np.array_equal(g["fids"], accepted[c])
+    np.testing.assert_allclose(g["norms"], norms[c], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_readout_after_decompose(lib, precision):
+    X = synth.power_law_tensor((300, 400, 30), 20000, 9, zipf_a=1.2)
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd(precision=precision)
+    try:
+        h.decompose(dims, idx, val, 0, 300, 4)
+        accepted = h.result()["accepted"]
+        norm_of = fiber_norms([X], 0, [0])
+        for gm in (1, 2):
+            g = h.attack_candidates(gm)
+            check_against_oracle(g, accepted, norm_of, X.dims, gm)
+        # a small cap returns the first candidates and the full count
+        g_all = h.attack_candidates(1)
+        g2 = h.attack_candidates(1, cap=2)
+        assert g2["count"] == g_all["count"]
+        assert np.array_equal(g2["fids"], g_all["fids"][:2])
+        with pytest.raises(lib.CtdError):
+            h.attack_candidates(0)
+        with pytest.raises(lib.CtdError):
+            h.attack_candidates(3)
+    finally:
+        h.close()
+
+
+def test_readout_finds_injected_attacks_in_stream(lib):
+    """CTD-D with the paper's d = 10, eps = 0.15 over traffic with three
+    injected attacks: every (victim, time) is a candidate, and the readout
+    equals the oracle's on the GPU's kept fibers."""
+    a = synth.attack_stream()
+    X = a.initial
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd(precision="fp64", want_C=True, eps=0.15)
+    try:
+        h.decompose(dims, idx, val, 0, 100, 0)
+        for sl in a.slices:
+            sd, si, sv = lib.to_device(sl, "cuda")
+            h.update(sd, si, sv, 10)
+        accepted = h.result()["accepted"]
+        g = h.attack_candidates(1)
+    finally:
+        h.close()
+    I, J, T0 = X.dims
+    offsets = [0] + [(T0 + t) * J for t in range(len(a.slices))]
+    norm_of = fiber_norms([X] + a.slices, 0, offsets)
+    check_against_oracle(g, accepted, norm_of, X.dims, 1)
+    found = {(group_coordinate(int(f), X.dims, 0, 1), group_coordinate(int(f), X.dims, 0, 2))
+             for f in g["fids"]}
+    for t, victim, _ in a.attacks:
+        assert (victim, T0 + t) in found

@@ -308,3 +308,67 @@ def test_batched_tensor_word_selects_independent_draws():
     assert not np.array_equal(b0.draws, b5.draws)
     want = ctd.sample_columns(w, W, 40, 3, step=0, tensor=5)
     assert np.array_equal(b5.draws, u.fids[want])
+
+
+# ---------------------------------------------------------------------------
+# Attack candidates read off R (Section 5): group by a coordinate, first
+# fiber per group, norm strictly above the representatives' mean.
+# ---------------------------------------------------------------------------
+
+def test_attack_readout_worked_example():
+    """A 5 x 4 x 3 source x destination x time tensor along the source mode:
+    fiber (j, k) has id j + 4 k.  Worked by hand."""
+    from oracle.anomaly import attack_candidates, group_coordinate
+    dims = (5, 4, 3)
+    # kept in this order: (dst 1, t 0), (dst 2, t 0), (dst 1, t 2), (dst 3, t 1)
+    accepted = [1, 2, 9, 7]
+    norms = [2.0, 1.0, 10.0, 6.0]
+    # by destination: representatives are positions 0, 1, 3 (position 2 repeats
+    # destination 1); mean (2 + 1 + 6) / 3 = 3, so only position 3 is above it
+    c, reps, mean = attack_candidates(accepted, norms, dims, 0, 1)
+    assert reps == [0, 1, 3] and mean == 3.0 and c == [3]
+    # by time: representatives 0 (t 0), 2 (t 2), 3 (t 1); mean (2 + 10 + 6) / 3
+    # = 6, and 6 itself is not above it
+    c, reps, mean = attack_candidates(accepted, norms, dims, 0, 2)
+    assert reps == [0, 2, 3] and mean == 6.0 and c == [2]
+    # a stream's time index grows past the initial length and decodes as is
+    assert group_coordinate(3 + 4 * 7, dims, 0, 2) == 7
+    assert group_coordinate(3 + 4 * 7, dims, 0, 1) == 3
+    with pytest.raises(ValueError):
+        group_coordinate(5, dims, 0, 0)
+
+
+def test_attack_readout_invariants():
+    from oracle.anomaly import attack_candidates
+    rng = np.random.default_rng(3)
+    dims = (50, 30, 40)
+    accepted = rng.choice(30 * 40, size=200, replace=False).tolist()
+    norms = rng.lognormal(0.0, 1.0, 200)
+    c, reps, mean = attack_candidates(accepted, norms, dims, 0, 1)
+    assert len(reps) == len({f % 30 for f in accepted})
+    # a positive common scale changes no decision
+    c2, reps2, _ = attack_candidates(accepted, 7.5 * norms, dims, 0, 1)
+    assert c2 == c and reps2 == reps
+    # equal norms: nothing is above the mean; one group: nothing either
+    assert attack_candidates(accepted, np.ones(200), dims, 0, 1)[0] == []
+    same_dst = [3 + 30 * k for k in range(10)]
+    assert attack_candidates(same_dst, np.arange(1.0, 11.0), dims, 0, 1)[0] == []
+
+
+def test_attack_readout_finds_injected_attacks():
+    """CTD-D with the paper's d = 10, eps = 0.15 on traffic with three injected
+    attacks (20 % of the sources each hit one victim): every (victim, time)
+    of an attack is among the candidates."""
+    from oracle.anomaly import attack_candidates, group_coordinate
+    a = synth.attack_stream()
+    X = a.initial
+    D = ctd.Dynamic(X.dims, X.idx, X.val, 0, 100, 0, eps=0.15)
+    for sl in a.slices:
+        D.update(sl.dims, sl.idx, sl.val, 10)
+    norms = np.sqrt((D.R * D.R).sum(axis=0))
+    c, _, _ = attack_candidates(D.accepted, norms, D.dims, 0, 1)
+    found = {(group_coordinate(D.accepted[i], D.dims, 0, 1),
+              group_coordinate(D.accepted[i], D.dims, 0, 2)) for i in c}
+    T0 = X.dims[2]
+    for t, victim, _ in a.attacks:
+        assert (victim, T0 + t) in found

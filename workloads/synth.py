@@ -258,6 +258,57 @@ def traffic_stream(dims=(4000, 4000, 200), nnz0=1_000_000, n_slices=200,
     return Stream(initial, slices, steps, blocks)
 
 
+@dataclasses.dataclass
+class AttackStream:
+    initial: CooTensor          # I x J x T0 normal traffic
+    slices: list                # list of CooTensor, each I x J x 1
+    attacks: list               # (slice number, victim destination, attacking sources)
+
+
+def attack_stream(dims=(300, 400, 10), nnz0=20_000, n_slices=20, slice_nnz=(500, 2000),
+                  zipf_a=1.1, n_attacks=3, attacker_frac=0.2, seed=8) -> AttackStream:
+    """Traffic with injected DDoS attacks (the setting of the paper's application
+    section): normal source x destination traffic under Zipf(zipf_a) degrees, and
+    `n_attacks` slices in which a randomly chosen `attacker_frac` of all sources
+    each send lognormal(ln 20, 0.25) traffic to one victim destination.  The
+    victims are destinations that normal traffic never reaches, so that each
+    attack is a new activity in R.
+    """
+    I, J, T0 = (int(d) for d in dims)
+    rng = _rng(seed)
+    perm_src = rng.permutation(I)
+    perm_dst = rng.permutation(J)
+    victims_all = perm_dst[J - n_attacks:]          # reserved for the attacks
+    normal_dst = perm_dst[:J - n_attacks]
+
+    def normal(n, t_len):
+        def draw(m):
+            return (_zipf_indices(rng, I, zipf_a, m, perm_src),
+                    _zipf_indices(rng, J - n_attacks, zipf_a, m, normal_dst),
+                    rng.integers(0, t_len, m))
+        idx = _distinct(draw, (I, J, t_len), n, rng)
+        return idx, _f32(rng.lognormal(0.0, 1.0, n))
+
+    idx0, v0 = normal(nnz0, T0)
+    initial = CooTensor((I, J, T0), idx0.astype(np.int32), v0)
+    steps = sorted(rng.choice(n_slices, size=n_attacks, replace=False).tolist())
+    attacks = []
+    slices = []
+    for t in range(n_slices):
+        idx, v = normal(int(rng.integers(slice_nnz[0], slice_nnz[1] + 1)), 1)
+        if t in steps:
+            victim = int(victims_all[len(attacks)])
+            srcs = np.sort(rng.choice(I, size=max(1, int(round(attacker_frac * I))), replace=False))
+            attacks.append((t, victim, srcs))
+            add_idx = np.stack([srcs, np.full(srcs.shape[0], victim), np.zeros(srcs.shape[0], np.int64)])
+            idx = np.concatenate([idx, add_idx.astype(idx.dtype)], axis=1)
+            v = np.concatenate([v, _f32(rng.lognormal(math.log(20.0), 0.25, srcs.shape[0]))])
+            p = rng.permutation(v.shape[0])
+            idx, v = idx[:, p], v[p]
+        slices.append(CooTensor((I, J, 1), idx.astype(np.int32), v))
+    return AttackStream(initial, slices, attacks)
+
+
 def many_tensors(n_tensors=512, seed=5, ij=(500, 5000), k=(20, 200),
                  nnz=(10_000, 200_000), zipf_a=1.2) -> list:
     """Independent tensors of uneven shape and size (uniform(0,1] values)."""
