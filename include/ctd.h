@@ -204,6 +204,18 @@ ctd_status ctd_get_batch_result(ctd_handle* h, int32_t b, ctd_result* out);
 ctd_status ctd_attack_candidates(ctd_handle* h, int32_t group_mode, uint64_t* fids, double* norms,
                                  int64_t cap, int64_t* n_out, int64_t* n_groups);
 
+/* Memory usage of the factors (Eq. 15): (nnz(C) + nnz(U) + nnz(R)) / nnz(X),
+ * X being all input held (CTD-D: the initial tensor and every slice).
+ * nnz(R) and nnz(C) count the nonzero entries of the kept fibers and of C;
+ * nnz(U) counts U = (R^T R)^{-1} structurally: kept fibers that share a row
+ * are linked, U is block diagonal over the connected groups, and each group
+ * of g fibers contributes g^2.  Needs C (want_C); waits for the stream. */
+typedef struct {
+  int64_t nnz_C, nnz_U, nnz_R, nnz_X;
+  double usage;
+} ctd_memory;
+ctd_status ctd_memory_usage(ctd_handle* h, ctd_memory* out);
+
 /* Wait for the stream and return the latched device status. */
 ctd_status ctd_sync(ctd_handle* h);
 

@@ -22,7 +22,8 @@ STATUS = {0: "CTD_OK", 1: "CTD_ERR_INVALID_ARG", 2: "CTD_ERR_EMPTY", 3: "CTD_ERR
           8: "CTD_ERR_STATE", 9: "CTD_ERR_CAPACITY"}
 EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
            "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result", "ctd_sync",
-           "ctd_get_result", "ctd_last_error", "ctd_destroy", "ctd_attack_candidates")
+           "ctd_get_result", "ctd_last_error", "ctd_destroy", "ctd_attack_candidates",
+           "ctd_memory_usage")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -48,6 +49,11 @@ class ResultStruct(ctypes.Structure):
                 ("Q", c_vp), ("ldq", c_i64), ("Linv_t", c_vp), ("ldx", c_i64),
                 ("R", c_vp), ("ldr", c_i64), ("C", c_vp), ("ldc", c_i64), ("n_cols", c_i64),
                 ("col_ids", c_vp), ("fiber_ids", c_vp), ("fiber_resid", c_vp)]
+
+
+class MemoryStruct(ctypes.Structure):
+    _fields_ = [("nnz_C", c_i64), ("nnz_U", c_i64), ("nnz_R", c_i64), ("nnz_X", c_i64),
+                ("usage", ctypes.c_double)]
 
 
 class CtdError(RuntimeError):
@@ -86,9 +92,10 @@ def load_library():
     lib.ctd_destroy.restype = None
     lib.ctd_attack_candidates.argtypes = [c_vp, c_i32, c_vp, c_vp, c_i64,
                                           ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
+    lib.ctd_memory_usage.argtypes = [c_vp, ctypes.POINTER(MemoryStruct)]
     for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
                  "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
-                 "ctd_sync", "ctd_get_result", "ctd_attack_candidates"):
+                 "ctd_sync", "ctd_get_result", "ctd_attack_candidates", "ctd_memory_usage"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -244,6 +251,13 @@ class Ctd:
 
     def sync(self):
         self._check(self.lib.ctd_sync(self.h))
+
+    def memory_usage(self):
+        """Eq. 15: nnz of C, U (structural) and R, nnz of the input, and the ratio."""
+        m = MemoryStruct()
+        self._check(self.lib.ctd_memory_usage(self.h, ctypes.byref(m)))
+        return {"nnz_C": m.nnz_C, "nnz_U": m.nnz_U, "nnz_R": m.nnz_R, "nnz_X": m.nnz_X,
+                "usage": m.usage}
 
     def attack_candidates(self, group_mode, cap=4096):
         """Candidates read off R: fiber ids and norms (host arrays), plus the

@@ -393,6 +393,7 @@ ctd_status static_back(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, 
   HIP_TRY(h, hipGetLastError());
   h->s = s;
   h->n_rows = n_rows;
+  h->nnz_seen = nnz;
   h->step = 0;
   h->has_static = true;
   h->last_was_update = false;

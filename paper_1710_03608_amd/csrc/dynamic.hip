@@ -768,6 +768,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
   S.T += B;
   S.d_ub = d_ub;
   S.n_cols_ub += nnz_sum;
+  h->nnz_seen += nnz_sum;
   return CTD_OK;
 }
 

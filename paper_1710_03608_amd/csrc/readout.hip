@@ -9,7 +9,14 @@
 // The norms are column norms of the dense R on the device (one thread per
 // kept fiber, rows summed in order); grouping and selection run on the host
 // over the s~ kept fibers, which is O(s~) work after an O(I_alpha s~) pass.
+//
+// The memory usage of the factors (Eq. 15) counts nonzeros of R and C on the
+// device; U = (R^T R)^{-1} is block diagonal over the groups of kept fibers
+// linked by shared rows, so its nonzeros are counted from R's pattern on the
+// host (union-find over the rows).
 #include <math.h>
+
+#include <algorithm>
 
 #include <string>
 #include <unordered_map>
@@ -42,6 +49,37 @@ __global__ __launch_bounds__(kBlock) void k_col_norms(const double* __restrict__
     if (_e != hipSuccess)                                                               \
       return fail(h, CTD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));   \
   } while (0)
+
+// Nonzero entries of an outer x inner strided block (element (o, i) at
+// p[o * ld + i]), added into *count.
+__global__ __launch_bounds__(kBlock) void k_count_nz(const double* __restrict__ p, int64_t outer,
+                                                     int64_t inner, int64_t ld,
+                                                     unsigned long long* count) {
+  __shared__ unsigned long long part[kBlock / kWave];
+  unsigned long long c = 0;
+  const int64_t total = outer * inner;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t o = t / inner, i = t % inner;
+    c += p[o * ld + i] != 0.0 ? 1ull : 0ull;
+  }
+  for (int off = kWave / 2; off > 0; off /= 2) c += __shfl_down(c, off, kWave);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) s += part[w];
+    atomicAdd(count, s);
+  }
+}
+
+int64_t find_root(std::vector<int64_t>& parent, int64_t a) {
+  while (parent[a] != a) {
+    parent[a] = parent[parent[a]];
+    a = parent[a];
+  }
+  return a;
+}
 
 // Coordinate in mode m of a fiber id (column-major over the non-alpha modes);
 // the last of those modes is not reduced modulo its length (a stream's time
@@ -114,5 +152,70 @@ extern "C" ctd_status ctd_attack_candidates(ctd_handle* h, int32_t group_mode, u
   }
   *n_out = n;
   *n_groups = (int64_t)reps.size();
+  return CTD_OK;
+}
+
+extern "C" ctd_status ctd_memory_usage(ctd_handle* h, ctd_memory* out) {
+  if (!h) return CTD_ERR_INVALID_ARG;
+  h->last_error.clear();
+  if (!out) return fail(h, CTD_ERR_INVALID_ARG, "out is NULL");
+  if (!h->has_static) return fail(h, CTD_ERR_STATE, "no decomposition held");
+  RO_HIP(h, hipStreamSynchronize(h->stream));
+  DevScalars sc{};
+  RO_HIP(h, hipMemcpy(&sc, h->d_sc, sizeof(sc), hipMemcpyDeviceToHost));
+  if (sc.status != 0) return fail(h, (ctd_status)sc.status, "device reported an error");
+  ctd_result res{};
+  fill_result(h, sc, &res);
+  if (!res.C) return fail(h, CTD_ERR_STATE, "C is not held (create the handle with want_C)");
+  if (!res.R) return fail(h, CTD_ERR_STATE, "the dense R is not held");
+  const int64_t k = res.s_tilde, n_rows = h->n_rows;
+  *out = ctd_memory{};
+  out->nnz_X = h->nnz_seen;
+  unsigned long long* d_cnt = nullptr;
+  RO_HIP(h, hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)));
+  hipError_t e = hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), h->stream);
+  if (e == hipSuccess && k > 0) {
+    hipLaunchKernelGGL(k_count_nz, dim3(1024), dim3(kBlock), 0, h->stream, res.R, n_rows, k,
+                       res.ldr, d_cnt);
+    hipLaunchKernelGGL(k_count_nz, dim3(1024), dim3(kBlock), 0, h->stream, res.C, res.n_cols, k,
+                       res.ldc, d_cnt + 1);
+    e = hipGetLastError();
+  }
+  unsigned long long cnt[2] = {0, 0};
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipMemcpy(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost);
+  // rows of R for the structure of U (host copy of the k kept columns)
+  std::vector<double> Rh;
+  if (e == hipSuccess && k > 0) {
+    Rh.resize((size_t)n_rows * k);
+    e = hipMemcpy2D(Rh.data(), (size_t)k * 8, res.R, (size_t)res.ldr * 8, (size_t)k * 8,
+                    (size_t)n_rows, hipMemcpyDeviceToHost);
+  }
+  (void)hipFree(d_cnt);
+  if (e != hipSuccess) return fail(h, CTD_ERR_HIP, std::string("memory usage: ") + hipGetErrorString(e));
+  out->nnz_R = (int64_t)cnt[0];
+  out->nnz_C = (int64_t)cnt[1];
+  // kept fibers sharing a row belong to one diagonal block of U
+  std::vector<int64_t> parent(k);
+  for (int64_t a = 0; a < k; ++a) parent[a] = a;
+  for (int64_t r = 0; r < n_rows; ++r) {
+    int64_t prev = -1;
+    for (int64_t a = 0; a < k; ++a) {
+      if (Rh[(size_t)r * k + a] == 0.0) continue;
+      if (prev >= 0) {
+        const int64_t x = find_root(parent, prev), y = find_root(parent, a);
+        if (x != y) parent[std::max(x, y)] = std::min(x, y);
+      }
+      prev = a;
+    }
+  }
+  std::vector<int64_t> size(k, 0);
+  for (int64_t a = 0; a < k; ++a) ++size[find_root(parent, a)];
+  int64_t nu = 0;
+  for (int64_t a = 0; a < k; ++a) nu += size[a] * size[a];
+  out->nnz_U = nu;
+  out->usage = out->nnz_X > 0
+                   ? (double)(out->nnz_C + out->nnz_U + out->nnz_R) / (double)out->nnz_X
+                   : 0.0;
   return CTD_OK;
 }

@@ -94,3 +94,47 @@ def test_readout_finds_injected_attacks_in_stream(lib):
              for f in g["fids"]}
     for t, victim, _ in a.attacks:
         assert (victim, T0 + t) in found
+
+
+def test_memory_usage_ctd_s(lib):
+    """Eq. 15 on the GPU equals the oracle's count from its own R and C
+    (same kept fibers in float64; positive values, so no entry of C cancels)."""
+    from oracle.metrics import memory_usage
+    X = synth.power_law_tensor((300, 400, 30), 20000, 9, zipf_a=1.2)
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 300, 4, want_C=True)
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd(precision="fp64", want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, 300, 4)
+        assert np.array_equal(h.result()["accepted"], o.accepted.astype(np.uint64))
+        m = h.memory_usage()
+    finally:
+        h.close()
+    nc, nu, nr, usage = memory_usage(o.R, o.C, X.nnz)
+    assert (m["nnz_C"], m["nnz_U"], m["nnz_R"], m["nnz_X"]) == (nc, nu, nr, X.nnz)
+    assert m["usage"] == pytest.approx(usage, rel=1e-15)
+
+
+def test_memory_usage_ctd_d(lib):
+    """Eq. 15 after CTD-D updates: nnz(X) counts every slice, and the counts
+    equal the oracle's on the same stream (the cross-term rows of C fill in)."""
+    from oracle.metrics import memory_usage
+    st = synth.traffic_stream(dims=(60, 50, 12), nnz0=2500, n_slices=6, slice_nnz=(60, 400),
+                              zipf_a=1.1, n_anomalies=1, block=6, seed=5)
+    o = ora.Dynamic(st.initial.dims, st.initial.idx, st.initial.val, 0, 40, 5)
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(precision="fp64", want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, 40, 5)
+        for sl in st.slices:
+            o.update(sl.dims, sl.idx, sl.val, 6)
+            sd, si, sv = lib.to_device(sl, "cuda")
+            h.update(sd, si, sv, 6)
+        assert np.array_equal(h.result()["accepted"], np.asarray(o.accepted, dtype=np.uint64))
+        m = h.memory_usage()
+    finally:
+        h.close()
+    total = st.initial.nnz + sum(sl.nnz for sl in st.slices)
+    nc, nu, nr, usage = memory_usage(o.R, o.C, total)
+    assert (m["nnz_U"], m["nnz_R"], m["nnz_X"]) == (nu, nr, total)
+    assert m["nnz_C"] == nc

@@ -372,3 +372,46 @@ def test_attack_readout_finds_injected_attacks():
     T0 = X.dims[2]
     for t, victim, _ in a.attacks:
         assert (victim, T0 + t) in found
+
+
+# ---------------------------------------------------------------------------
+# Memory usage of the factors (Eq. 15)
+# ---------------------------------------------------------------------------
+
+def test_memory_usage_worked_example():
+    """R's fibers a (rows 0, 1), b (rows 1, 2) and c (row 5) on a 6 x 4 matrix
+    X: a and b share row 1, so U = (R^T R)^{-1} has a dense 2 x 2 block and a
+    1 x 1 block, 5 nonzeros; the inverse computed directly agrees."""
+    from oracle.metrics import memory_usage, structural_nnz_U
+    R = np.zeros((6, 3))
+    R[[0, 1], 0] = [1.0, 2.0]
+    R[[1, 2], 1] = [3.0, 1.0]
+    R[5, 2] = 4.0
+    U = np.linalg.inv(R.T @ R)
+    assert structural_nnz_U(R) == 5 == int(np.count_nonzero(np.abs(U) > 1e-12))
+    X = np.zeros((6, 4))
+    X[0, 0] = 1.0      # meets a only
+    X[2, 1] = 1.0      # meets b only
+    X[4, 2] = 1.0      # meets nothing: an empty column of C
+    X[1, 3] = X[5, 3] = 1.0   # meets a, b and c
+    C = R.T @ X
+    nc, nu, nr, usage = memory_usage(R, C, int(np.count_nonzero(X)))
+    assert (nc, nu, nr) == (1 + 1 + 0 + 3, 5, 5)
+    assert usage == (5 + 5 + 5) / 5
+
+
+def test_structural_U_matches_inverse_on_block_data():
+    """Fibers drawn inside disjoint row blocks: the structural count equals the
+    nonzeros of the explicitly inverted Gram."""
+    from oracle.metrics import structural_nnz_U
+    rng = np.random.default_rng(4)
+    R = np.zeros((40, 12))
+    blocks = [(0, 10, [0, 1, 2, 3]), (10, 25, [4, 5, 6]), (25, 40, [7, 8, 9, 10, 11])]
+    for r0, r1, cols in blocks:
+        for c in cols:
+            rows = rng.choice(np.arange(r0, r1), size=5, replace=False)
+            R[rows, c] = rng.random(5) + 0.5
+    U = np.linalg.inv(R.T @ R)
+    expect = int(np.count_nonzero(np.abs(U) > 1e-12 * np.abs(U).max()))
+    assert structural_nnz_U(R) <= 16 + 9 + 25
+    assert structural_nnz_U(R) == expect
