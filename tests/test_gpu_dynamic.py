@@ -173,3 +173,24 @@ def test_batched_update_argument_checks(lib):
         assert h.result()["step"] == 1
     finally:
         h.close()
+
+
+def test_four_way_stream_matches_oracle(lib):
+    """CTD-D on a 4-way tensor (time last) along mode 0."""
+    X = synth.uniform_tensor((40, 10, 8, 6), 2000, 41)
+    slices = [synth.uniform_tensor((40, 10, 8, 1), 150 + 40 * t, 50 + t) for t in range(5)]
+    o = ora.Dynamic(X.dims, X.idx, X.val, 0, 25, 3)
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd(precision="fp64", want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, 25, 3)
+        for sl in slices:
+            o.update(sl.dims, sl.idx, sl.val, 5)
+            sd, si, sv = lib.to_device(sl, "cuda")
+            h.update(sd, si, sv, 5)
+            r = h.result()
+            assert np.array_equal(r["accepted"], np.asarray(o.accepted, dtype=np.uint64))
+            rel = o.err2 / o.norm2
+            assert abs(r["rel_err"] - rel) <= 1e-6 * rel + 1e-12, (r["rel_err"], rel)
+    finally:
+        h.close()

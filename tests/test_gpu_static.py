@@ -228,3 +228,19 @@ def test_planted_rank20_full_size_noisy(lib, planted, precision):
     # at most the noise (plus what the noise contributes to the kept fibers)
     noise2 = float(np.sum(noisy.val ** 2)) - float(np.sum(clean.val ** 2))
     assert g["rel_err"] <= 1.5 * abs(noise2) / float(np.sum(noisy.val ** 2))
+
+
+@pytest.mark.parametrize("dims,nnz,mode,s", [((300, 200), 5000, 0, 80), ((300, 200), 5000, 1, 80),
+                                             ((60, 15, 12, 10), 8000, 0, 40),
+                                             ((20, 15, 60, 10), 8000, 2, 40),
+                                             ((20, 15, 12, 10), 8000, 3, 150),
+                                             ((6, 7, 5, 4, 40), 3000, 4, 30)])
+def test_general_order_and_mode(lib, dims, nnz, mode, s):
+    """Matrices and 4- and 5-way tensors along any mode (the fiber id is
+    column-major over the other modes in increasing order)."""
+    X = synth.uniform_tensor(dims, nnz, 31 + len(dims) + mode)
+    o = ora.ctd_s(X.dims, X.idx, X.val, mode, s, 9)
+    g = run_gpu(lib, X, mode, s, 9)
+    if borderline(o):
+        pytest.skip("candidate within rounding of the threshold")
+    check_parity(g, o)
