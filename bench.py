@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-stream", action="store_true", help="skip the CTD-D stream leg")
     ap.add_argument("--stream-only", action="store_true", help="run only the CTD-D stream leg")
+    ap.add_argument("--stream-batches", default=f"1,{STREAM_BATCH}",
+                    help="comma-separated slices per update call for the stream leg")
     ap.add_argument("--no-many", action="store_true", help="skip the many-tensor batched leg")
     ap.add_argument("--many-only", action="store_true", help="run only the many-tensor batched leg")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -236,7 +238,7 @@ def main():
         stream_line = {"workload": "ctd_d_stream_4000x4000x200_nnz1000000_zipf1.1_200slices_s800_d8",
                        "slices": len(st.slices), "slice_nnz": slice_nnz, "modes": {}}
         for mode in args.modes.split(","):
-            for batch in (1, STREAM_BATCH):
+            for batch in [int(b) for b in args.stream_batches.split(",")]:
                 key = mode if batch == 1 else f"{mode}_batch{batch}"
                 log(f"CTD-D stream, {key}")
                 r = time_stream(ctd, st, mode, batch)

@@ -33,8 +33,6 @@ constexpr int kSplitW = 16;     // row splits of W2 = Q^T Y (at most)
 constexpr int kSplitDD = 256;   // row splits of the double-double Gram (at most)
 
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
 // One input's arguments and scratch, in device memory: every kernel below
 // serves a set of independent inputs at once, input blockIdx.z reading entry
 // blockIdx.z of the array, so a block step of many inputs is one sequence of
@@ -61,12 +59,6 @@ struct BasisDev {
 };
 static_assert(sizeof(BasisDev) % 8 == 0, "BasisDev is copied as 64-bit words");
 
-// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; the 16 x 16 result D[i][j] sits in lane j + 16 (i % 4)
-// at component i / 4 (lane l holds D[l / 16 + 4 r][l % 16], r = 0..3).
-__device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // Double-double arithmetic (a value is hi + lo with |lo| <= ulp(hi)/2): the
 // error-free transforms of Knuth (two_sum) and Dekker/FMA (two_prod).  FMA

@@ -46,6 +46,14 @@ __device__ inline void latch_status(DevScalars* sc, int code) {
 
 __device__ inline int lane_id() { return __lane_id(); }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+// v_mfma_f64_16x16x4f64 on gfx950: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; the 16 x 16 result D[i][j] sits in lane j + 16 (i % 4)
+// at component i / 4 (lane l holds D[l / 16 + 4 r][l % 16], r = 0..3).
+__device__ inline dbl4 mfma16(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll

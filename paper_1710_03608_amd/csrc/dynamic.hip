@@ -233,77 +233,102 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 
 // Cross term: C[d + a][f] = sum_{k<d} Y[a][k] C[k][f] for f in [c_lo, c_hi)
 // (d = K of the pass; pass 0 reads all of C^(t): the HBM-bound step).  Pass
-// p = blockIdx.y.  A workgroup owns 256 columns and streams them in chunks of
-// KCH rows: KCH threads read one column's contiguous rows into LDS, the next
-// chunk is prefetched into registers meanwhile, and thread t accumulates up
-// to ROWS new rows of column t from LDS, so C is read once per ROWS rows.
+// p = blockIdx.y.  A product of the 16 RT new rows with C, on f64 MFMAs: a
+// workgroup owns 256 columns, wave w the 64 columns 64 w .. + 64 (four 16-column
+// tiles) against all RT row tiles.  The reduction runs in chunks of 16 rows
+// of C; lane (i, g) = (l % 16, l / 16) reads C[k0 + 4 g .. + 4][f] of its
+// column as one 32-byte vector (C is column-major), and MFMA t multiplies
+// element t with Y[a][k0 + 4 g + t], so the four MFMAs of a chunk cover its 16
+// rows in a fixed permutation.  The 16 RT x 16 Y chunk is shared through LDS
+// (double-buffered, one barrier per chunk); the next chunk of C is in flight
+// in registers while the current one is in the MFMAs.  C is read once per
+// 16 RT new rows.
 constexpr int kCrossCols = 256;
-template <int ROWS, int KCH>
+template <int RT>
 __global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ C, int64_t ldc,
                                                            const double* __restrict__ Yall,
                                                            int64_t ldy, int64_t ystride,
                                                            const int64_t* rng_all) {
-  __shared__ double Cs[kCrossCols][KCH + 1];
-  __shared__ __align__(16) double Ys[KCH][ROWS];   // [row k][new row a]
+  constexpr int kRows = 16 * RT;
+  __shared__ dbl4 Ys[2][kRows][5];   // [buf][row a][g]: Y[a][k0 + 4 g .. + 4], padded
   const int64_t* rng = rng_all + 5 * blockIdx.y;
   const double* Y = Yall + blockIdx.y * ystride;
   const int64_t d = rng[0], na = rng[2], ncols = rng[4];
   const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
   if (na <= 0 || f0 >= ncols) return;
-  const int t = threadIdx.x;
-  const int64_t nch = (d + KCH - 1) / KCH;
-  // thread t loads rows k0 + t % KCH of columns f0 + t / KCH + (256 / KCH) u
-  constexpr int kColStep = kCrossCols / KCH;
-  const int64_t fcol = f0 + t / KCH;
-  const int rr = t % KCH;
-  const double* base = C + fcol * ldc + rr;
-  const int64_t stride = (int64_t)kColStep * ldc;
-  for (int64_t a0 = 0; a0 < na; a0 += ROWS) {
-    const int nr = (int)min<int64_t>(ROWS, na - a0);
-    double acc[ROWS];
+  const int t = threadIdx.x, w = t / kWave, l = lane_id(), i = l % 16, g = l / 16;
+  const int64_t nch = (d + 15) / 16;
+  const double* cp[4];
+  bool cin[4];
 #pragma unroll
-    for (int u = 0; u < ROWS; ++u) acc[u] = 0.0;
-    double pre[KCH];
+  for (int ct = 0; ct < 4; ++ct) {
+    const int64_t f = f0 + 64 * w + 16 * ct + i;
+    cin[ct] = f < ncols;
+    cp[ct] = C + (cin[ct] ? f : f0) * ldc + 4 * g;
+  }
+  const int yr = t / 4, yg = t % 4;   // this thread's 4 values of the Y chunk
+  // zero the elements of a 4-vector at rows k .. k + 3 that lie at or past d
+  auto mask4 = [&](dbl4 v, int64_t k) -> dbl4 {
+    v[0] = k < d ? v[0] : 0.0;
+    v[1] = k + 1 < d ? v[1] : 0.0;
+    v[2] = k + 2 < d ? v[2] : 0.0;
+    v[3] = k + 3 < d ? v[3] : 0.0;
+    return v;
+  };
+  for (int64_t a0 = 0; a0 < na; a0 += kRows) {
+    const int nr = (int)min<int64_t>(kRows, na - a0);
+    const bool yin = yr < nr;
+    const double* yrow = Y + (a0 + (yin ? yr : 0)) * ldy + 4 * yg;
+    dbl4 acc[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = dbl4{0, 0, 0, 0};
+    dbl4 cf[4], yv;
     auto load = [&](int64_t ch) {
-      const int64_t k0 = ch * KCH;
-      const bool kin = ch < nch && k0 + rr < d;
+      const int64_t k = ch * 16 + 4 * g;
 #pragma unroll
-      for (int u = 0; u < KCH; ++u) {
-        const bool in = kin && fcol + (int64_t)kColStep * u < ncols;
-        pre[u] = in ? base[k0 + u * stride] : 0.0;
+      for (int ct = 0; ct < 4; ++ct) {
+        cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const dbl4*)(cp[ct] + ch * 16) : dbl4{0, 0, 0, 0};
+        cf[ct] = mask4(cf[ct], k);
       }
+      const int64_t ky = ch * 16 + 4 * yg;
+      yv = (ch < nch && yin && ky < d) ? *(const dbl4*)(yrow + ch * 16) : dbl4{0, 0, 0, 0};
+      yv = mask4(yv, ky);
     };
     load(0);
+    int buf = 0;
     for (int64_t ch = 0; ch < nch; ++ch) {
-      __syncthreads();
+      if (yr < kRows) Ys[buf][yr][yg] = yv;
+      dbl4 cc[4];
 #pragma unroll
-      for (int u = 0; u < KCH; ++u) Cs[t / KCH + kColStep * u][rr] = pre[u];
-      for (int i = t; i < ROWS * KCH; i += kCrossCols) {
-        const int a = i / KCH, r = i % KCH;
-        const int64_t k = ch * KCH + r;
-        Ys[r][a] = (a < nr && k < d) ? Y[(a0 + a) * ldy + k] : 0.0;
-      }
+      for (int ct = 0; ct < 4; ++ct) cc[ct] = cf[ct];
       __syncthreads();
       load(ch + 1);
-#pragma unroll 2
-      for (int r = 0; r < KCH; ++r) {
-        const double cv = Cs[t][r];
-        const double2* yr = (const double2*)Ys[r];
 #pragma unroll
-        for (int u = 0; u < ROWS / 2; ++u) {
-          const double2 y = yr[u];
-          acc[2 * u] += y.x * cv;
-          acc[2 * u + 1] += y.y * cv;
+      for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const double a = Ys[buf][rt * 16 + i][g][tt];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = mfma16(a, cc[ct][tt], acc[rt][ct]);
         }
-      }
+      buf ^= 1;
     }
-    const int64_t f = f0 + t;
-    if (f < ncols) {
-      double* col = C + f * ldc + d + a0;
+    // lane (i, g) holds D[g + 4 r][i] of tile (rt, ct): new row rt * 16 + g + 4 r, column ct * 16 + i
 #pragma unroll
-      for (int u = 0; u < ROWS; ++u)
-        if (u < nr) col[u] = acc[u];
+    for (int ct = 0; ct < 4; ++ct) {
+      if (!cin[ct]) continue;
+      double* col = C + (f0 + 64 * w + 16 * ct + i) * ldc + d + a0;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = rt * 16 + g + 4 * r;
+          if (a < nr) col[a] = acc[rt][ct][r];
+        }
     }
+    __syncthreads();   // the next row block reuses Ys
   }
 }
 
@@ -752,10 +777,10 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
                        S.capD, Wacc, S.capD, Y, S.capD, ystride, rng);
     if (tiles > 0) {
       if (kept_max <= 16)
-        hipLaunchKernelGGL((k_cross_term<16, 32>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
+        hipLaunchKernelGGL((k_cross_term<1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
                            S.capD, Y, S.capD, ystride, rng);
       else
-        hipLaunchKernelGGL((k_cross_term<64, 16>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
+        hipLaunchKernelGGL((k_cross_term<4>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
                            S.capD, Y, S.capD, ystride, rng);
     }
   }
