@@ -72,10 +72,13 @@ __global__ void k_static_totals(DevScalars* sc) {
 }
 
 // Columns of R^T X: out[(col0 + f) * ldo + k] = sum_e v_e A[r_e][k] for
-// k < ncols and every fiber f < n_f.  A wave takes 64 consecutive fibers and
-// walks those of up to kLongFiber nonzeros (rows and values loaded once into
-// lanes and broadcast, two nonzeros times two 256-column chunks in flight);
-// longer ones are listed for k_spmm_long.
+// k < ncols and every fiber f < n_f.  A wave takes fpw consecutive fibers
+// (64 for a large input; a few for a small one such as a time slice, so that
+// its few fibers still spread over many waves) and walks those of up to
+// kLongFiber nonzeros (rows and values loaded once into lanes and broadcast,
+// two nonzeros times two 256-column chunks in flight) over the columns
+// [cspan y, cspan (y + 1)) of y = blockIdx.y; longer ones are listed (by the
+// y = 0 workgroups) for k_spmm_long.
 __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict__ fptr,
                                                       const int32_t* __restrict__ row,
                                                       const double* __restrict__ val,
@@ -84,22 +87,26 @@ __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict_
                                                       const int32_t* d_ncols,
                                                       double* __restrict__ out, int64_t ldo,
                                                       const int64_t* d_col0,
-                                                      int32_t* __restrict__ long_list) {
+                                                      int32_t* __restrict__ long_list, int fpw,
+                                                      int64_t cspan) {
   constexpr int VEC = 4, kCols = VEC * kWave;
   const int64_t n_f = sc->status == 0 ? sc->n_f : 0;
   const int64_t ncols = *d_ncols;
   const int64_t col0 = d_col0 ? *d_col0 : 0;
+  const int64_t c_beg = (int64_t)blockIdx.y * cspan;
+  if (c_beg >= ncols) return;
+  const int64_t c_end = min(ncols, c_beg + cspan);
   const int lane = lane_id();
   const uint64_t lt = lane == 0 ? 0ull : ((~0ull) >> (kWave - lane));
   const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
-  for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * kWave; fb < n_f;
-       fb += nwaves * kWave) {
+  for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * fpw; fb < n_f;
+       fb += nwaves * fpw) {
     const int64_t fl = fb + lane;
     int32_t len = 0;
-    if (fl < n_f) len = fptr[fl + 1] - fptr[fl];
+    if (lane < fpw && fl < n_f) len = fptr[fl + 1] - fptr[fl];
     const bool lng = len > kLongFiber;
     const uint64_t ml = __ballot(lng);
-    if (ml) {
+    if (ml && blockIdx.y == 0) {
       int32_t base = 0;
       if (lane == 0) base = atomicAdd(&sc->n_long, (int32_t)__popcll(ml));
       base = __shfl(base, 0, kWave);
@@ -115,9 +122,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict_
       const int32_t rr = lane < n ? row[e0 + lane] : 0;
       const double vv = lane < n ? val[e0 + lane] : 0.0;
       double* o = out + (col0 + f) * ldo;
-      for (int64_t c0 = 0; c0 < ncols; c0 += 2 * kCols) {
+      for (int64_t c0 = c_beg; c0 < c_end; c0 += 2 * kCols) {
         const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
-        const bool ina = ca < ncols, inb = cb < ncols;
+        const bool ina = ca < c_end, inb = cb < c_end;
         double acc0[VEC], acc1[VEC];
 #pragma unroll
         for (int k = 0; k < VEC; ++k) acc0[k] = acc1[k] = 0.0;
@@ -125,8 +132,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict_
                                   lda, acc0, acc1);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
-          if (ca + k < ncols) o[ca + k] = acc0[k];
-          if (cb + k < ncols) o[cb + k] = acc1[k];
+          if (ca + k < c_end) o[ca + k] = acc0[k];
+          if (cb + k < c_end) o[cb + k] = acc1[k];
         }
       }
     }
@@ -355,9 +362,16 @@ void launch_cols(hipStream_t st, const StaticBufs& b, int64_t nnz_max, DevScalar
                  const double* A, int64_t lda, const int32_t* d_ncols, int64_t ncols_max,
                  double* out, int64_t ldo, const int64_t* d_col0) {
   hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
-  const int gm = std::max(1, std::min(4096, (int)((nnz_max + kBlock - 1) / kBlock)));
-  hipLaunchKernelGGL(k_spmm_cols, dim3(gm), dim3(kBlock), 0, st, b.fptr, b.row, b.val, sc, A, lda,
-                     d_ncols, out, ldo, d_col0, b.long_list);
+  // a small input (a time slice) has few fibers: two per wave, and its
+  // columns split over blockIdx.y in spans of 512
+  const bool small = nnz_max <= (int64_t(1) << 18);
+  const int fpw = small ? 2 : kWave;
+  const int64_t cspan = small ? 2 * 4 * kWave : std::max<int64_t>(ncols_max, 1);
+  const int ny = (int)std::max<int64_t>(1, (ncols_max + cspan - 1) / cspan);
+  const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
+  const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
+  hipLaunchKernelGGL(k_spmm_cols, dim3(gm, ny), dim3(kBlock), 0, st, b.fptr, b.row, b.val, sc, A,
+                     lda, d_ncols, out, ldo, d_col0, b.long_list, fpw, cspan);
   const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
   const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
   const int nch = (int)std::max<int64_t>(1, (ncols_max + 4 * kWave - 1) / (4 * kWave));

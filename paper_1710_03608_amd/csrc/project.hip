@@ -22,8 +22,9 @@ constexpr int kBlock = 256;
 constexpr int kRedBlock = 1024;
 constexpr int kRedItems = 8;
 
-// Residual of every fiber.  A wave takes 64 consecutive fibers, one per
-// lane.  Kept fibers lie in span(Q) and get 0.  Fibers with one nonzero v at
+// Residual of every fiber.  A wave takes fpw consecutive fibers, one per
+// lane (64 for a large input; a few for a small one such as a time slice, so
+// that its few fibers still spread over many waves).  Kept fibers lie in span(Q) and get 0.  Fibers with one nonzero v at
 // row r are done lane-parallel from the row leverage: ||Q^T x||^2 =
 // v^2 ||Q_r||^2.  Fibers of more than kLongFiber nonzeros are listed for
 // k_proj_long.  The wave walks the rest one at a time: z_f = sum_e v_e
@@ -32,7 +33,7 @@ constexpr int kRedItems = 8;
 // broadcast, two nonzeros times two chunks of row gathers in flight.  Column
 // chunks of z are squared and summed as they complete; z is never written.
 template <typename T, int VEC>
-__global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars* sc, int fpw) {
   constexpr int kCols = VEC * kWave;
   if (sc->status != 0) return;
   const int64_t n_f = sc->n_f;
@@ -42,11 +43,11 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars
   const T* vals = sizeof(T) == 8 ? (const T*)a.val : (const T*)a.val32;
   const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
   const uint64_t lt = lane == 0 ? 0ull : ((~0ull) >> (kWave - lane));
-  for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * kWave; fb < n_f;
-       fb += nwaves * kWave) {
+  for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * fpw; fb < n_f;
+       fb += nwaves * fpw) {
     const int64_t fl = fb + lane;
     bool multi = false, lng = false;
-    if (fl < n_f) {
+    if (lane < fpw && fl < n_f) {
       const int32_t s0 = a.fptr[fl], s1 = a.fptr[fl + 1];
       const bool kept = a.fiber_mark && a.fiber_mark[fl];
       if (kept) {
@@ -189,18 +190,21 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_final(const double* __rest
 void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,
                     hipEvent_t ev0, hipEvent_t ev1) {
   hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
-  const int gm = std::max(1, std::min(4096, div_up(nnz_max, kBlock)));
+  // a small input (a time slice) has few fibers: two per wave
+  const int fpw = nnz_max <= (int64_t(1) << 18) ? 2 : kWave;
+  const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
+  const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
   const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
   const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
   const int cols = a.mixed ? 8 * kWave : 4 * kWave;
   const int nch = (int)std::max<int64_t>(1, div_up(a.ncols_max, cols));
   if (ev0) (void)hipEventRecord(ev0, st);
   if (a.mixed) {
-    hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(gm), dim3(kBlock), 0, st, a, sc);
+    hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(gm), dim3(kBlock), 0, st, a, sc, fpw);
     hipLaunchKernelGGL((k_proj_long<float, 8>), dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, a,
                        sc);
   } else {
-    hipLaunchKernelGGL((k_proj_multi<double, 4>), dim3(gm), dim3(kBlock), 0, st, a, sc);
+    hipLaunchKernelGGL((k_proj_multi<double, 4>), dim3(gm), dim3(kBlock), 0, st, a, sc, fpw);
     hipLaunchKernelGGL((k_proj_long<double, 4>), dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, a,
                        sc);
   }
