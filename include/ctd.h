@@ -60,7 +60,7 @@ typedef enum {
 } ctd_status;
 
 enum { CTD_F64 = 0, CTD_F32 = 1 };                 /* value dtype of a ctd_coo */
-enum { CTD_PREC_FP64 = 0, CTD_PREC_MIXED = 1 };    /* arithmetic of the projection */
+enum { CTD_PREC_FP64 = 0, CTD_PREC_MIXED = 1 };    /* arithmetic of the projection and of C */
 
 /* A sparse tensor in COO form.  `dims` is a host array; `idx` and `val`
  * are device arrays owned by the caller. */
@@ -74,7 +74,8 @@ typedef struct {
 } ctd_coo;
 
 typedef struct {
-  int32_t precision;        /* CTD_PREC_FP64 (all float64) or CTD_PREC_MIXED (float32 projection) */
+  int32_t precision;        /* CTD_PREC_FP64 (all float64) or CTD_PREC_MIXED (float32 projection;
+                               the CTD-D C held and updated in float32) */
   double eps;               /* tolerance of Algorithm 1's independence test (the paper uses 1e-6) */
   int32_t want_C;           /* CTD-S: also write C_(alpha) = R^T X_(alpha) (dense s~ x n_f) */
   int32_t want_fiber_stats; /* also keep per-fiber ||x_f||^2 - ||P x_f||^2 */
@@ -124,13 +125,16 @@ typedef struct {
   int64_t ldx;
   const double* R;          /* [I_alpha x ldr] row-major kept fibers (the paper's R) */
   int64_t ldr;
-  const double* C;          /* column-major C_(alpha), ldc rows per column: CTD-S n_f columns if
-                               want_C; CTD-D one column per non-empty fiber seen (n_cols) */
+  const void* C;            /* column-major C_(alpha), ldc rows per column: CTD-S n_f columns if
+                               want_C; CTD-D one column per non-empty fiber seen (n_cols);
+                               element type C_dtype */
   int64_t ldc;
   int64_t n_cols;           /* columns of C */
   const uint64_t* col_ids;  /* [n_cols] fiber id of each column of C */
   const uint64_t* fiber_ids;/* [n_f] ascending non-empty fiber ids of the last input */
   const double* fiber_resid;/* [n_f] ||x_f||^2 - ||P x_f||^2 if want_fiber_stats */
+  int32_t C_dtype;          /* CTD_F64; CTD_F32 for the CTD-D C of a mixed-precision handle
+                               (held and updated in float32) */
 } ctd_result;
 
 typedef struct ctd_handle ctd_handle;

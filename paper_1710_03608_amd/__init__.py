@@ -48,7 +48,8 @@ class ResultStruct(ctypes.Structure):
                 ("scale", c_vp), ("accepted", c_vp),
                 ("Q", c_vp), ("ldq", c_i64), ("Linv_t", c_vp), ("ldx", c_i64),
                 ("R", c_vp), ("ldr", c_i64), ("C", c_vp), ("ldc", c_i64), ("n_cols", c_i64),
-                ("col_ids", c_vp), ("fiber_ids", c_vp), ("fiber_resid", c_vp)]
+                ("col_ids", c_vp), ("fiber_ids", c_vp), ("fiber_resid", c_vp),
+                ("C_dtype", c_i32)]
 
 
 class MemoryStruct(ctypes.Structure):
@@ -283,7 +284,8 @@ class Ctd:
         r = self.raw_result()
         if not r.C:
             raise CtdError(8, "no C held")
-        return device_columns(r.C, r.ldc, r.s_tilde, cols)
+        return device_columns(r.C, r.ldc, r.s_tilde, cols,
+                              np.float32 if r.C_dtype == 1 else np.float64)
 
     def result(self, arrays=True, factors=False):
         """Scalars plus host copies of the index arrays (and factors if asked)."""
@@ -309,7 +311,8 @@ class Ctd:
             if r.R:
                 out["R"] = device_matrix(r.R, r.n_rows, k, r.ldr)
             if r.C:
-                out["C"] = device_matrix(r.C, k, r.n_cols, r.ldc, row_major=False)
+                out["C"] = device_matrix(r.C, k, r.n_cols, r.ldc, row_major=False,
+                                         dtype=np.float32 if r.C_dtype == 1 else np.float64)
                 out["col_ids"] = device_to_numpy(r.col_ids, r.n_cols, np.uint64)
         return out
 

@@ -79,13 +79,14 @@ __global__ void k_static_totals(DevScalars* sc) {
 // two nonzeros times two 256-column chunks in flight) over the columns
 // [cspan y, cspan (y + 1)) of y = blockIdx.y; longer ones are listed (by the
 // y = 0 workgroups) for k_spmm_long.
+template <typename TO>
 __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict__ fptr,
                                                       const int32_t* __restrict__ row,
                                                       const double* __restrict__ val,
                                                       DevScalars* sc,
                                                       const double* __restrict__ A, int64_t lda,
                                                       const int32_t* d_ncols,
-                                                      double* __restrict__ out, int64_t ldo,
+                                                      TO* __restrict__ out, int64_t ldo,
                                                       const int64_t* d_col0,
                                                       int32_t* __restrict__ long_list, int fpw,
                                                       int64_t cspan) {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict_
       const int n = fptr[f + 1] - e0;
       const int32_t rr = lane < n ? row[e0 + lane] : 0;
       const double vv = lane < n ? val[e0 + lane] : 0.0;
-      double* o = out + (col0 + f) * ldo;
+      TO* o = out + (col0 + f) * ldo;
       for (int64_t c0 = c_beg; c0 < c_end; c0 += 2 * kCols) {
         const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
         const bool ina = ca < c_end, inb = cb < c_end;
@@ -132,8 +133,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict_
                                   lda, acc0, acc1);
 #pragma unroll
         for (int k = 0; k < VEC; ++k) {
-          if (ca + k < c_end) o[ca + k] = acc0[k];
-          if (cb + k < c_end) o[cb + k] = acc1[k];
+          if (ca + k < c_end) o[ca + k] = (TO)acc0[k];
+          if (cb + k < c_end) o[cb + k] = (TO)acc1[k];
         }
       }
     }
@@ -142,10 +143,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_cols(const int32_t* __restrict_
 
 // Listed long fibers: workgroup (chunk, i) writes one 256-column chunk of
 // fiber i's column.
+template <typename TO>
 __global__ __launch_bounds__(kLongWaves * kWave) void k_spmm_long(
     const int32_t* __restrict__ fptr, const int32_t* __restrict__ row,
     const double* __restrict__ val, const DevScalars* sc, const double* __restrict__ A,
-    int64_t lda, const int32_t* d_ncols, double* __restrict__ out, int64_t ldo,
+    int64_t lda, const int32_t* d_ncols, TO* __restrict__ out, int64_t ldo,
     const int64_t* d_col0, const int32_t* __restrict__ long_list) {
   constexpr int VEC = 4, kCols = VEC * kWave;
   __shared__ double red[kLongWaves * VEC * kWave];
@@ -164,10 +166,10 @@ __global__ __launch_bounds__(kLongWaves * kWave) void k_spmm_long(
     wg_gather_chunk<double, VEC>(row, val, fptr[f], fptr[f + 1], A + (in ? c : 0), in, lda, red,
                                  z);
     if (wv == 0) {
-      double* o = out + (col0 + f) * ldo;
+      TO* o = out + (col0 + f) * ldo;
 #pragma unroll
       for (int k = 0; k < VEC; ++k)
-        if (c + k < ncols) o[c + k] = z[k];
+        if (c + k < ncols) o[c + k] = (TO)z[k];
     }
   }
 }
@@ -339,6 +341,112 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ 
   }
 }
 
+// The same product for a mixed-precision handle, whose C is held in float32:
+// float32 MFMAs (v_mfma_f32_16x16x4f32) with float32 accumulation over C read
+// as 16-byte column vectors, Y rounded to float32 as it is staged.  Lane l
+// holds D[4 (l / 16) + r][l % 16] of a 16 x 16 float32 tile.
+template <int RT>
+__global__ __launch_bounds__(kCrossCols) void k_cross_term32(float* __restrict__ C, int64_t ldc,
+                                                             const double* __restrict__ Yall,
+                                                             int64_t ldy, int64_t ystride,
+                                                             const int64_t* rng_all) {
+  typedef float flt4 __attribute__((ext_vector_type(4)));
+  constexpr int kRows = 16 * RT;
+  __shared__ flt4 Ys[2][kRows][5];   // [buf][row a][g]: Y[a][k0 + 4 g .. + 4], padded
+  const int64_t* rng = rng_all + 5 * blockIdx.y;
+  const double* Y = Yall + blockIdx.y * ystride;
+  const int64_t d = rng[0], na = rng[2], ncols = rng[4];
+  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
+  if (na <= 0 || f0 >= ncols) return;
+  const int t = threadIdx.x, w = t / kWave, l = lane_id(), i = l % 16, g = l / 16;
+  const int64_t nch = (d + 15) / 16;
+  const float* cp[4];
+  bool cin[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int64_t f = f0 + 64 * w + 16 * ct + i;
+    cin[ct] = f < ncols;
+    cp[ct] = C + (cin[ct] ? f : f0) * ldc + 4 * g;
+  }
+  const int yr = t / 4, yg = t % 4;
+  auto mask4 = [&](flt4 v, int64_t k) -> flt4 {
+    v[0] = k < d ? v[0] : 0.0f;
+    v[1] = k + 1 < d ? v[1] : 0.0f;
+    v[2] = k + 2 < d ? v[2] : 0.0f;
+    v[3] = k + 3 < d ? v[3] : 0.0f;
+    return v;
+  };
+  for (int64_t a0 = 0; a0 < na; a0 += kRows) {
+    const int nr = (int)min<int64_t>(kRows, na - a0);
+    const bool yin = yr < nr;
+    const double* yrow = Y + (a0 + (yin ? yr : 0)) * ldy + 4 * yg;
+    flt4 acc[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = flt4{0, 0, 0, 0};
+    flt4 cf[4], yv;
+    auto load = [&](int64_t ch) {
+      const int64_t k = ch * 16 + 4 * g;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const flt4*)(cp[ct] + ch * 16) : flt4{0, 0, 0, 0};
+        cf[ct] = mask4(cf[ct], k);
+      }
+      const int64_t ky = ch * 16 + 4 * yg;
+      const dbl4 y8 = (ch < nch && yin && ky < d) ? *(const dbl4*)(yrow + ch * 16) : dbl4{0, 0, 0, 0};
+      yv = mask4(flt4{(float)y8[0], (float)y8[1], (float)y8[2], (float)y8[3]}, ky);
+    };
+    load(0);
+    int buf = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      if (yr < kRows) Ys[buf][yr][yg] = yv;
+      flt4 cc[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) cc[ct] = cf[ct];
+      __syncthreads();
+      load(ch + 1);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const float a = Ys[buf][rt * 16 + i][g][tt];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct)
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cc[ct][tt], acc[rt][ct], 0, 0, 0);
+        }
+      buf ^= 1;
+    }
+    // lane (i, g) holds D[4 g + r][i] of tile (rt, ct): new row rt * 16 + 4 g + r, column ct * 16 + i
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (!cin[ct]) continue;
+      float* col = C + (f0 + 64 * w + 16 * ct + i) * ldc + d + a0;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = rt * 16 + 4 * g + r;
+          if (a < nr) col[a] = acc[rt][ct][r];
+        }
+    }
+    __syncthreads();   // the next row block reuses Ys
+  }
+}
+
+// dst[f * ldd + k] = (float)src[f * lds + k] for k < rows, f < cols (a
+// column-major float64 block converted to float32).
+__global__ __launch_bounds__(kBlock) void k_cols_to_f32(const double* __restrict__ src,
+                                                        int64_t lds, float* __restrict__ dst,
+                                                        int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * kBlock) {
+    const int64_t f = t / rows, k = t % rows;
+    dst[f * ldd + k] = (float)src[f * lds + k];
+  }
+}
+
 __global__ void k_append_ids(const uint64_t* __restrict__ src, const int32_t* d_count,
                              uint64_t* __restrict__ dst, const int32_t* d_off32,
                              const int64_t* d_off64, uint64_t add) {
@@ -358,9 +466,10 @@ __global__ void k_finish_slice(DevScalars* sc) {
 int grid_for(int64_t work, int per = kBlock);
 
 // C columns R^T X for the fibers of the current input (short and long paths).
+template <typename TO>
 void launch_cols(hipStream_t st, const StaticBufs& b, int64_t nnz_max, DevScalars* sc,
                  const double* A, int64_t lda, const int32_t* d_ncols, int64_t ncols_max,
-                 double* out, int64_t ldo, const int64_t* d_col0) {
+                 TO* out, int64_t ldo, const int64_t* d_col0) {
   hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
   // a small input (a time slice) has few fibers: two per wave, and its
   // columns split over blockIdx.y in spans of 512
@@ -370,13 +479,13 @@ void launch_cols(hipStream_t st, const StaticBufs& b, int64_t nnz_max, DevScalar
   const int ny = (int)std::max<int64_t>(1, (ncols_max + cspan - 1) / cspan);
   const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
   const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
-  hipLaunchKernelGGL(k_spmm_cols, dim3(gm, ny), dim3(kBlock), 0, st, b.fptr, b.row, b.val, sc, A,
-                     lda, d_ncols, out, ldo, d_col0, b.long_list, fpw, cspan);
+  hipLaunchKernelGGL(k_spmm_cols<TO>, dim3(gm, ny), dim3(kBlock), 0, st, b.fptr, b.row, b.val, sc,
+                     A, lda, d_ncols, out, ldo, d_col0, b.long_list, fpw, cspan);
   const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
   const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
   const int nch = (int)std::max<int64_t>(1, (ncols_max + 4 * kWave - 1) / (4 * kWave));
-  hipLaunchKernelGGL(k_spmm_long, dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, b.fptr, b.row,
-                     b.val, sc, A, lda, d_ncols, out, ldo, d_col0, b.long_list);
+  hipLaunchKernelGGL(k_spmm_long<TO>, dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, b.fptr,
+                     b.row, b.val, sc, A, lda, d_ncols, out, ldo, d_col0, b.long_list);
 }
 
 int grid_for(int64_t work, int per) {
@@ -417,7 +526,12 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
   ok = ok && alloc((void**)&N.Q, n_rows * capD * 8);
   if (mixed) ok = ok && alloc((void**)&N.Qf, n_rows * capD * 4);
   ok = ok && alloc((void**)&N.Xt, capD * capD * 8);
-  ok = ok && alloc((void**)&N.C, (size_t)capD * capN * 8);
+  N.C = nullptr;
+  N.Cf = nullptr;
+  if (mixed)
+    ok = ok && alloc((void**)&N.Cf, (size_t)capD * capN * 4);
+  else
+    ok = ok && alloc((void**)&N.C, (size_t)capD * capN * 8);
   ok = ok && alloc((void**)&N.acc_fid, capD * 8);
   ok = ok && alloc((void**)&N.col_fid, capN * 8);
   if (!S.lev) ok = ok && alloc((void**)&N.lev, n_rows * 8);
@@ -426,7 +540,8 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
     (void)hipFree(N.Q);
     if (mixed) (void)hipFree(N.Qf);
     (void)hipFree(N.Xt);
-    (void)hipFree(N.C);
+    if (N.C) (void)hipFree(N.C);
+    if (N.Cf) (void)hipFree(N.Cf);
     (void)hipFree(N.acc_fid);
     (void)hipFree(N.col_fid);
     if (!S.lev) (void)hipFree(N.lev);
@@ -443,8 +558,11 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
                                     hipMemcpyDeviceToDevice, h->stream));
     HIP_CHECK(h, hipMemcpy2DAsync(N.Xt, capD * 8, S.Xt, S.capD * 8, dr * 8, dr,
                                   hipMemcpyDeviceToDevice, h->stream));
-    if (nc > 0)
+    if (nc > 0 && !mixed)
       HIP_CHECK(h, hipMemcpy2DAsync(N.C, capD * 8, S.C, S.capD * 8, dr * 8, nc,
+                                    hipMemcpyDeviceToDevice, h->stream));
+    if (nc > 0 && mixed)
+      HIP_CHECK(h, hipMemcpy2DAsync(N.Cf, capD * 4, S.Cf, S.capD * 4, dr * 4, nc,
                                     hipMemcpyDeviceToDevice, h->stream));
     HIP_CHECK(h, hipMemcpyAsync(N.acc_fid, S.acc_fid, dr * 8, hipMemcpyDeviceToDevice, h->stream));
     if (nc > 0)
@@ -456,7 +574,8 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
     (void)hipFree(S.Q);
     if (S.Qf) (void)hipFree(S.Qf);
     (void)hipFree(S.Xt);
-    (void)hipFree(S.C);
+    if (S.C) (void)hipFree(S.C);
+    if (S.Cf) (void)hipFree(S.Cf);
     (void)hipFree(S.acc_fid);
     (void)hipFree(S.col_fid);
   }
@@ -490,7 +609,7 @@ void launch_static_totals(hipStream_t st, DevScalars* sc) {
 void launch_core_static(hipStream_t st, StaticBufs& b, int64_t n_rows, int64_t nnz_max,
                         DevScalars* sc) {
   (void)n_rows;
-  launch_cols(st, b, nnz_max, sc, b.Rs, b.ld, &sc->s_tilde, b.ld, b.C, b.ld, nullptr);
+  launch_cols<double>(st, b, nnz_max, sc, b.Rs, b.ld, &sc->s_tilde, b.ld, b.C, b.ld, nullptr);
 }
 
 ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X) {
@@ -529,8 +648,12 @@ ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X) {
                                   hipMemcpyDeviceToDevice, h->stream));
   HIP_CHECK(h, hipMemcpy2DAsync(S.Xt, S.capD * 8, b.M, b.ld * 8, st * 8, st,
                                 hipMemcpyDeviceToDevice, h->stream));
-  HIP_CHECK(h, hipMemcpy2DAsync(S.C, S.capD * 8, b.C, b.ld * 8, st * 8, nf,
-                                hipMemcpyDeviceToDevice, h->stream));
+  if (mixed)
+    hipLaunchKernelGGL(k_cols_to_f32, dim3(grid_for(st * nf)), dim3(kBlock), 0, h->stream, b.C,
+                       b.ld, S.Cf, S.capD, st, nf);
+  else
+    HIP_CHECK(h, hipMemcpy2DAsync(S.C, S.capD * 8, b.C, b.ld * 8, st * 8, nf,
+                                  hipMemcpyDeviceToDevice, h->stream));
   HIP_CHECK(h, hipMemcpyAsync(S.lev, b.lev, n_rows * 8, hipMemcpyDeviceToDevice, h->stream));
   HIP_CHECK(h, hipMemcpyAsync(S.acc_fid, b.acc_fid, st * 8, hipMemcpyDeviceToDevice, h->stream));
   HIP_CHECK(h, hipMemcpyAsync(S.col_fid, b.fid, nf * 8, hipMemcpyDeviceToDevice, h->stream));
@@ -553,6 +676,7 @@ void dyn_free(ctd_handle* h) {
   if (S.Qf) (void)hipFree(S.Qf);
   if (S.Xt) (void)hipFree(S.Xt);
   if (S.C) (void)hipFree(S.C);
+  if (S.Cf) (void)hipFree(S.Cf);
   if (S.lev) (void)hipFree(S.lev);
   if (S.acc_fid) (void)hipFree(S.acc_fid);
   if (S.col_fid) (void)hipFree(S.col_fid);
@@ -560,6 +684,9 @@ void dyn_free(ctd_handle* h) {
   S = DynState{};
   h->dyn_ready = false;
 }
+
+// Whether the CTD-D C is held in float32 (mixed-precision handle).
+static bool mixed_c(const DynState& S) { return S.Cf != nullptr; }
 
 void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out) {
   const StaticBufs& b = h->sb;
@@ -607,7 +734,8 @@ void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out) {
     out->ldx = S.capD;
     out->R = S.Rs;
     out->ldr = S.capD;
-    out->C = S.C;
+    out->C = mixed_c(S) ? (const void*)S.Cf : (const void*)S.C;
+    out->C_dtype = mixed_c(S) ? CTD_F32 : CTD_F64;
     out->ldc = S.capD;
     out->n_cols = sc.n_cols_total;
     out->col_ids = S.col_fid;
@@ -621,6 +749,7 @@ void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out) {
     out->R = b.Rs;
     out->ldr = b.ld;
     out->C = h->opt.want_C ? b.C : nullptr;
+    out->C_dtype = CTD_F64;
     out->ldc = b.ld;
     out->n_cols = sc.n_f;
     out->col_ids = b.fid;
@@ -759,8 +888,12 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       launch_basis(st, &ba, &sc, 1, h->bdev);
       mark(h, MARK_BASIS);
       // the slice's own columns R^(t+1)T dX (rows held after its filter)
-      launch_cols(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total, d_next, S.C, S.capD,
-                  &sc->n_cols_total);
+      if (mixed)
+        launch_cols<float>(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total, d_next, S.Cf, S.capD,
+                           &sc->n_cols_total);
+      else
+        launch_cols<double>(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total, d_next, S.C,
+                            S.capD, &sc->n_cols_total);
       hipLaunchKernelGGL(k_append_ids, dim3(grid_for(nnz)), dim3(kBlock), 0, st, b.fid, &sc->n_f,
                          S.col_fid, nullptr, &sc->n_cols_total, t_off);
       // slice residual against the grown basis
@@ -789,7 +922,14 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
     hipLaunchKernelGGL(k_cross_setup, dim3(1), dim3(CTD_MAX_BATCH), 0, st, info, B, sc, rng);
     hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave), B), dim3(kBlock), 0, st, S.Xt,
                        S.capD, Wacc, S.capD, Y, S.capD, ystride, rng);
-    if (tiles > 0) {
+    if (tiles > 0 && S.Cf) {
+      if (kept_max <= 16)
+        hipLaunchKernelGGL((k_cross_term32<1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
+                           S.capD, Y, S.capD, ystride, rng);
+      else
+        hipLaunchKernelGGL((k_cross_term32<4>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
+                           S.capD, Y, S.capD, ystride, rng);
+    } else if (tiles > 0) {
       if (kept_max <= 16)
         hipLaunchKernelGGL((k_cross_term<1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
                            S.capD, Y, S.capD, ystride, rng);

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_col_norms(const double* __restrict__
 
 // Nonzero entries of an outer x inner strided block (element (o, i) at
 // p[o * ld + i]), added into *count.
-__global__ __launch_bounds__(kBlock) void k_count_nz(const double* __restrict__ p, int64_t outer,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_count_nz(const T* __restrict__ p, int64_t outer,
                                                      int64_t inner, int64_t ld,
                                                      unsigned long long* count) {
   __shared__ unsigned long long part[kBlock / kWave];
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_count_nz(const double* __restrict__ 
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * kBlock) {
     const int64_t o = t / inner, i = t % inner;
-    c += p[o * ld + i] != 0.0 ? 1ull : 0ull;
+    c += p[o * ld + i] != T(0) ? 1ull : 0ull;
   }
   for (int off = kWave / 2; off > 0; off /= 2) c += __shfl_down(c, off, kWave);
   if (lane_id() == 0) part[threadIdx.x / kWave] = c;
@@ -175,10 +176,14 @@ extern "C" ctd_status ctd_memory_usage(ctd_handle* h, ctd_memory* out) {
   RO_HIP(h, hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)));
   hipError_t e = hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), h->stream);
   if (e == hipSuccess && k > 0) {
-    hipLaunchKernelGGL(k_count_nz, dim3(1024), dim3(kBlock), 0, h->stream, res.R, n_rows, k,
-                       res.ldr, d_cnt);
-    hipLaunchKernelGGL(k_count_nz, dim3(1024), dim3(kBlock), 0, h->stream, res.C, res.n_cols, k,
-                       res.ldc, d_cnt + 1);
+    hipLaunchKernelGGL(k_count_nz<double>, dim3(1024), dim3(kBlock), 0, h->stream, res.R, n_rows,
+                       k, res.ldr, d_cnt);
+    if (res.C_dtype == CTD_F32)
+      hipLaunchKernelGGL(k_count_nz<float>, dim3(1024), dim3(kBlock), 0, h->stream,
+                         (const float*)res.C, res.n_cols, k, res.ldc, d_cnt + 1);
+    else
+      hipLaunchKernelGGL(k_count_nz<double>, dim3(1024), dim3(kBlock), 0, h->stream,
+                         (const double*)res.C, res.n_cols, k, res.ldc, d_cnt + 1);
     e = hipGetLastError();
   }
   unsigned long long cnt[2] = {0, 0};

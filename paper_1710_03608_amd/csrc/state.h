@@ -77,7 +77,8 @@ struct DynState {
   float* Qf = nullptr;     // mixed precision copy of Q
   double* Xt = nullptr;    // capD x capD row-major upper M with Q = R M
   double* lev = nullptr;   // n_rows: ||Q_i||^2
-  double* C = nullptr;     // capD x capN column-major
+  double* C = nullptr;     // capD x capN column-major (float64 handles)
+  float* Cf = nullptr;     // the same in float32 (mixed handles; C stays null)
   uint64_t* acc_fid = nullptr;  // capD kept fiber ids
   uint64_t* col_fid = nullptr;  // capN fiber ids of C's columns
   void* ws = nullptr;      // per-slice workspace

@@ -194,3 +194,31 @@ def test_four_way_stream_matches_oracle(lib):
             assert abs(r["rel_err"] - rel) <= 1e-6 * rel + 1e-12, (r["rel_err"], rel)
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("B", [1, 4])
+def test_mixed_core_held_in_float32(lib, B):
+    """A mixed-precision handle holds the CTD-D C in float32 (new columns and the
+    cross term on float32 MFMAs): the same kept fibers as float64, and C within
+    float32 rounding amplified by the conditioning of R."""
+    st = _stream(5, dims=(60, 50, 12), n_slices=8)
+    _, ref = _run(lib, st, 50, 8, 5)
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(precision="mixed", want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, 50, 5)
+        slices = [lib.to_device(sl, "cuda") for sl in st.slices]
+        for i in range(0, len(slices), B):
+            if B == 1:
+                h.update(*slices[i], 8)
+            else:
+                h.update_batched(slices[i:i + B], 8)
+        final = h.result(factors=True)
+    finally:
+        h.close()
+    assert final["C"].dtype == np.float32
+    assert np.array_equal(final["accepted"], ref["accepted"])
+    assert np.array_equal(final["col_ids"], ref["col_ids"])
+    cond = np.linalg.cond(ref["R"])
+    err = np.abs(final["C"].astype(np.float64) - ref["C"]).max() / np.abs(ref["C"]).max()
+    assert err <= max(1e-6, 6e-8 * cond ** 2), (err, cond)
