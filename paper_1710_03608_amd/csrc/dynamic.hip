@@ -342,72 +342,79 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ 
 }
 
 // The same product for a mixed-precision handle, whose C is held in float32:
-// float32 MFMAs (v_mfma_f32_16x16x4f32) with float32 accumulation over C read
-// as 16-byte column vectors, Y rounded to float32 as it is staged.  Lane l
-// holds D[4 (l / 16) + r][l % 16] of a 16 x 16 float32 tile.
+// float32 MFMAs (v_mfma_f32_16x16x4f32) with float32 accumulation, Y rounded to
+// float32 as it is staged.  The reduction runs in chunks of 32 rows so that a
+// lane still reads 32 bytes of its column (8 consecutive rows, k0 + 8 g ..),
+// and MFMA t (t < 8) takes element t of them.  Lane l holds D[4 (l / 16) +
+// r][l % 16] of a 16 x 16 float32 tile.
 template <int RT>
 __global__ __launch_bounds__(kCrossCols) void k_cross_term32(float* __restrict__ C, int64_t ldc,
                                                              const double* __restrict__ Yall,
                                                              int64_t ldy, int64_t ystride,
                                                              const int64_t* rng_all) {
   typedef float flt4 __attribute__((ext_vector_type(4)));
+  typedef float flt8 __attribute__((ext_vector_type(8)));
   constexpr int kRows = 16 * RT;
-  __shared__ flt4 Ys[2][kRows][5];   // [buf][row a][g]: Y[a][k0 + 4 g .. + 4], padded
+  __shared__ flt8 Ys[2][kRows][5];   // [buf][row a][g]: Y[a][k0 + 8 g .. + 8], padded
   const int64_t* rng = rng_all + 5 * blockIdx.y;
   const double* Y = Yall + blockIdx.y * ystride;
   const int64_t d = rng[0], na = rng[2], ncols = rng[4];
   const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
   if (na <= 0 || f0 >= ncols) return;
   const int t = threadIdx.x, w = t / kWave, l = lane_id(), i = l % 16, g = l / 16;
-  const int64_t nch = (d + 15) / 16;
+  const int64_t nch = (d + 31) / 32;
   const float* cp[4];
   bool cin[4];
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) {
     const int64_t f = f0 + 64 * w + 16 * ct + i;
     cin[ct] = f < ncols;
-    cp[ct] = C + (cin[ct] ? f : f0) * ldc + 4 * g;
+    cp[ct] = C + (cin[ct] ? f : f0) * ldc + 8 * g;
   }
   const int yr = t / 4, yg = t % 4;
-  auto mask4 = [&](flt4 v, int64_t k) -> flt4 {
-    v[0] = k < d ? v[0] : 0.0f;
-    v[1] = k + 1 < d ? v[1] : 0.0f;
-    v[2] = k + 2 < d ? v[2] : 0.0f;
-    v[3] = k + 3 < d ? v[3] : 0.0f;
+  auto mask8 = [&](flt8 v, int64_t k) -> flt8 {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = k + e < d ? v[e] : 0.0f;
     return v;
   };
   for (int64_t a0 = 0; a0 < na; a0 += kRows) {
     const int nr = (int)min<int64_t>(kRows, na - a0);
     const bool yin = yr < nr;
-    const double* yrow = Y + (a0 + (yin ? yr : 0)) * ldy + 4 * yg;
+    const double* yrow = Y + (a0 + (yin ? yr : 0)) * ldy + 8 * yg;
     flt4 acc[RT][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = flt4{0, 0, 0, 0};
-    flt4 cf[4], yv;
+    flt8 cf[4], yv;
     auto load = [&](int64_t ch) {
-      const int64_t k = ch * 16 + 4 * g;
+      const int64_t k = ch * 32 + 8 * g;
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
-        cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const flt4*)(cp[ct] + ch * 16) : flt4{0, 0, 0, 0};
-        cf[ct] = mask4(cf[ct], k);
+        cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const flt8*)(cp[ct] + ch * 32)
+                                                 : flt8{0, 0, 0, 0, 0, 0, 0, 0};
+        cf[ct] = mask8(cf[ct], k);
       }
-      const int64_t ky = ch * 16 + 4 * yg;
-      const dbl4 y8 = (ch < nch && yin && ky < d) ? *(const dbl4*)(yrow + ch * 16) : dbl4{0, 0, 0, 0};
-      yv = mask4(flt4{(float)y8[0], (float)y8[1], (float)y8[2], (float)y8[3]}, ky);
+      const int64_t ky = ch * 32 + 8 * yg;
+      dbl4 ya = {0, 0, 0, 0}, yb = {0, 0, 0, 0};
+      if (ch < nch && yin && ky < d) {
+        ya = *(const dbl4*)(yrow + ch * 32);
+        yb = *(const dbl4*)(yrow + ch * 32 + 4);
+      }
+      yv = mask8(flt8{(float)ya[0], (float)ya[1], (float)ya[2], (float)ya[3],
+                      (float)yb[0], (float)yb[1], (float)yb[2], (float)yb[3]}, ky);
     };
     load(0);
     int buf = 0;
     for (int64_t ch = 0; ch < nch; ++ch) {
       if (yr < kRows) Ys[buf][yr][yg] = yv;
-      flt4 cc[4];
+      flt8 cc[4];
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) cc[ct] = cf[ct];
       __syncthreads();
       load(ch + 1);
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
+      for (int tt = 0; tt < 8; ++tt)
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
           const float a = Ys[buf][rt * 16 + i][g][tt];
