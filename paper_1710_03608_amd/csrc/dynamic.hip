@@ -254,7 +254,8 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 // 16 RT new rows.
 constexpr int kCrossCols = 256;
 template <int RT>
-__global__ __launch_bounds__(kCrossCols) void k_cross_term(double* __restrict__ C, int64_t ldc,
+__global__ __launch_bounds__(kCrossCols) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 3 : 1)))
+void k_cross_term(double* __restrict__ C, int64_t ldc,
                                                            const double* __restrict__ Yall,
                                                            int64_t ldy, int64_t ystride,
                                                            const int64_t* rng_all) {
