@@ -140,7 +140,14 @@ typedef struct {
 typedef struct ctd_handle ctd_handle;
 
 /* Create a handle bound to a HIP stream (NULL = default stream).  Options may
- * be NULL (float64, eps 1e-6, no C).  Allocates device memory lazily. */
+ * be NULL (float64, eps 1e-6, no C).  Allocates device memory lazily.
+ *
+ * Where kernels have variants that compute identical values and differ only
+ * in how work is spread (fibers per wave of the projection and of C's
+ * columns), a per-process autotuner times every variant on the first call of
+ * an input-size bucket and keeps the fastest; results never depend on the
+ * choice.  If the environment variable CTD_TUNE_CACHE names a file, choices
+ * are read from it at first use and appended to it when made. */
 ctd_status ctd_create(ctd_handle** out, const ctd_options* opt, void* hip_stream);
 
 /* CTD-S, Algorithm 1 (Section 3.1) on tensor X for mode `mode` with s draws

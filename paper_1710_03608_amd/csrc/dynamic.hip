@@ -478,17 +478,37 @@ template <typename TO>
 void launch_cols(hipStream_t st, const StaticBufs& b, int64_t nnz_max, DevScalars* sc,
                  const double* A, int64_t lda, const int32_t* d_ncols, int64_t ncols_max,
                  TO* out, int64_t ldo, const int64_t* d_col0) {
-  hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
-  // a small input (a time slice) has few fibers: two per wave, and its
-  // columns split over blockIdx.y in spans of 512
-  const bool small = nnz_max <= (int64_t(1) << 18);
-  const int fpw = small ? 2 : kWave;
-  const int64_t cspan = small ? 2 * 4 * kWave : std::max<int64_t>(ncols_max, 1);
-  const int ny = (int)std::max<int64_t>(1, (ncols_max + cspan - 1) / cspan);
-  const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
-  const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
-  hipLaunchKernelGGL(k_spmm_cols<TO>, dim3(gm, ny), dim3(kBlock), 0, st, b.fptr, b.row, b.val, sc,
-                     A, lda, d_ncols, out, ldo, d_col0, b.long_list, fpw, cspan);
+  // fibers per wave and column span: a small input (a time slice) has few
+  // fibers, which must still spread over many waves (two per wave, columns
+  // split over blockIdx.y in spans of 512); a large one takes 64 per wave
+  // over all columns.  The autotuner picks among the candidates per
+  // input-size bucket (all write the same values).
+  static const int kFpw[] = {2, 8, kWave};
+  constexpr int kNCand = 3;
+  const int bucket = tune_bucket(nnz_max), prec = sizeof(TO) == 4 ? 1 : 0;
+  int choice = tune_get(TUNE_COLS_FPW, prec, bucket, kNCand);
+  std::vector<hipEvent_t> tev;
+  const bool measure = choice < 0 && tune_begin(TUNE_COLS_FPW, prec, bucket, kNCand, &tev);
+  if (choice < 0) choice = nnz_max <= (int64_t(1) << 18) ? 0 : 2;
+  auto cols = [&](int c) {
+    const int fpw = kFpw[c];
+    const int64_t cspan = fpw < kWave ? 2 * 4 * kWave : std::max<int64_t>(ncols_max, 1);
+    const int ny = (int)std::max<int64_t>(1, (ncols_max + cspan - 1) / cspan);
+    const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
+    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
+    hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
+    hipLaunchKernelGGL(k_spmm_cols<TO>, dim3(gm, ny), dim3(kBlock), 0, st, b.fptr, b.row, b.val, sc,
+                       A, lda, d_ncols, out, ldo, d_col0, b.long_list, fpw, cspan);
+  };
+  if (measure) {
+    for (int c = 0; c < kNCand; ++c) {
+      (void)hipEventRecord(tev[2 * c], st);
+      cols(c);
+      (void)hipEventRecord(tev[2 * c + 1], st);
+    }
+  } else {
+    cols(choice);
+  }
   const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
   const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
   const int nch = (int)std::max<int64_t>(1, (ncols_max + 4 * kWave - 1) / (4 * kWave));

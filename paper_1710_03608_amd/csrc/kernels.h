@@ -5,9 +5,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.h"
 
 namespace ctd {
+
+// ---- tune.hip --------------------------------------------------------------
+// Per-process choice among bit-identical kernel variants, by shape bucket
+// (tune_bucket(n) = ceil(log2 n)).  tune_get returns the chosen variant or -1
+// (undecided; a finished measurement is resolved here).  tune_begin returns
+// true, with 2 events per candidate, when the caller should time every
+// candidate now (event 2c before candidate c, 2c + 1 after it).
+enum { TUNE_PROJ_FPW = 0, TUNE_COLS_FPW = 1 };
+int tune_bucket(int64_t n);
+int tune_get(int knob, int prec, int bucket, int ncand);
+bool tune_begin(int knob, int prec, int bucket, int ncand, std::vector<hipEvent_t>* evs);
 
 // ---- sort.hip --------------------------------------------------------------
 // Stable LSD radix sort of (key, payload) pairs on the low `nbits` bits of the

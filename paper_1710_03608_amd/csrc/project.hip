@@ -189,25 +189,47 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_final(const double* __rest
 
 void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,
                     hipEvent_t ev0, hipEvent_t ev1) {
-  hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
-  // a small input (a time slice) has few fibers: two per wave
-  const int fpw = nnz_max <= (int64_t(1) << 18) ? 2 : kWave;
-  const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
-  const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
+  // fibers per wave: few for a small input (a time slice has a few thousand
+  // fibers, which must still spread over many waves), 64 for a large one;
+  // the autotuner picks among the candidates per input-size bucket
+  static const int kFpw[] = {2, 8, kWave};
+  constexpr int kNFpw = 3;
+  const int prec = a.mixed ? 1 : 0, bucket = tune_bucket(nnz_max);
+  int choice = tune_get(TUNE_PROJ_FPW, prec, bucket, kNFpw);
+  std::vector<hipEvent_t> tev;
+  const bool measure = choice < 0 && tune_begin(TUNE_PROJ_FPW, prec, bucket, kNFpw, &tev);
+  if (choice < 0) choice = nnz_max <= (int64_t(1) << 18) ? 0 : 2;
+  auto multi = [&](int fpw) {
+    hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
+    const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
+    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
+    if (a.mixed)
+      hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(gm), dim3(kBlock), 0, st, a, sc, fpw);
+    else
+      hipLaunchKernelGGL((k_proj_multi<double, 4>), dim3(gm), dim3(kBlock), 0, st, a, sc, fpw);
+  };
   const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
   const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
   const int cols = a.mixed ? 8 * kWave : 4 * kWave;
   const int nch = (int)std::max<int64_t>(1, div_up(a.ncols_max, cols));
   if (ev0) (void)hipEventRecord(ev0, st);
-  if (a.mixed) {
-    hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(gm), dim3(kBlock), 0, st, a, sc, fpw);
+  if (measure) {
+    // every candidate once, timed; the last run's residuals and long-fiber
+    // list are the ones used (all runs write the same values)
+    for (int c = 0; c < kNFpw; ++c) {
+      (void)hipEventRecord(tev[2 * c], st);
+      multi(kFpw[c]);
+      (void)hipEventRecord(tev[2 * c + 1], st);
+    }
+  } else {
+    multi(kFpw[choice]);
+  }
+  if (a.mixed)
     hipLaunchKernelGGL((k_proj_long<float, 8>), dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, a,
                        sc);
-  } else {
-    hipLaunchKernelGGL((k_proj_multi<double, 4>), dim3(gm), dim3(kBlock), 0, st, a, sc, fpw);
+  else
     hipLaunchKernelGGL((k_proj_long<double, 4>), dim3(nch, gy), dim3(kLongWaves * kWave), 0, st, a,
                        sc);
-  }
   hipLaunchKernelGGL(k_proj_long_fin, dim3(std::max(1, std::min(1024, (int)div_up(max_long * kWave, kBlock)))),
                      dim3(kBlock), 0, st, a, sc, cols);
   if (ev1) (void)hipEventRecord(ev1, st);

@@ -1,0 +1,113 @@
+// Autotuner for kernel variants whose results are bit-identical: they differ
+// only in how the work is spread over waves (fibers per wave, column spans),
+// so choosing among them changes no value.  The first call of a shape bucket
+// runs every candidate once on the real data with HIP events around each run
+// (the last run's output is the one kept: all runs write the same values);
+// a later call finds the events complete and keeps the fastest candidate for
+// the bucket.  Choices are per process; with CTD_TUNE_CACHE naming a file
+// they are read from it at first use and appended to it when made.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+namespace ctd {
+namespace {
+
+struct Entry {
+  int choice = -1;
+  std::vector<hipEvent_t> ev;   // 2 per candidate while a measurement is pending
+};
+
+std::mutex g_mu;
+std::map<uint64_t, Entry> g_table;
+bool g_loaded = false;
+
+uint64_t key_of(int knob, int prec, int bucket) {
+  return ((uint64_t)(uint32_t)knob << 40) | ((uint64_t)(uint32_t)prec << 32) | (uint32_t)bucket;
+}
+
+void load_file_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  const char* path = getenv("CTD_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  int knob, prec, bucket, choice;
+  while (fscanf(f, "%d %d %d %d", &knob, &prec, &bucket, &choice) == 4)
+    if (choice >= 0) g_table[key_of(knob, prec, bucket)].choice = choice;
+  fclose(f);
+}
+
+void append_file(int knob, int prec, int bucket, int choice) {
+  const char* path = getenv("CTD_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%d %d %d %d\n", knob, prec, bucket, choice);
+  fclose(f);
+}
+
+}  // namespace
+
+int tune_bucket(int64_t n) {
+  return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)n - 1);
+}
+
+int tune_get(int knob, int prec, int bucket, int ncand) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  load_file_locked();
+  auto it = g_table.find(key_of(knob, prec, bucket));
+  if (it == g_table.end()) return -1;
+  Entry& e = it->second;
+  if (e.choice >= 0 && e.choice < ncand) return e.choice;
+  if ((int)e.ev.size() != 2 * ncand) return -1;
+  if (hipEventQuery(e.ev.back()) != hipSuccess) {
+    (void)hipGetLastError();   // not ready yet
+    return -1;
+  }
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int c = 0; c < ncand; ++c) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e.ev[2 * c], e.ev[2 * c + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      ms = 1e30f;
+    }
+    if (c == 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  for (hipEvent_t ev : e.ev) (void)hipEventDestroy(ev);
+  e.ev.clear();
+  e.choice = best;
+  append_file(knob, prec, bucket, best);
+  return best;
+}
+
+bool tune_begin(int knob, int prec, int bucket, int ncand, std::vector<hipEvent_t>* evs) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  load_file_locked();
+  const uint64_t key = key_of(knob, prec, bucket);
+  if (g_table.count(key)) return false;   // decided, or a measurement is in flight
+  std::vector<hipEvent_t> ev(2 * ncand, nullptr);
+  for (hipEvent_t& e : ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+      return false;
+    }
+  }
+  g_table[key].ev = ev;
+  *evs = ev;
+  return true;
+}
+
+}  // namespace ctd
