@@ -786,10 +786,12 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const BasisDev* __restric
 
 // Kept residuals times the first-pass factor: Q[r][k + a] = sum_{a' <= a}
 // Ybuf[r][pos[a']] T[a'][a]; R[r][k + a] = P[r][b0 + pos[a]].  A workgroup
-// walks 64-row tiles with a stride of the grid (four threads per row, 16
-// outputs each) and accumulates the Gram of its new rows of Q with f64 MFMAs
-// (wave w: Gram rows 16 w .. + 16); the sum over its tiles goes to
-// part[blockIdx.x] for the orthogonality check of the block.
+// walks 64-row tiles with a stride of the grid.  Per tile, wave w forms rows
+// 16 w .. + 16 of the new columns with f64 MFMAs (A gathered from the Y tile
+// through pos, B = T; T is zero past the kept count), and after a barrier the
+// Gram of the tile's new rows (wave w: Gram rows 16 w .. + 16) accumulates;
+// the sum over its tiles goes to part[blockIdx.x] for the orthogonality
+// check of the block.
 __global__ __launch_bounds__(kBlock) void k_blk_take(const BasisDev* __restrict__ bd, int64_t b0) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Ybuf = d.Ybuf;
@@ -821,28 +823,36 @@ __global__ __launch_bounds__(kBlock) void k_blk_take(const BasisDev* __restrict_
       Ys[t / kB][t % kB] = rr < n_rows ? Ybuf[rr * kB + t % kB] : 0.0;
     }
     __syncthreads();
-    const int64_t r = r0 + rl;
-    double out[16];
+    // new columns of rows 16 w .. + 16: lane (i, g) holds row 16 w + g + 4 x, column 16 ct + i
+    dbl4 qo[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    const int nks = (na + 3) / 4;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int ap = ks * 4 + l / 16;
+      const double av = Ys[w * 16 + l % 16][ps[ap]];   // A[i][a'] = Y[row][pos[a']]
 #pragma unroll
-    for (int u = 0; u < 16; ++u) out[u] = 0.0;
-    for (int ap = 0; ap < na; ++ap) {
-      const double y = Ys[rl][ps[ap]];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) out[u] += y * Ts[ap][a_lo + u];
+      for (int ct = 0; ct < 4; ++ct) qo[ct] = mfma16(av, Ts[ap][ct * 16 + l % 16], qo[ct]);
     }
-    const bool live = r < n_rows;
-    double* q = Q + r * ldq + k;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int a = a_lo + u;
-      if (live && a < na) {
-        q[a] = out[u];
-        if (R) R[r * ldr + k + a] = P[r * ldp + b0 + ps[a]];
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int64_t r = r0 + w * 16 + l / 16 + 4 * x;
+        const int a = ct * 16 + l % 16;
+        if (r < n_rows && a < na) Q[r * ldq + k + a] = qo[ct][x];
+      }
+    if (R) {
+      const int64_t r = r0 + rl;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int a = a_lo + u;
+        if (r < n_rows && a < na) R[r * ldr + k + a] = P[r * ldp + b0 + ps[a]];
       }
     }
     __syncthreads();   // all reads of Ys done
 #pragma unroll
-    for (int u = 0; u < 16; ++u) Ys[rl][a_lo + u] = (live && a_lo + u < na) ? out[u] : 0.0;
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) Ys[w * 16 + l / 16 + 4 * x][ct * 16 + l % 16] = qo[ct][x];
     __syncthreads();
     // acc[i][j] += sum_r Qn[r][i] Qn[r][j] over this tile
 #pragma unroll
