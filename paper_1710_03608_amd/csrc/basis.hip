@@ -53,6 +53,7 @@ struct BasisDev {
   double* Tacc;
   double* g;        // 64 squared candidate norms
   double* Ybuf;     // n_rows x 64 block residuals
+  double* Zp;       // newm_splits(cap) x cap x 64 partials of Z = M W_A^T
   int32_t* pos;     // 64 kept positions
   int32_t nsplit_w, nsplit_dd, ntake;
   int32_t pad;
@@ -395,8 +396,13 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
   for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * kBlock) {
     const int64_t j = t / k, c = t % k;
+    // all partial loads in flight before the sum, which runs in order of p
+    double v[kSplitW];
+#pragma unroll
+    for (int p = 0; p < kSplitW; ++p) v[p] = p < nsplit ? W2p[(int64_t)p * kB * ldw + j * ldw + c] : 0.0;
     double s = 0.0;
-    for (int p = 0; p < nsplit; ++p) s += W2p[(int64_t)p * kB * ldw + j * ldw + c];
+#pragma unroll
+    for (int p = 0; p < kSplitW; ++p) s += v[p];
     W2[j * ldw + c] = s;
     W[j * ldw + c] += s;
   }
@@ -486,11 +492,22 @@ __global__ __launch_bounds__(kBlock) void k_blk_sum_dd(const BasisDev* __restric
   const int t = blockIdx.x * kPer + e;
   double h = 0.0, l = 0.0;
   if (t < kB * kB) {
-    for (int p = q; p < nsplit; p += kSumWays) {
+    // loads first (all in flight), then the compensated sum in order of p
+    constexpr int kIt = kSplitDD / kSumWays;
+    double vh[kIt], vl[kIt];
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {
+      const int p = q + i * kSumWays;
+      vh[i] = p < nsplit ? part_hi[(int64_t)p * kB * kB + t] : 0.0;
+      vl[i] = p < nsplit ? part_lo[(int64_t)p * kB * kB + t] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {
+      if (q + i * kSumWays >= nsplit) break;
       double s2, er;
-      two_sum(h, part_hi[(int64_t)p * kB * kB + t], s2, er);
+      two_sum(h, vh[i], s2, er);
       h = s2;
-      l += er + part_lo[(int64_t)p * kB * kB + t];
+      l += er + vl[i];
     }
   }
   sh[threadIdx.x] = h;
@@ -520,8 +537,17 @@ __global__ __launch_bounds__(kBlock) void k_blk_sum_parts(const BasisDev* __rest
   const int e = threadIdx.x % kPer, q = threadIdx.x / kPer;
   const int t = blockIdx.x * kPer + e;
   double s = 0.0;
-  if (t < kB * kB)
-    for (int p = q; p < nparts; p += kSumWays) s += part[(int64_t)p * kB * kB + t];
+  if (t < kB * kB) {
+    constexpr int kIt = kTakeParts / kSumWays;
+    double v[kIt];
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {
+      const int p = q + i * kSumWays;
+      v[i] = p < nparts ? part[(int64_t)p * kB * kB + t] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) s += v[i];
+  }
   sh[threadIdx.x] = s;
   __syncthreads();
   if (q == 0 && t < kB * kB) {
@@ -908,74 +934,62 @@ __global__ __launch_bounds__(kBlock) void k_blk_apply(const BasisDev* __restrict
     if (a_lo + u < na) q[a_lo + u] = out[u];
 }
 
-// Z[a][c] = sum_{c <= j < k} M[c][j] W[pos[a]][j] for c < k (M upper
-// triangular), split over j: workgroup (ct, js) covers rows 64 ct .. + 64 and
-// j in [256 js, 256 js + 256), writing Zp[js][a][c] (zero when the range is
-// empty); k_blk_zsum adds the splits in a fixed order.
 // New columns of M (Q = R M) for the block's kept fibers:
 //   M[c][k + a] = -sum_{b <= a} Z[c][b] T[b][a],  Z = M W_A^T  (c < k),
 //   M[k + b][k + a] = T[b][a] (b <= a), M[k + b][c] = 0 below the diagonal,
-// W_A the W rows of the kept candidates and T = L1^{-T} (L2^{-T}).  Workgroup
-// x covers rows 32 x .. + 32 of M: Z's tile comes from f64 MFMAs over
-// j >= 32 x (M is upper triangular) with two groups of four waves splitting
-// the j chunks, then the tile times T in LDS.  All workgroups first write the
-// diagonal block and the zero rows.
-__global__ __launch_bounds__(kGemm) void k_blk_newm(const BasisDev* __restrict__ bd) {
+// W_A the W rows of the kept candidates and T = L1^{-T} (L2^{-T}).
+//
+// k_blk_newm_part: Z over the upper triangle of M, split over j: workgroup
+// (x, js) covers rows 32 x .. + 32 and j in [jw js, jw js + jw) from j = 32 x
+// on, with f64 MFMAs (two groups of four waves alternating the 32-wide j
+// chunks), and writes its 32 x 64 partial to Zp[js] (workgroups whose j range
+// lies left of their rows write nothing).  jw is at least 128 and gives at
+// most 16 splits of the block step's bound on k.
+constexpr int kNewmJMin = 128, kNewmSplits = 16;
+inline int64_t newm_jw(int64_t k1) {
+  return std::max<int64_t>(kNewmJMin, div_up(div_up(k1, kNewmSplits), 32) * 32);
+}
+inline int64_t newm_splits(int64_t cap) {
+  return std::min<int64_t>(kNewmSplits, div_up(cap, kNewmJMin));
+}
+__global__ __launch_bounds__(kGemm) void k_blk_newm_part(const BasisDev* __restrict__ bd, int64_t jw) {
   const BasisDev& d = bd[blockIdx.z];
-  double* __restrict__ M = d.a.M;
+  const double* __restrict__ M = d.a.M;
   const double* __restrict__ W = d.W;
   const int32_t* __restrict__ pos = d.pos;
-  const double* __restrict__ T = d.Tacc;
+  double* __restrict__ Zp = d.Zp;
   const int64_t ldm = d.a.ldm, ldw = d.a.cap;
   const DevScalars* sc = d.sc;
   constexpr int kR = 32;
-  // one LDS buffer: the main loop's tiles, then the epilogue's Z (32 x 65)
-  // and T (64 x 65) over the same space
-  constexpr int kAsz = 2 * kR * (kGK + 1), kBsz = 2 * kGK * (kB + 1);
-  static_assert(kR * (kB + 1) + kB * (kB + 1) <= kAsz + kBsz, "epilogue tiles fit");
-  __shared__ double smem[kAsz + kBsz];
+  __shared__ double As[2][kR][kGK + 1];   // M tile [grp][row][j]
+  __shared__ double Bs[2][kGK][kB + 1];   // W_A^T tile [grp][j][a]
   __shared__ int32_t ps[kB];
-  double(*As)[kR][kGK + 1] = (double(*)[kR][kGK + 1])smem;          // M tile [grp][row][j]
-  double(*Bs)[kGK][kB + 1] = (double(*)[kGK][kB + 1])(smem + kAsz); // W_A^T tile [grp][j][a]
   const int64_t k = sc->n_accept_total;
   const int na = sc->blk_na;
   if (na == 0 || sc->status != 0) return;
-  // diagonal block and zero rows (grid-stride over all workgroups)
-  {
-    const int64_t tot = (int64_t)na * (k + na);
-    for (int64_t t = (int64_t)blockIdx.x * kGemm + threadIdx.x; t < tot;
-         t += (int64_t)gridDim.x * kGemm) {
-      const int64_t b = t / (k + na), c = t % (k + na);
-      double v = 0.0;
-      if (c >= k) {
-        const int64_t a = c - k;
-        v = b <= a ? T[b * kB + a] : 0.0;
-      }
-      M[(k + b) * ldm + c] = v;
-    }
-  }
   const int64_t r0 = (int64_t)blockIdx.x * kR;
-  if (r0 >= k) return;
+  const int64_t js = blockIdx.y;
+  const int64_t jlo = max(r0, js * jw), jhi = min(k, (js + 1) * jw);
+  if (r0 >= k || jlo >= jhi) return;
   if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
   __syncthreads();
   const int grp = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
   const int w = t / kWave, l = lane_id();
   const int rb = (w / 2) * 16, cb = (w % 2) * 32;
-  const int64_t jbeg = r0;                       // M[c][j] = 0 for j < c
-  const int64_t nch = (k - jbeg + kGK - 1) / kGK;
+  const int64_t nch = (jhi - jlo + kGK - 1) / kGK;
   const int64_t iters = (nch + 1) / 2;
   double ra[kR * kGK / kBlock], rw[kB * kGK / kBlock];
   auto load = [&](int64_t ch) {
-    const int64_t j0 = jbeg + ch * kGK;
+    const int64_t j0 = jlo + ch * kGK;
 #pragma unroll
     for (int u = 0; u < kR * kGK / kBlock; ++u) {
       const int idx = u * kBlock + t, r = idx / kGK, jj = idx % kGK;
-      ra[u] = (ch < nch && j0 + jj < k && r0 + r < k) ? M[(r0 + r) * ldm + j0 + jj] : 0.0;
+      ra[u] = (ch < nch && j0 + jj < jhi && r0 + r < k) ? M[(r0 + r) * ldm + j0 + jj] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kB * kGK / kBlock; ++u) {
       const int idx = u * kBlock + t, a = idx / kGK, jj = idx % kGK;
-      rw[u] = (ch < nch && j0 + jj < k && a < na) ? W[(int64_t)ps[a] * ldw + j0 + jj] : 0.0;
+      rw[u] = (ch < nch && j0 + jj < jhi && a < na) ? W[(int64_t)ps[a] * ldw + j0 + jj] : 0.0;
     }
   };
   dbl4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
@@ -1003,37 +1017,92 @@ __global__ __launch_bounds__(kGemm) void k_blk_newm(const BasisDev* __restrict__
       acc1 = mfma16(av, b1v, acc1);
     }
   }
-  // Z tile = both groups' sums (32 x 64 in LDS), T in LDS, then out = -Z T
-  double(*Zs)[kB + 1] = (double(*)[kB + 1])smem;                         // 32 x 65
-  double(*Ts)[kB + 1] = (double(*)[kB + 1])(smem + kR * (kB + 1));       // 64 x 65
+  // combine the two groups and write the partial tile
+  double(*red)[kB + 1] = Bs[0];   // 32 x 65 doubles
   __syncthreads();
   if (grp == 1) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      Zs[rb + l / 16 + 4 * r][cb + l % 16] = acc0[r];
-      Zs[rb + l / 16 + 4 * r][cb + 16 + l % 16] = acc1[r];
+      red[rb + l / 16 + 4 * r][cb + l % 16] = acc0[r];
+      red[rb + l / 16 + 4 * r][cb + 16 + l % 16] = acc1[r];
     }
   }
   __syncthreads();
-  if (grp == 0) {
+  if (grp == 1) return;
+  double* zp = Zp + js * ldw * kB;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Zs[rb + l / 16 + 4 * r][cb + l % 16] += acc0[r];
-      Zs[rb + l / 16 + 4 * r][cb + 16 + l % 16] += acc1[r];
+  for (int r = 0; r < 4; ++r) {
+    const int rr = rb + l / 16 + 4 * r;
+    if (r0 + rr >= k) continue;
+    zp[(r0 + rr) * kB + cb + l % 16] = acc0[r] + red[rr][cb + l % 16];
+    zp[(r0 + rr) * kB + cb + 16 + l % 16] = acc1[r] + red[rr][cb + 16 + l % 16];
+  }
+}
+
+// k_blk_newm_fin: the diagonal block and the zero rows (grid-stride over all
+// workgroups), then workgroup x sums the partials of rows 32 x .. + 32 in
+// order of js and multiplies by T on f64 MFMAs.
+__global__ __launch_bounds__(kGemm) void k_blk_newm_fin(const BasisDev* __restrict__ bd, int64_t jw) {
+  const BasisDev& d = bd[blockIdx.z];
+  double* __restrict__ M = d.a.M;
+  const double* __restrict__ Zp = d.Zp;
+  const double* __restrict__ T = d.Tacc;
+  const int64_t ldm = d.a.ldm, ldw = d.a.cap;
+  const DevScalars* sc = d.sc;
+  constexpr int kR = 32;
+  __shared__ double Zs[kR][kB + 1];
+  __shared__ double Ts[kB][kB + 1];
+  const int64_t k = sc->n_accept_total;
+  const int na = sc->blk_na;
+  if (na == 0 || sc->status != 0) return;
+  {
+    const int64_t tot = (int64_t)na * (k + na);
+    for (int64_t t = (int64_t)blockIdx.x * kGemm + threadIdx.x; t < tot;
+         t += (int64_t)gridDim.x * kGemm) {
+      const int64_t b = t / (k + na), c = t % (k + na);
+      double v = 0.0;
+      if (c >= k) {
+        const int64_t a = c - k;
+        v = b <= a ? T[b * kB + a] : 0.0;
+      }
+      M[(k + b) * ldm + c] = v;
     }
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * kR;
+  if (r0 >= k) return;
+  const int64_t js0 = r0 / jw, js1 = (k + jw - 1) / jw;
+  // every partial's load issued before the sums, which run in order of js
+  static_assert(kR * kB % kGemm == 0, "whole tile per pass");
+#pragma unroll
+  for (int u = 0; u < kR * kB / kGemm; ++u) {
+    const int e = u * kGemm + threadIdx.x, r = e / kB, a = e % kB;
+    double zv[kNewmSplits];
+#pragma unroll
+    for (int q = 0; q < kNewmSplits; ++q)
+      zv[q] = (r0 + r < k && js0 + q < js1) ? Zp[(js0 + q) * ldw * kB + (r0 + r) * kB + a] : 0.0;
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNewmSplits; ++q) z += zv[q];
+    Zs[r][a] = z;
   }
   for (int e = threadIdx.x; e < kB * kB; e += kGemm) {
     const int b = e / kB, a = e % kB;
-    Ts[b][a] = (b < na && a < na) ? T[e] : 0.0;
+    Ts[b][a] = (b <= a && a < na) ? T[e] : 0.0;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kR * kB; e += kGemm) {
-    const int r = e / kB, a = e % kB;
-    const int64_t c = r0 + r;
-    if (c >= k || a >= na) continue;
-    double s2 = 0.0;
-    for (int b = 0; b <= a; ++b) s2 += Zs[r][b] * Ts[b][a];
-    M[c * ldm + k + a] = -s2;
+  // -Z T on f64 MFMAs: wave w forms the 16 x 16 tile (w / 4, w % 4)
+  static_assert(kGemm / kWave == (kR / 16) * (kB / 16), "one output tile per wave");
+  const int w = threadIdx.x / kWave, l = lane_id();
+  const int rt = (w / 4) * 16, ct = (w % 4) * 16;
+  dbl4 acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < kB / 4; ++ks)
+    acc = mfma16(Zs[rt + l % 16][ks * 4 + l / 16], Ts[ks * 4 + l / 16][ct + l % 16], acc);
+  const int a = ct + l % 16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t c = r0 + rt + l / 16 + 4 * r;
+    if (c < k && a < na) M[c * ldm + k + a] = -acc[r];
   }
 }
 
@@ -1139,6 +1208,7 @@ size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
          + (size_t)kB * kB * 3                      // G, Tcur, Tacc
          + kB                                       // g
          + (size_t)kB * n_rows                      // Ybuf
+         + (size_t)newm_splits(cap) * cap * kB      // Zp
          + 64;                                      // pos
 }
 
@@ -1173,7 +1243,8 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     d.Tacc = d.Tcur + kB * kB;
     d.g = d.Tacc + kB * kB;
     d.Ybuf = d.g + kB;
-    d.pos = (int32_t*)(d.Ybuf + (size_t)kB * a.n_rows);
+    d.Zp = d.Ybuf + (size_t)kB * a.n_rows;
+    d.pos = (int32_t*)(d.Zp + (size_t)newm_splits(a.cap) * a.cap * kB);
     d.nsplit_w = sp.w;
     d.nsplit_dd = sp.dd;
     d.ntake = sp.take;
@@ -1227,7 +1298,10 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       hipLaunchKernelGGL(k_blk_sum_parts, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd);
       hipLaunchKernelGGL(k_blk_cholinv, dim3(1, 1, nz), dim3(kChol), 0, st, bd);
       hipLaunchKernelGGL(k_blk_apply, dim3(rows4, 1, nz), dim3(kBlock), 0, st, bd);
-      hipLaunchKernelGGL(k_blk_newm, dim3(div_up(k1, 32), 1, nz), dim3(kGemm), 0, st, bd);
+      const int64_t jw = newm_jw(k1);
+      hipLaunchKernelGGL(k_blk_newm_part, dim3(div_up(k1, 32), div_up(k1, jw), nz), dim3(kGemm), 0,
+                         st, bd, jw);
+      hipLaunchKernelGGL(k_blk_newm_fin, dim3(div_up(k1, 32), 1, nz), dim3(kGemm), 0, st, bd, jw);
       hipLaunchKernelGGL(k_blk_finish, dim3(1, 1, nz), dim3(256), 0, st, bd, b0);
     }
     hipLaunchKernelGGL(k_lev, dim3(div_up(rows_all * kWave, kBlock), 1, nz_all), dim3(kBlock), 0, st,
