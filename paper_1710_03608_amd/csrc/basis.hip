@@ -29,7 +29,8 @@ namespace {
 constexpr int kB = 64;        // candidates per block
 constexpr int kTakeParts = 256;   // workgroups of k_blk_take: partial Grams of the new columns
 constexpr int kBlock = 256;
-constexpr int kSplitW = 16;     // row splits of W2 = Q^T Y (at most)
+constexpr int kSplitWMax = 128; // row splits of W2 = Q^T Y (at most)
+constexpr int kW2Grid = 512;    // workgroups aimed at for W2 = Q^T Y (two per CU)
 constexpr int kSplitDD = 256;   // row splits of the double-double Gram (at most)
 
 
@@ -42,7 +43,7 @@ struct BasisDev {
   BasisArgs a;
   DevScalars* sc;
   double* W;        // 64 x cap: Q^T x rows of the block's candidates
-  double* W2p;      // nsplit_w x 64 x cap partial second-pass coefficients
+  double* W2p;      // w2_splits x 64 x 64 T partial second-pass coefficients
   double* W2;       // 64 x cap
   double* part;     // ntake x 64 x 64 partial Grams of the new columns
   double* part_hi;  // nsplit_dd x 64 x 64 partial double-double Grams
@@ -55,7 +56,7 @@ struct BasisDev {
   double* Ybuf;     // n_rows x 64 block residuals
   double* Zp;       // newm_splits(cap) x cap x 64 partials of Z = M W_A^T
   int32_t* pos;     // 64 kept positions
-  int32_t nsplit_w, nsplit_dd, ntake;
+  int32_t nsplit_dd, ntake;
   int32_t pad;
 };
 static_assert(sizeof(BasisDev) % 8 == 0, "BasisDev is copied as 64-bit words");
@@ -302,18 +303,37 @@ __global__ __launch_bounds__(kGemm) void k_blk_form_y(const BasisDev* __restrict
   }
 }
 
+// Row splits of W2 = Q^T Y at a block step whose Q spans T tiles of 64
+// columns: at most kW2Grid workgroups in all (one round of two resident
+// workgroups per CU: a second round for a few more costs more than the
+// larger splits), each split at least 64 rows, at most kSplitWMax splits.
+// A step's own T is the launch's bound capped by the input's column capacity.
+__host__ __device__ inline int w2_splits(int64_t n_rows, int64_t T) {
+  int64_t by_rows = (n_rows + 63) / 64;
+  if (by_rows > kSplitWMax) by_rows = kSplitWMax;
+  int64_t want = kW2Grid / (T > 0 ? T : 1);
+  if (want > by_rows) want = by_rows;
+  return want > 0 ? (int)want : 1;
+}
+__device__ inline int64_t w2_tiles(const BasisDev& d, int64_t t_launch) {
+  const int64_t tc = (d.a.cap + kB - 1) / kB;
+  return t_launch < tc ? t_launch : tc;
+}
+
 // Second projection coefficients W2[j][c] = sum_r Q[r][c] Y[r][j] for c < k,
-// partial over kSplitW row ranges: workgroup (ct, s) covers c in
-// [64 ct, 64 ct + 64); wave w of a group computes c rows 16 w .. + 16 against
-// all 64 j with four f64 MFMA tiles.
+// partial over w2_splits row ranges: workgroup (ct, s) covers c in
+// [64 ct, 64 ct + 64) and writes W2p[s][j][c] (row length 64 T); wave w of a
+// group computes c rows 16 w .. + 16 against all 64 j with four f64 MFMA
+// tiles.
 __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restrict__ bd,
-                                                       int64_t b0) {
+                                                       int64_t b0, int64_t t_launch) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Q = d.a.Q;
   const double* __restrict__ Y = d.Ybuf;
   double* __restrict__ W2p = d.W2p;
-  const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows, ldw = d.a.cap;
-  const int nsplit = d.nsplit_w;
+  const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows;
+  const int64_t T = w2_tiles(d, t_launch), ldp = T * kB;
+  const int nsplit = w2_splits(n_rows, T);
   const DevScalars* sc = d.sc;
   __shared__ double Qs[2][kGK][kB + 1];   // [r][c]
   __shared__ double Ys[2][kGK][kB + 1];   // [r][j]
@@ -368,7 +388,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restric
   }
   __syncthreads();
   if (grp == 1) return;
-  double* p = W2p + (int64_t)blockIdx.y * kB * ldw;
+  double* p = W2p + (int64_t)blockIdx.y * kB * ldp;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -376,35 +396,53 @@ __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restric
       const int cc = w * 16 + l / 16 + 4 * r;
       const int64_t c = c0 + cc;
       const int j = q * 16 + l % 16;
-      if (c < k) p[(int64_t)j * ldw + c] = acc[q][r] + red[cc][j];
+      if (c < k) p[(int64_t)j * ldp + c] = acc[q][r] + red[cc][j];
     }
 }
 
-// W2[j][c] = sum_s W2p[s][j][c] (fixed order); W[j][c] += W2[j][c].
+// W2[j][c] = sum_s W2p[s][j][c] (fixed order); W[j][c] += W2[j][c].  A
+// workgroup takes 32 consecutive entries per pass, each summed by kW2Ways
+// threads over every kW2Ways-th partial (all loads in flight together), and
+// the ways are added in order.
+constexpr int kW2Ways = 8, kW2Per = kBlock / kW2Ways;
 __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restrict__ bd,
-                                                       int64_t b0) {
+                                                       int64_t b0, int64_t t_launch) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ W2p = d.W2p;
   double* __restrict__ W2 = d.W2;
   double* __restrict__ W = d.W;
   const int64_t ldw = d.a.cap;
-  const int nsplit = d.nsplit_w;
+  const int64_t T = w2_tiles(d, t_launch), ldp = T * kB;
+  const int nsplit = w2_splits(d.a.n_rows, T);
   const DevScalars* sc = d.sc;
   const int64_t nb = blk_work(sc, b0, d.a.n_rows);
   const int64_t k = sc->n_accept_total;
   const int64_t total = nb * k;
-  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * kBlock) {
+  __shared__ double sh[kBlock];
+  const int e = threadIdx.x % kW2Per, q = threadIdx.x / kW2Per;
+  constexpr int kIt = kSplitWMax / kW2Ways;
+  for (int64_t t0 = (int64_t)blockIdx.x * kW2Per; t0 < total; t0 += (int64_t)gridDim.x * kW2Per) {
+    const int64_t t = t0 + e;
     const int64_t j = t / k, c = t % k;
-    // all partial loads in flight before the sum, which runs in order of p
-    double v[kSplitW];
-#pragma unroll
-    for (int p = 0; p < kSplitW; ++p) v[p] = p < nsplit ? W2p[(int64_t)p * kB * ldw + j * ldw + c] : 0.0;
     double s = 0.0;
+    if (t < total) {
+      double v[kIt];
 #pragma unroll
-    for (int p = 0; p < kSplitW; ++p) s += v[p];
-    W2[j * ldw + c] = s;
-    W[j * ldw + c] += s;
+      for (int u = 0; u < kIt; ++u) {
+        const int p = q + u * kW2Ways;
+        v[u] = p < nsplit ? W2p[((int64_t)p * kB + j) * ldp + c] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kIt; ++u) s += v[u];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (q == 0 && t < total) {
+      for (int w = 1; w < kW2Ways; ++w) s += sh[w * kW2Per + e];
+      W2[j * ldw + c] = s;
+      W[j * ldw + c] += s;
+    }
+    __syncthreads();
   }
 }
 
@@ -414,8 +452,11 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
 // need the block Gram to about u^2: rounding it to float64 alone moves the
 // Schur complement of an exactly dependent candidate to ~u * cond^2 ||x||^2,
 // which can reach eps^2 ||x||^2.
-__global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const BasisDev* __restrict__ bd,
-                                                        int64_t b0) {
+// kGramGroups groups of kBlock threads take every kGramGroups-th row of each
+// 64-row tile (four waves per SIMD); their sums are added in group order.
+constexpr int kGramGroups = 4;
+__global__ __launch_bounds__(kBlock * kGramGroups) void k_blk_gram_dd(const BasisDev* __restrict__ bd,
+                                                                      int64_t b0) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Y = d.Ybuf;
   double* __restrict__ part_hi = d.part_hi;
@@ -429,17 +470,26 @@ __global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const BasisDev* __restri
   const int64_t chunk = (n_rows + nsplit - 1) / nsplit;
   const int64_t k0 = blockIdx.x * chunk;
   const int64_t k1 = min(n_rows, k0 + chunk);
-  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  const int grp = threadIdx.x / kBlock, tl = threadIdx.x % kBlock;
+  const int ty = tl / 16, tx = tl % 16;
   double hi[4][4] = {}, lo[4][4] = {};
   for (int64_t kk0 = k0; kk0 < k1; kk0 += kB) {
     __syncthreads();
-    for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
-      const int kk = t / kB, i = t % kB;
-      Ys[kk][i] = (kk0 + kk < k1 && i < width) ? Y[(kk0 + kk) * kB + i] : 0.0;
+    constexpr int kLd = kB * kB / (kBlock * kGramGroups);
+    double v[kLd];
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int t = u * kBlock * kGramGroups + threadIdx.x, kk = t / kB, i = t % kB;
+      v[u] = (kk0 + kk < k1 && i < width) ? Y[(kk0 + kk) * kB + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int t = u * kBlock * kGramGroups + threadIdx.x;
+      Ys[t / kB][t % kB] = v[u];
     }
     __syncthreads();
     const int kn = (int)min((int64_t)kB, k1 - kk0);
-    for (int kk = 0; kk < kn; ++kk) {
+    for (int kk = grp; kk < kn; kk += kGramGroups) {
       double x[4], y[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -458,6 +508,34 @@ __global__ __launch_bounds__(kBlock) void k_blk_gram_dd(const BasisDev* __restri
         }
     }
   }
+  // groups 1, 2, 3 in turn park their sums in LDS and group 0 adds them
+  double(*Yl)[kB + 1] = Ys;   // hi parked in Ys, lo in Yl2
+  __shared__ double Yl2[kB][kB + 1];
+  for (int g = 1; g < kGramGroups; ++g) {
+    __syncthreads();
+    if (grp == g) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Yl[ty * 4 + u][tx * 4 + v] = hi[u][v];
+          Yl2[ty * 4 + u][tx * 4 + v] = lo[u][v];
+        }
+    }
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double s2, se;
+          two_sum(hi[u][v], Yl[ty * 4 + u][tx * 4 + v], s2, se);
+          hi[u][v] = s2;
+          lo[u][v] += se + Yl2[ty * 4 + u][tx * 4 + v];
+        }
+    }
+  }
+  if (grp != 0) return;
   const int64_t off = (int64_t)blockIdx.x * kB * kB;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -836,18 +914,29 @@ __global__ __launch_bounds__(kBlock) void k_blk_take(const BasisDev* __restrict_
   const int na = sc->blk_na;
   if (na == 0 || (int)blockIdx.x >= ntake) return;
   const int64_t k = sc->n_accept_total;
-  for (int t = threadIdx.x; t < kB * kB; t += kBlock) Ts[t / kB][t % kB] = T[t];
+  constexpr int kLd = kB * kB / kBlock;   // tile elements per thread
+  {
+    double v[kLd];
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) v[u] = T[u * kBlock + threadIdx.x];
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) Ts[(u * kBlock + threadIdx.x) / kB][threadIdx.x % kB] = v[u];
+  }
   if (threadIdx.x < kB) ps[threadIdx.x] = threadIdx.x < na ? pos[threadIdx.x] : 0;
   const int rl = threadIdx.x / 4;
   const int a_lo = (threadIdx.x % 4) * 16;
   const int w = threadIdx.x / kWave, l = lane_id();
   dbl4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
   for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < n_rows; r0 += (int64_t)ntake * kB) {
-    __syncthreads();   // previous tile's Gram reads of Ys done (and Ts, ps written)
-    for (int t = threadIdx.x; t < kB * kB; t += kBlock) {
-      const int64_t rr = r0 + t / kB;
-      Ys[t / kB][t % kB] = rr < n_rows ? Ybuf[rr * kB + t % kB] : 0.0;
+    double v[kLd];
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int64_t rr = r0 + (u * kBlock + threadIdx.x) / kB;
+      v[u] = rr < n_rows ? Ybuf[rr * kB + threadIdx.x % kB] : 0.0;
     }
+    __syncthreads();   // previous tile's Gram reads of Ys done (and Ts, ps written)
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) Ys[(u * kBlock + threadIdx.x) / kB][threadIdx.x % kB] = v[u];
     __syncthreads();
     // new columns of rows 16 w .. + 16: lane (i, g) holds row 16 w + g + 4 x, column 16 ct + i
     dbl4 qo[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
@@ -1174,13 +1263,12 @@ __global__ __launch_bounds__(kBlock) void k_lev(const BasisDev* __restrict__ bd)
 }
 
 struct Splits {
-  int w, dd, take;
+  int dd, take;
 };
 // Row splits of one input: enough rows per split that small inputs do not
 // write (and sum) mostly empty partials.
 Splits splits_for(int64_t n_rows) {
   Splits sp;
-  sp.w = (int)std::max<int64_t>(1, std::min<int64_t>(kSplitW, div_up(n_rows, 256)));
   sp.dd = (int)std::max<int64_t>(1, std::min<int64_t>(kSplitDD, div_up(n_rows, 32)));
   sp.take = (int)std::max<int64_t>(1, std::min<int64_t>(kTakeParts, div_up(n_rows, kB)));
   return sp;
@@ -1199,10 +1287,18 @@ __global__ void k_put_dev(BasisDev* __restrict__ out, BasisPack pk, int n) {
 }
 }  // namespace
 
+// Room for the W2 partials at any block step of an input.
+size_t w2p_doubles(int64_t n_rows, int64_t cap) {
+  size_t w2p = 0;
+  for (int64_t T = 1; T <= div_up(cap, kB); ++T)
+    w2p = std::max(w2p, (size_t)w2_splits(n_rows, T) * kB * kB * T);
+  return w2p;
+}
+
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
   const Splits sp = splits_for(n_rows);
   return (size_t)kB * cap                           // W
-         + (size_t)sp.w * kB * cap + (size_t)kB * cap   // W2p, W2
+         + w2p_doubles(n_rows, cap) + (size_t)kB * cap   // W2p, W2
          + (size_t)sp.take * kB * kB                // part
          + (size_t)sp.dd * kB * kB * 2 + (size_t)kB * kB   // part_hi/lo, G_lo
          + (size_t)kB * kB * 3                      // G, Tcur, Tacc
@@ -1233,7 +1329,7 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     d.sc = scs[order[i]];
     d.W = a.scratch;
     d.W2p = d.W + (size_t)kB * a.cap;
-    d.W2 = d.W2p + (size_t)sp.w * kB * a.cap;
+    d.W2 = d.W2p + w2p_doubles(a.n_rows, a.cap);
     d.part = d.W2 + (size_t)kB * a.cap;
     d.part_hi = d.part + (size_t)sp.take * kB * kB;
     d.part_lo = d.part_hi + (size_t)sp.dd * kB * kB;
@@ -1245,7 +1341,6 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     d.Ybuf = d.g + kB;
     d.Zp = d.Ybuf + (size_t)kB * a.n_rows;
     d.pos = (int32_t*)(d.Zp + (size_t)newm_splits(a.cap) * a.cap * kB);
-    d.nsplit_w = sp.w;
     d.nsplit_dd = sp.dd;
     d.ntake = sp.take;
   }
@@ -1274,11 +1369,15 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
         const BasisDev& d = hd[z0 + nz];
         rows = std::max(rows, d.a.n_rows);
         kub = std::max(kub, std::min(std::min(d.a.n_rows, d.a.k0_max + b0), d.a.cap));
-        w_max = std::max(w_max, d.nsplit_w);
         dd_max = std::max(dd_max, d.nsplit_dd);
         take_max = std::max(take_max, d.ntake);
         ++nz;
       }
+      // column tiles of Q at this step (per input: capped by its capacity)
+      const int64_t t_launch = div_up(std::max<int64_t>(kub, 1), kB);
+      for (int i = z0; i < z0 + nz; ++i)
+        w_max = std::max(w_max, w2_splits(hd[i].a.n_rows,
+                                          std::min<int64_t>(t_launch, div_up(hd[i].a.cap, kB))));
       const int rows_tiles32 = div_up(rows, 32);
       const int rows4 = div_up(rows, kB);
       const int64_t k1 = std::max<int64_t>(kub, 1);
@@ -1286,12 +1385,14 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
                          bd, b0);
       hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0, false);
       // second projection against Q (block classical Gram-Schmidt, twice)
-      hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(k1, kB), w_max, nz), dim3(kGemm), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(k1, kB), w_max, nz), dim3(kGemm), 0, st, bd, b0,
+                         t_launch);
       hipLaunchKernelGGL(k_blk_w2_sum,
-                         dim3(std::max(1, std::min(1024, div_up((int64_t)kB * k1, kBlock))), 1, nz),
-                         dim3(kBlock), 0, st, bd, b0);
+                         dim3(std::max(1, std::min(4096, div_up((int64_t)kB * k1, kW2Per))), 1, nz),
+                         dim3(kBlock), 0, st, bd, b0, t_launch);
       hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0, true);
-      hipLaunchKernelGGL(k_blk_gram_dd, dim3(dd_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_gram_dd, dim3(dd_max, 1, nz), dim3(kBlock * kGramGroups), 0, st, bd,
+                         b0);
       hipLaunchKernelGGL(k_blk_sum_dd, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd, b0);
       hipLaunchKernelGGL(k_blk_decide, dim3(1, 1, nz), dim3(kChol), 0, st, bd, b0);
       hipLaunchKernelGGL(k_blk_take, dim3(take_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
