@@ -298,6 +298,11 @@ ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const fl
 namespace ctd {
 
 // Device array of basis arguments for up to `count` inputs.
+BasisSide* basis_side(ctd_handle* h) {
+  if (h->side_state == 0) h->side_state = basis_side_init(&h->side) ? 1 : -1;
+  return h->side_state > 0 ? &h->side : nullptr;
+}
+
 ctd_status ensure_bdev(ctd_handle* h, int count) {
   if (h->bdev && h->bdev_cap >= count) return CTD_OK;
   if (h->bdev) {
@@ -412,7 +417,7 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
   rc = ensure_bdev(h, 1);
   if (rc != CTD_OK) return rc;
   DevScalars* sc = h->d_sc;
-  launch_basis(h->stream, &ba, &sc, 1, h->bdev);
+  launch_basis(h->stream, &ba, &sc, 1, h->bdev, basis_side(h));
   mark(h, MARK_BASIS);
   return static_back(h, X, lay, s);
 }
@@ -543,6 +548,7 @@ void ctd_destroy(ctd_handle* h) {
     if (e) (void)hipEventDestroy(e);
   dyn_free(h);
   if (h->bdev) (void)hipFree(h->bdev);
+  if (h->side_state > 0) basis_side_free(&h->side);
   if (h->arena.base) (void)hipFree(h->arena.base);
   if (h->d_sc) (void)hipFree(h->d_sc);
   delete h;

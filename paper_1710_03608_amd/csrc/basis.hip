@@ -42,7 +42,7 @@ constexpr int kSplitDD = 256;   // row splits of the double-double Gram (at most
 struct BasisDev {
   BasisArgs a;
   DevScalars* sc;
-  double* W;        // 64 x cap: Q^T x rows of the block's candidates
+  double* W;        // 2 x 64 x cap: Q^T x rows of the candidates (even, odd steps)
   double* W2p;      // w2_splits x 64 x 64 T partial second-pass coefficients
   double* W2;       // 64 x cap
   double* part;     // ntake x 64 x 64 partial Grams of the new columns
@@ -52,9 +52,10 @@ struct BasisDev {
   double* G;
   double* Tcur;
   double* Tacc;
-  double* g;        // 64 squared candidate norms
-  double* Ybuf;     // n_rows x 64 block residuals
+  double* g;        // 2 x 64 squared candidate norms (even, odd steps)
+  double* Ybuf;     // 2 x n_rows x 64 block residuals (even, odd steps)
   double* Zp;       // newm_splits(cap) x cap x 64 partials of Z = M W_A^T
+  int64_t* kcut;    // 2: columns of Q the early first pass of a step covers
   int32_t* pos;     // 64 kept positions
   int32_t nsplit_dd, ntake;
   int32_t pad;
@@ -109,6 +110,24 @@ __device__ inline void dd_rsqrt(double ah, double al, double& rh, double& rl) {
   quick_two_sum(r0, r0 * e * 0.5, rh, rl);
 }
 
+// Steps alternate between two sets of the per-step buffers W, g and Ybuf, so
+// that the first projection pass of step b0 + 64 can run while step b0 is
+// still deciding (see launch_basis).
+__device__ inline int64_t blk_par(int64_t b0) { return (b0 / kB) & 1; }
+__device__ inline double* w_of(const BasisDev& d, int64_t b0) {
+  return d.W + blk_par(b0) * kB * d.a.cap;
+}
+__device__ inline double* g_of(const BasisDev& d, int64_t b0) { return d.g + blk_par(b0) * kB; }
+__device__ inline double* y_of(const BasisDev& d, int64_t b0) {
+  return d.Ybuf + blk_par(b0) * kB * d.a.n_rows;
+}
+
+// First-pass column ranges: the whole of [0, k) at once, or split into an
+// early part [0, kcut) (run ahead on a second stream against the columns
+// already final) and the late part [kcut, k) (the previous step's new
+// columns, at most 64, whose coefficients come from the early residual).
+enum Pass1 : int { kPassAll = 0, kPassEarly = 1, kPassLate = 2 };
+
 __device__ inline int64_t blk_count(const DevScalars* sc, int64_t b0) {
   const int64_t sp = sc->status == 0 ? sc->s_unique : 0;
   return b0 < sp ? min((int64_t)kB, sp - b0) : 0;
@@ -120,7 +139,20 @@ __device__ inline int64_t blk_work(const DevScalars* sc, int64_t b0, int64_t n_r
   return sc->n_accept_total >= n_rows ? 0 : blk_count(sc, b0);
 }
 
-// W[j][c] = sum_e v_e Q[r_e][c] for c < k, and g[j] = ||x_{b0+j}||^2.
+// The late part runs on the second stream too, as soon as the previous
+// step's new columns are final, while that step still finishes: its range is
+// [kcut, kcut + na) with na that step's kept count (read before the next
+// decisions overwrite it), and whether the step has work follows from the
+// range's end, the k the step starts with.
+__device__ inline int64_t late_end(const BasisDev& d, int64_t b0) {
+  return d.kcut[blk_par(b0)] + d.sc->blk_na;
+}
+__device__ inline int64_t late_work(const BasisDev& d, int64_t b0) {
+  return late_end(d, b0) >= d.a.n_rows ? 0 : blk_count(d.sc, b0);
+}
+
+// W[j][c] = sum_e v_e Q[r_e][c] for c in the first pass's range (all of
+// [0, k), or the early part [0, kcut)), and g[j] = ||x_{b0+j}||^2.
 // Workgroup (chunk, j) covers columns 128 chunk .. + 128 of candidate j (two
 // per lane); its eight waves take the fiber's nonzeros in interleaved groups
 // of 16 (sixteen row gathers in flight per wave) and their partial rows are
@@ -128,7 +160,7 @@ __device__ inline int64_t blk_work(const DevScalars* sc, int64_t b0, int64_t n_r
 constexpr int kWWaves = 8;
 constexpr int kWCols = 2 * kWave;
 __global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(const BasisDev* __restrict__ bd,
-                                                            int64_t b0) {
+                                                            int64_t b0, int pass) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Q = d.a.Q;
   const int64_t ldq = d.a.ldq, ldw = d.a.cap;
@@ -136,14 +168,16 @@ __global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(const BasisDev* __res
   const int32_t* __restrict__ fptr = d.a.fptr;
   const int32_t* __restrict__ row = d.a.row;
   const double* __restrict__ val = d.a.val;
-  double* __restrict__ W = d.W;
-  double* __restrict__ g = d.g;
+  double* __restrict__ W = w_of(d, b0);
+  double* __restrict__ g = g_of(d, b0);
   const DevScalars* sc = d.sc;
   constexpr int kU = 16;
   __shared__ double part[kWWaves][kWCols];
   __shared__ double gpart[kWWaves];
-  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
-  const int64_t k = sc->n_accept_total;
+  const int64_t kc = d.kcut[blk_par(b0)];
+  const int64_t nb = pass == kPassEarly ? (kc >= d.a.n_rows ? 0 : blk_count(sc, b0))
+                                        : blk_work(sc, b0, d.a.n_rows);
+  const int64_t k = pass == kPassEarly ? kc : (int64_t)sc->n_accept_total;
   const int j = blockIdx.y;
   const int64_t cbase = (int64_t)blockIdx.x * kWCols;
   if (j >= nb || (blockIdx.x > 0 && cbase >= k)) return;
@@ -206,38 +240,48 @@ __global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(const BasisDev* __res
 constexpr int kGemm = 512;
 constexpr int kGK = 32;       // reduction chunk
 
-// Y[r][j] = P[r][b0 + j] - sum_{c<k} Q[r][c] W[j][c] for every candidate j of
-// the block (residuals against span(Q)), into Ybuf (n_rows x 64).  One
+// Y[r][j] = P[r][b0 + j] - sum_c Q[r][c] W[j][c] for every candidate j of
+// the block (residuals against span(Q)), into Ybuf (n_rows x 64), over the
+// first-pass range of columns: all of [0, k) or the early part [0, kcut)
+// (kPassAll, kPassEarly); the late part subtracts the rest, Ybuf[r][j] -=
+// sum_{kcut <= c < k} Q[r][c] W[j][c] (kPassLate); the second projection pass
+// subtracts Ybuf[r][j] -= sum_{c < k} Q[r][c] W2[j][c] (kReproject).  One
 // workgroup per 32 rows; wave w of a group computes rows 16 (w / 2) .. + 16
 // and candidates 32 (w % 2) .. + 32 with two f64 MFMA accumulators.
-// With reproject set, the base is Ybuf itself (second projection pass):
-// Ybuf[r][j] -= sum_c Q[r][c] W2[j][c].
+constexpr int kReproject = 3;
 __global__ __launch_bounds__(kGemm) void k_blk_form_y(const BasisDev* __restrict__ bd, int64_t b0,
-                                                      bool reproject) {
+                                                      int pass) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ P = d.a.P;
   const double* __restrict__ Q = d.a.Q;
-  const double* __restrict__ W = reproject ? d.W2 : d.W;
+  const bool reproject = pass == kReproject, subtract = reproject || pass == kPassLate;
+  const double* __restrict__ W = reproject ? d.W2 : w_of(d, b0);
   const int64_t ldp = d.a.ldp, n_rows = d.a.n_rows, ldq = d.a.ldq, ldw = d.a.cap;
-  double* __restrict__ Ybuf = d.Ybuf;
+  double* __restrict__ Ybuf = y_of(d, b0);
   const DevScalars* sc = d.sc;
   constexpr int kR = 32;
   __shared__ double As[2][kR][kGK + 1];   // Q tile [row][c]
   __shared__ double Bs[2][kGK][kB + 1];   // W^T tile [c][j]
-  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
+  const int64_t kc = d.kcut[blk_par(b0)];
+  const int64_t nb = pass == kPassEarly  ? (kc >= n_rows ? 0 : blk_count(sc, b0))
+                     : pass == kPassLate ? late_work(d, b0)
+                                         : blk_work(sc, b0, n_rows);
   if (nb == 0) return;
-  const int64_t k = sc->n_accept_total;
-  if (reproject && k == 0) return;
+  const int64_t klo = pass == kPassLate ? kc : 0;
+  const int64_t k = pass == kPassEarly  ? kc
+                    : pass == kPassLate ? late_end(d, b0)
+                                        : (int64_t)sc->n_accept_total;
+  if (subtract && klo >= k) return;
   const int64_t r0 = (int64_t)blockIdx.x * kR;
   if (r0 >= n_rows) return;
   const int grp = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
   const int w = t / kWave, l = lane_id();
   const int rb = (w / 2) * 16, cb = (w % 2) * 32;
-  const int64_t nch = (k + kGK - 1) / kGK;
+  const int64_t nch = (k - klo + kGK - 1) / kGK;
   const int64_t iters = (nch + 1) / 2;
   double ra[kR * kGK / kBlock], rw[kB * kGK / kBlock];
   auto load = [&](int64_t ch) {
-    const int64_t c0 = ch * kGK;
+    const int64_t c0 = klo + ch * kGK;
 #pragma unroll
     for (int u = 0; u < kR * kGK / kBlock; ++u) {
       const int idx = u * kBlock + t, r = idx / kGK, c = idx % kGK;
@@ -293,7 +337,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_form_y(const BasisDev* __restrict
     if (row >= n_rows) continue;
     const int j0 = cb + l % 16, j1 = cb + 16 + l % 16;
     const double s0 = acc0[r] + red[rr][j0], s1 = acc1[r] + red[rr][j1];
-    if (reproject) {
+    if (subtract) {
       if (j0 < nb) Ybuf[row * kB + j0] -= s0;
       if (j1 < nb) Ybuf[row * kB + j1] -= s1;
     } else {
@@ -324,22 +368,28 @@ __device__ inline int64_t w2_tiles(const BasisDev& d, int64_t t_launch) {
 // partial over w2_splits row ranges: workgroup (ct, s) covers c in
 // [64 ct, 64 ct + 64) and writes W2p[s][j][c] (row length 64 T); wave w of a
 // group computes c rows 16 w .. + 16 against all 64 j with four f64 MFMA
-// tiles.
+// tiles.  With late set, the same for the late part of the first pass, the
+// previous step's new columns c in [kcut, k) (at most 64) against the early
+// residual: W[j][c] = sum_r Q[r][c] Y[r][j] (these columns are orthogonal to
+// the ones the early part removed, so this equals Q^T x to working accuracy,
+// and it is exactly the coefficient the late pass subtracts); T is then 1 and
+// W2p[s][j][c - kcut].
 __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restrict__ bd,
-                                                       int64_t b0, int64_t t_launch) {
+                                                       int64_t b0, int64_t t_launch, int late) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Q = d.a.Q;
-  const double* __restrict__ Y = d.Ybuf;
+  const double* __restrict__ Y = y_of(d, b0);
   double* __restrict__ W2p = d.W2p;
   const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows;
-  const int64_t T = w2_tiles(d, t_launch), ldp = T * kB;
+  const int64_t T = late ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
   const int nsplit = w2_splits(n_rows, T);
   const DevScalars* sc = d.sc;
   __shared__ double Qs[2][kGK][kB + 1];   // [r][c]
   __shared__ double Ys[2][kGK][kB + 1];   // [r][j]
-  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
-  const int64_t k = sc->n_accept_total;
-  const int64_t c0 = (int64_t)blockIdx.x * kB;
+  const int64_t nb = late ? late_work(d, b0) : blk_work(sc, b0, d.a.n_rows);
+  const int64_t k = late ? late_end(d, b0) : (int64_t)sc->n_accept_total;
+  const int64_t cw = late ? d.kcut[blk_par(b0)] : 0;   // first column held
+  const int64_t c0 = cw + (int64_t)blockIdx.x * kB;
   if (nb == 0 || c0 >= k || (int)blockIdx.y >= nsplit) return;
   const int64_t chunk = (n_rows + nsplit - 1) / nsplit;
   const int64_t r0 = blockIdx.y * chunk, r1 = min(n_rows, r0 + chunk);
@@ -396,28 +446,30 @@ __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restric
       const int cc = w * 16 + l / 16 + 4 * r;
       const int64_t c = c0 + cc;
       const int j = q * 16 + l % 16;
-      if (c < k) p[(int64_t)j * ldp + c] = acc[q][r] + red[cc][j];
+      if (c < k) p[(int64_t)j * ldp + c - cw] = acc[q][r] + red[cc][j];
     }
 }
 
-// W2[j][c] = sum_s W2p[s][j][c] (fixed order); W[j][c] += W2[j][c].  A
+// W2[j][c] = sum_s W2p[s][j][c] (fixed order); W[j][c] += W2[j][c] (late:
+// W[j][kcut + c] = sum_s W2p[s][j][c] for the late first-pass columns).  A
 // workgroup takes 32 consecutive entries per pass, each summed by kW2Ways
 // threads over every kW2Ways-th partial (all loads in flight together), and
 // the ways are added in order.
 constexpr int kW2Ways = 8, kW2Per = kBlock / kW2Ways;
 __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restrict__ bd,
-                                                       int64_t b0, int64_t t_launch) {
+                                                       int64_t b0, int64_t t_launch, int late) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ W2p = d.W2p;
   double* __restrict__ W2 = d.W2;
-  double* __restrict__ W = d.W;
+  double* __restrict__ W = w_of(d, b0);
   const int64_t ldw = d.a.cap;
-  const int64_t T = w2_tiles(d, t_launch), ldp = T * kB;
+  const int64_t T = late ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
   const int nsplit = w2_splits(d.a.n_rows, T);
   const DevScalars* sc = d.sc;
-  const int64_t nb = blk_work(sc, b0, d.a.n_rows);
-  const int64_t k = sc->n_accept_total;
-  const int64_t total = nb * k;
+  const int64_t nb = late ? late_work(d, b0) : blk_work(sc, b0, d.a.n_rows);
+  const int64_t cw = late ? d.kcut[blk_par(b0)] : 0;   // first column
+  const int64_t k = (late ? late_end(d, b0) : (int64_t)sc->n_accept_total) - cw;   // columns
+  const int64_t total = k > 0 ? nb * k : 0;
   __shared__ double sh[kBlock];
   const int e = threadIdx.x % kW2Per, q = threadIdx.x / kW2Per;
   constexpr int kIt = kSplitWMax / kW2Ways;
@@ -439,8 +491,12 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
     __syncthreads();
     if (q == 0 && t < total) {
       for (int w = 1; w < kW2Ways; ++w) s += sh[w * kW2Per + e];
-      W2[j * ldw + c] = s;
-      W[j * ldw + c] += s;
+      if (late) {
+        W[j * ldw + cw + c] = s;
+      } else {
+        W2[j * ldw + c] = s;
+        W[j * ldw + c] += s;
+      }
     }
     __syncthreads();
   }
@@ -458,7 +514,7 @@ constexpr int kGramGroups = 4;
 __global__ __launch_bounds__(kBlock * kGramGroups) void k_blk_gram_dd(const BasisDev* __restrict__ bd,
                                                                       int64_t b0) {
   const BasisDev& d = bd[blockIdx.z];
-  const double* __restrict__ Y = d.Ybuf;
+  const double* __restrict__ Y = y_of(d, b0);
   double* __restrict__ part_hi = d.part_hi;
   double* __restrict__ part_lo = d.part_lo;
   const int64_t n_rows = d.a.n_rows;
@@ -791,7 +847,7 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const BasisDev* __restrict
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ G = d.G;
   const double* __restrict__ Glo = d.Glo;
-  const double* __restrict__ g = d.g;
+  const double* __restrict__ g = g_of(d, b0);
   const double eps2 = d.a.eps2;
   const int64_t n_rows = d.a.n_rows;
   int32_t* __restrict__ pos = d.pos;
@@ -898,7 +954,7 @@ __global__ __launch_bounds__(kChol) void k_blk_cholinv(const BasisDev* __restric
 // check of the block.
 __global__ __launch_bounds__(kBlock) void k_blk_take(const BasisDev* __restrict__ bd, int64_t b0) {
   const BasisDev& d = bd[blockIdx.z];
-  const double* __restrict__ Ybuf = d.Ybuf;
+  const double* __restrict__ Ybuf = y_of(d, b0);
   const double* __restrict__ P = d.a.P;
   const int32_t* __restrict__ pos = d.pos;
   const double* __restrict__ T = d.Tacc;
@@ -1041,10 +1097,11 @@ inline int64_t newm_jw(int64_t k1) {
 inline int64_t newm_splits(int64_t cap) {
   return std::min<int64_t>(kNewmSplits, div_up(cap, kNewmJMin));
 }
-__global__ __launch_bounds__(kGemm) void k_blk_newm_part(const BasisDev* __restrict__ bd, int64_t jw) {
+__global__ __launch_bounds__(kGemm) void k_blk_newm_part(const BasisDev* __restrict__ bd, int64_t b0,
+                                                         int64_t jw) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ M = d.a.M;
-  const double* __restrict__ W = d.W;
+  const double* __restrict__ W = w_of(d, b0);
   const int32_t* __restrict__ pos = d.pos;
   double* __restrict__ Zp = d.Zp;
   const int64_t ldm = d.a.ldm, ldw = d.a.cap;
@@ -1206,7 +1263,7 @@ __global__ void k_blk_finish(const BasisDev* __restrict__ bd, int64_t b0) {
   uint64_t* __restrict__ acc_fid = d.a.acc_fid;
   int32_t* __restrict__ acc_fi_local = d.a.acc_fi_local;
   uint8_t* __restrict__ fiber_mark = d.a.fiber_mark;
-  const double* __restrict__ W = d.W;
+  const double* __restrict__ W = w_of(d, b0);
   double* __restrict__ Wacc = d.a.Wacc;
   const int64_t ldw = d.a.cap, ldwa = d.a.ldwa;
   DevScalars* sc = d.sc;
@@ -1228,13 +1285,17 @@ __global__ void k_blk_finish(const BasisDev* __restrict__ bd, int64_t b0) {
   if (threadIdx.x == 0) {
     sc->n_accept_total = (int32_t)(k + na);
     sc->s_tilde += na;
+    d.kcut[blk_par(b0)] = k + na;   // the early first pass of step b0 + 128
   }
 }
 
 __global__ void k_begin_basis(const BasisDev* __restrict__ bd) {
-  DevScalars* sc = bd[blockIdx.z].sc;
+  const BasisDev& d = bd[blockIdx.z];
+  DevScalars* sc = d.sc;
   sc->base_accept = sc->n_accept_total;   // kept before this call
   sc->s_tilde = 0;
+  d.kcut[0] = sc->n_accept_total;
+  d.kcut[1] = sc->n_accept_total;   // the early first pass of step 64
 }
 
 // lev[i] = sum_{c in [c0, k)} Q[i][c]^2 (+= when accumulating); Qf copy of those columns.
@@ -1297,13 +1358,14 @@ size_t w2p_doubles(int64_t n_rows, int64_t cap) {
 
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
   const Splits sp = splits_for(n_rows);
-  return (size_t)kB * cap                           // W
+  return (size_t)2 * kB * cap                       // W (two sets)
          + w2p_doubles(n_rows, cap) + (size_t)kB * cap   // W2p, W2
          + (size_t)sp.take * kB * kB                // part
          + (size_t)sp.dd * kB * kB * 2 + (size_t)kB * kB   // part_hi/lo, G_lo
          + (size_t)kB * kB * 3                      // G, Tcur, Tacc
-         + kB                                       // g
-         + (size_t)kB * n_rows                      // Ybuf
+         + 2 * kB                                   // g (two sets)
+         + (size_t)2 * kB * n_rows                  // Ybuf (two sets)
+         + 2                                        // kcut
          + (size_t)newm_splits(cap) * cap * kB      // Zp
          + 64;                                      // pos
 }
@@ -1311,7 +1373,7 @@ size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
 size_t basis_dev_bytes(int count) { return (size_t)std::max(count, 1) * sizeof(BasisDev); }
 
 void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs, int count,
-                  void* dev) {
+                  void* dev, BasisSide* side) {
   if (count <= 0) return;
   // inputs in order of decreasing candidate bound, so the inputs still
   // working at a block step are a prefix of the array
@@ -1328,7 +1390,7 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     d.a = a;
     d.sc = scs[order[i]];
     d.W = a.scratch;
-    d.W2p = d.W + (size_t)kB * a.cap;
+    d.W2p = d.W + (size_t)2 * kB * a.cap;
     d.W2 = d.W2p + w2p_doubles(a.n_rows, a.cap);
     d.part = d.W2 + (size_t)kB * a.cap;
     d.part_hi = d.part + (size_t)sp.take * kB * kB;
@@ -1338,8 +1400,9 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     d.Tcur = d.G + kB * kB;
     d.Tacc = d.Tcur + kB * kB;
     d.g = d.Tacc + kB * kB;
-    d.Ybuf = d.g + kB;
-    d.Zp = d.Ybuf + (size_t)kB * a.n_rows;
+    d.Ybuf = d.g + 2 * kB;
+    d.kcut = (int64_t*)(d.Ybuf + (size_t)2 * kB * a.n_rows);
+    d.Zp = (double*)(d.kcut + 2);
     d.pos = (int32_t*)(d.Zp + (size_t)newm_splits(a.cap) * a.cap * kB);
     d.nsplit_dd = sp.dd;
     d.ntake = sp.take;
@@ -1353,61 +1416,137 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
   }
   const int sums = kB * kB * kSumWays / kBlock;
   constexpr int kMaxZ = 65535;
+  const bool ahead = side && side->st;
   for (int z0 = 0; z0 < count; z0 += kMaxZ) {
     const int nz_all = std::min(kMaxZ, count - z0);
     const BasisDev* bd = dd + z0;
     int64_t rows_all = 1;
     for (int i = z0; i < z0 + nz_all; ++i) rows_all = std::max(rows_all, hd[i].a.n_rows);
+    // inputs with candidates left at b0 (a prefix), and host bounds over them
+    // of the columns held at the start of the step (k <= min(n_rows, k0 + b0))
+    // and of the row splits
+    struct Bounds {
+      int nz = 0, dd_max = 1, take_max = 1;
+      int64_t rows = 1, kub = 0;
+    };
+    auto bounds = [&](int64_t b0) {
+      Bounds r;
+      while (r.nz < nz_all && hd[z0 + r.nz].a.s_max > b0) {
+        const BasisDev& d = hd[z0 + r.nz];
+        r.rows = std::max(r.rows, d.a.n_rows);
+        r.kub = std::max(r.kub, std::min(std::min(d.a.n_rows, d.a.k0_max + b0), d.a.cap));
+        r.dd_max = std::max(r.dd_max, d.nsplit_dd);
+        r.take_max = std::max(r.take_max, d.ntake);
+        ++r.nz;
+      }
+      return r;
+    };
+    const dim3 wthreads(kWWaves * kWave);
     hipLaunchKernelGGL(k_begin_basis, dim3(1, 1, nz_all), dim3(1), 0, st, bd);
     for (int64_t b0 = 0; b0 < hd[z0].a.s_max; b0 += kB) {
-      // inputs with candidates left at b0, and host bounds over them of the
-      // columns held (k <= min(n_rows, k0 + b0)) and of the row splits
-      int nz = 0;
-      int64_t rows = 1, kub = 0;
-      int w_max = 1, dd_max = 1, take_max = 1;
-      while (nz < nz_all && hd[z0 + nz].a.s_max > b0) {
-        const BasisDev& d = hd[z0 + nz];
-        rows = std::max(rows, d.a.n_rows);
-        kub = std::max(kub, std::min(std::min(d.a.n_rows, d.a.k0_max + b0), d.a.cap));
-        dd_max = std::max(dd_max, d.nsplit_dd);
-        take_max = std::max(take_max, d.ntake);
-        ++nz;
-      }
+      const Bounds bn = bounds(b0);
+      const int nz = bn.nz;
+      const int64_t k1 = std::max<int64_t>(bn.kub, 1);
+      const int rows_tiles32 = div_up(bn.rows, 32);
+      const int rows4 = div_up(bn.rows, kB);
       // column tiles of Q at this step (per input: capped by its capacity)
-      const int64_t t_launch = div_up(std::max<int64_t>(kub, 1), kB);
+      const int64_t t_launch = div_up(k1, kB);
+      int w_max = 1;
       for (int i = z0; i < z0 + nz; ++i)
         w_max = std::max(w_max, w2_splits(hd[i].a.n_rows,
                                           std::min<int64_t>(t_launch, div_up(hd[i].a.cap, kB))));
-      const int rows_tiles32 = div_up(rows, 32);
-      const int rows4 = div_up(rows, kB);
-      const int64_t k1 = std::max<int64_t>(kub, 1);
-      hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nz), dim3(kWWaves * kWave), 0, st,
-                         bd, b0);
-      hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0, false);
+      const int par = (int)((b0 / kB) & 1);
+      // first projection pass: at the first step all of it here; later, its
+      // early part ran on the side stream during the previous step and the
+      // late part (the previous step's new columns) follows here
+      if (ahead && b0 > 0) {
+        (void)hipStreamWaitEvent(st, side->done[par], 0);   // both parts ran on the side
+      } else {
+        hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nz), wthreads, 0, st, bd, b0,
+                           (int)kPassAll);
+        hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0,
+                           (int)kPassAll);
+      }
       // second projection against Q (block classical Gram-Schmidt, twice)
       hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(k1, kB), w_max, nz), dim3(kGemm), 0, st, bd, b0,
-                         t_launch);
+                         t_launch, 0);
       hipLaunchKernelGGL(k_blk_w2_sum,
                          dim3(std::max(1, std::min(4096, div_up((int64_t)kB * k1, kW2Per))), 1, nz),
-                         dim3(kBlock), 0, st, bd, b0, t_launch);
-      hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0, true);
-      hipLaunchKernelGGL(k_blk_gram_dd, dim3(dd_max, 1, nz), dim3(kBlock * kGramGroups), 0, st, bd,
-                         b0);
+                         dim3(kBlock), 0, st, bd, b0, t_launch, 0);
+      hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0,
+                         kReproject);
+      hipLaunchKernelGGL(k_blk_gram_dd, dim3(bn.dd_max, 1, nz), dim3(kBlock * kGramGroups), 0, st,
+                         bd, b0);
       hipLaunchKernelGGL(k_blk_sum_dd, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd, b0);
+      // early part of the next step's first pass, against the k columns held
+      // at the start of this step (final once the previous step finished),
+      // started as this step's single-workgroup decisions begin; it writes
+      // the other set of W, g and Ybuf
+      if (ahead && b0 + kB < hd[z0].a.s_max) {
+        const Bounds nx = bounds(b0 + kB);
+        (void)hipEventRecord(side->start, st);
+        (void)hipStreamWaitEvent(side->st, side->start, 0);
+        hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nx.nz), wthreads, 0, side->st, bd,
+                           b0 + kB, (int)kPassEarly);
+        hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0,
+                           side->st, bd, b0 + kB, (int)kPassEarly);
+      }
       hipLaunchKernelGGL(k_blk_decide, dim3(1, 1, nz), dim3(kChol), 0, st, bd, b0);
-      hipLaunchKernelGGL(k_blk_take, dim3(take_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
+      hipLaunchKernelGGL(k_blk_take, dim3(bn.take_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
       hipLaunchKernelGGL(k_blk_sum_parts, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd);
       hipLaunchKernelGGL(k_blk_cholinv, dim3(1, 1, nz), dim3(kChol), 0, st, bd);
       hipLaunchKernelGGL(k_blk_apply, dim3(rows4, 1, nz), dim3(kBlock), 0, st, bd);
+      // late part of the next step's first pass: this step's new columns
+      // are final here, and M's new columns and the book-keeping follow on st
+      if (ahead && b0 + kB < hd[z0].a.s_max) {
+        const Bounds nx = bounds(b0 + kB);
+        int w_late = 1;
+        for (int i = z0; i < z0 + nx.nz; ++i) w_late = std::max(w_late, w2_splits(hd[i].a.n_rows, 1));
+        (void)hipEventRecord(side->mid, st);
+        (void)hipStreamWaitEvent(side->st, side->mid, 0);
+        hipLaunchKernelGGL(k_blk_w2_part, dim3(1, w_late, nx.nz), dim3(kGemm), 0, side->st, bd,
+                           b0 + kB, (int64_t)1, 1);
+        hipLaunchKernelGGL(k_blk_w2_sum, dim3(div_up((int64_t)kB * kB, kW2Per), 1, nx.nz),
+                           dim3(kBlock), 0, side->st, bd, b0 + kB, (int64_t)1, 1);
+        hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0,
+                           side->st, bd, b0 + kB, (int)kPassLate);
+        (void)hipEventRecord(side->done[1 - par], side->st);
+      }
       const int64_t jw = newm_jw(k1);
       hipLaunchKernelGGL(k_blk_newm_part, dim3(div_up(k1, 32), div_up(k1, jw), nz), dim3(kGemm), 0,
-                         st, bd, jw);
+                         st, bd, b0, jw);
       hipLaunchKernelGGL(k_blk_newm_fin, dim3(div_up(k1, 32), 1, nz), dim3(kGemm), 0, st, bd, jw);
       hipLaunchKernelGGL(k_blk_finish, dim3(1, 1, nz), dim3(256), 0, st, bd, b0);
     }
     hipLaunchKernelGGL(k_lev, dim3(div_up(rows_all * kWave, kBlock), 1, nz_all), dim3(kBlock), 0, st,
                        bd);
   }
+}
+
+bool basis_side_init(BasisSide* side) {
+  *side = BasisSide{};
+  // the events order work between two streams of one device: a device-scope
+  // release suffices (no system-scope cache writeback at each record)
+  const unsigned fl = hipEventDisableTiming | hipEventReleaseToDevice;
+  bool ok = hipStreamCreateWithFlags(&side->st, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&side->start, fl) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&side->mid, fl) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&side->done[0], fl) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&side->done[1], fl) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    basis_side_free(side);
+  }
+  return ok;
+}
+
+void basis_side_free(BasisSide* side) {
+  if (side->st) (void)hipStreamDestroy(side->st);
+  if (side->start) (void)hipEventDestroy(side->start);
+  if (side->mid) (void)hipEventDestroy(side->mid);
+  for (hipEvent_t& e : side->done)
+    if (e) (void)hipEventDestroy(e);
+  *side = BasisSide{};
 }
 
 }  // namespace ctd

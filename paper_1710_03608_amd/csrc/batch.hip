@@ -180,7 +180,7 @@ extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, in
     }
     ctd_status rc = ensure_bdev(h, n);
     if (rc != CTD_OK) return rc;
-    launch_basis(h->stream, args.data(), scs.data(), n, h->bdev);
+    launch_basis(h->stream, args.data(), scs.data(), n, h->bdev, basis_side(h));
     BATCH_HIP(h, hipGetLastError());
     BATCH_HIP(h, hipEventRecord(B.based, h->stream));
     for (int k = 0; k < K; ++k) BATCH_HIP(h, hipStreamWaitEvent(B.pool[k], B.based, 0));

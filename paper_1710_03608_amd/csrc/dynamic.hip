@@ -913,7 +913,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       ba.cap = S.capD;
       rc = ensure_bdev(h, 1);
       if (rc != CTD_OK) return rc;
-      launch_basis(st, &ba, &sc, 1, h->bdev);
+      launch_basis(st, &ba, &sc, 1, h->bdev, basis_side(h));
       mark(h, MARK_BASIS);
       // the slice's own columns R^(t+1)T dX (rows held after its filter)
       if (mixed)

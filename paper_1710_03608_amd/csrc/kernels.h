@@ -125,11 +125,26 @@ struct BasisArgs {
 size_t basis_scratch_doubles(int64_t n_rows, int64_t cap);
 // Device bytes of the argument array for `count` inputs.
 size_t basis_dev_bytes(int count);
+// A second stream (default priority, non-blocking) and events on which the
+// first projection pass of each block step runs ahead, against the columns of
+// Q already final, while the previous step decides.  Owned by the caller.
+struct BasisSide {
+  hipStream_t st = nullptr;
+  hipEvent_t start = nullptr, mid = nullptr;
+  hipEvent_t done[2] = {nullptr, nullptr};
+};
+// Creates the stream and events on the current device; false (and nothing
+// held) if any creation fails.
+bool basis_side_init(BasisSide* side);
+void basis_side_free(BasisSide* side);
 // The basis of `count` independent inputs (args[i] with scalars scs[i]) in one
 // sequence of launches on st; dev holds basis_dev_bytes(count) device bytes
-// that stay untouched by others until the launches have run.
+// that stay untouched by others until the launches have run.  With a side
+// (may be null), part of each step runs on side->st, joined back to st by
+// events before the step's results are used: the work as a whole is ordered
+// on st like a single-stream launch sequence.
 void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs, int count,
-                  void* dev);
+                  void* dev, BasisSide* side);
 
 // ---- project.hip -----------------------------------------------------------
 // A8: per-fiber residual ||x_f||^2 - ||Q^T x_f||^2 (0 for marked fibers) and

@@ -137,6 +137,8 @@ struct ctd_handle {
   int64_t nnz_seen = 0;             // nonzeros of all input held (CTD-D: initial plus slices)
   void* bdev = nullptr;             // device array of basis arguments
   int bdev_cap = 0;
+  ctd::BasisSide side{};            // side stream of the basis (created at first use)
+  int side_state = 0;               // 0 not yet tried, 1 held, -1 unavailable
   ctd::BatchState* batch = nullptr;
 };
 
@@ -152,6 +154,9 @@ int64_t round8(int64_t x);
 ctd_status fail(ctd_handle* h, ctd_status st, const std::string& msg);
 ctd_status check_coo(ctd_handle* h, const ctd_coo* X, int32_t mode, FiberLayout* lay,
                      uint64_t* n_cols_total);
+// The handle's basis side stream, created on first use; null if unavailable
+// (the basis then runs on the handle's stream alone).
+BasisSide* basis_side(ctd_handle* h);
 ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bool mixed,
                        bool want_C, bool want_R, int64_t max_cols, StaticBufs* b);
 ctd_status enqueue_input(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, int64_t s,
