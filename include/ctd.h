@@ -181,7 +181,7 @@ ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B, i
  * CTD-S): tensor b of the host array Xs[0..B) gets Algorithm 1 with s[b]
  * draws in mode `mode`, its draws using Philox counter word tensor = b
  * (tensor 0 reproduces ctd_decompose).  Tensors go in groups within a
- * workspace budget: the per-tensor stages run concurrently on internal
+ * workspace budget (128 GiB): the per-tensor stages run concurrently on internal
  * streams of default priority, and the independence filter and basis of a
  * whole group run as one sequence of launches on the handle's stream.  All
  * of it is ordered after the caller's earlier work on that stream, and later

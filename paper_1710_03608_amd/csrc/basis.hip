@@ -31,6 +31,7 @@ constexpr int kTakeParts = 256;   // workgroups of k_blk_take: partial Grams of 
 constexpr int kBlock = 256;
 constexpr int kSplitWMax = 128; // row splits of W2 = Q^T Y (at most)
 constexpr int kW2Grid = 512;    // workgroups aimed at for W2 = Q^T Y (two per CU)
+constexpr int kFewInputs = 4;   // inputs per launch up to which single-input tunings apply
 constexpr int kSplitDD = 256;   // row splits of the double-double Gram (at most)
 
 
@@ -54,7 +55,7 @@ struct BasisDev {
   double* Tacc;
   double* g;        // 2 x 64 squared candidate norms (even, odd steps)
   double* Ybuf;     // 2 x n_rows x 64 block residuals (even, odd steps)
-  double* Zp;       // newm_splits(cap) x cap x 64 partials of Z = M W_A^T
+  double* Zp;       // newm_splits(kmax) x kmax x 64 partials of Z = M W_A^T
   int64_t* kcut;    // 2: columns of Q the early first pass of a step covers
   int32_t* pos;     // 64 kept positions
   int32_t nsplit_dd, ntake;
@@ -348,19 +349,25 @@ __global__ __launch_bounds__(kGemm) void k_blk_form_y(const BasisDev* __restrict
 }
 
 // Row splits of W2 = Q^T Y at a block step whose Q spans T tiles of 64
-// columns: at most kW2Grid workgroups in all (one round of two resident
-// workgroups per CU: a second round for a few more costs more than the
-// larger splits), each split at least 64 rows, at most kSplitWMax splits.
-// A step's own T is the launch's bound capped by the input's column capacity.
-__host__ __device__ inline int w2_splits(int64_t n_rows, int64_t T) {
+// columns, for nz inputs in the launch: at most kW2Grid workgroups in all
+// (one round of two resident workgroups per CU: a second round for a few more
+// costs more than the larger splits), each split at least 64 rows, at most
+// kSplitWMax splits.  A step's own T is the launch's bound capped by the
+// input's column capacity.
+__host__ __device__ inline int w2_splits(int64_t n_rows, int64_t T, int nz) {
   int64_t by_rows = (n_rows + 63) / 64;
   if (by_rows > kSplitWMax) by_rows = kSplitWMax;
-  int64_t want = kW2Grid / (T > 0 ? T : 1);
+  int64_t want = kW2Grid / ((T > 0 ? T : 1) * (nz > 0 ? nz : 1));
   if (want > by_rows) want = by_rows;
   return want > 0 ? (int)want : 1;
 }
+// Columns an input can hold: at most its capacity and at most n_rows (kept
+// fibers are linearly independent).
+__host__ __device__ inline int64_t kmax_of(const BasisArgs& a) {
+  return a.cap < a.n_rows ? a.cap : a.n_rows;
+}
 __device__ inline int64_t w2_tiles(const BasisDev& d, int64_t t_launch) {
-  const int64_t tc = (d.a.cap + kB - 1) / kB;
+  const int64_t tc = (kmax_of(d.a) + kB - 1) / kB;
   return t_launch < tc ? t_launch : tc;
 }
 
@@ -382,7 +389,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restric
   double* __restrict__ W2p = d.W2p;
   const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows;
   const int64_t T = late ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
-  const int nsplit = w2_splits(n_rows, T);
+  const int nsplit = w2_splits(n_rows, T, gridDim.z);
   const DevScalars* sc = d.sc;
   __shared__ double Qs[2][kGK][kB + 1];   // [r][c]
   __shared__ double Ys[2][kGK][kB + 1];   // [r][j]
@@ -464,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
   double* __restrict__ W = w_of(d, b0);
   const int64_t ldw = d.a.cap;
   const int64_t T = late ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
-  const int nsplit = w2_splits(d.a.n_rows, T);
+  const int nsplit = w2_splits(d.a.n_rows, T, gridDim.z);
   const DevScalars* sc = d.sc;
   const int64_t nb = late ? late_work(d, b0) : blk_work(sc, b0, d.a.n_rows);
   const int64_t cw = late ? d.kcut[blk_par(b0)] : 0;   // first column
@@ -508,11 +515,12 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
 // need the block Gram to about u^2: rounding it to float64 alone moves the
 // Schur complement of an exactly dependent candidate to ~u * cond^2 ||x||^2,
 // which can reach eps^2 ||x||^2.
-// kGramGroups groups of kBlock threads take every kGramGroups-th row of each
-// 64-row tile (four waves per SIMD); their sums are added in group order.
-constexpr int kGramGroups = 4;
-__global__ __launch_bounds__(kBlock * kGramGroups) void k_blk_gram_dd(const BasisDev* __restrict__ bd,
-                                                                      int64_t b0) {
+// NG groups of kBlock threads take every NG-th row of each 64-row tile and
+// their sums are added in group order: four groups (four waves per SIMD) when
+// few inputs share the launch, one when many fill the GPU by themselves.
+template <int NG>
+__global__ __launch_bounds__(kBlock * NG) void k_blk_gram_dd(const BasisDev* __restrict__ bd,
+                                                             int64_t b0) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Y = y_of(d, b0);
   double* __restrict__ part_hi = d.part_hi;
@@ -531,21 +539,21 @@ __global__ __launch_bounds__(kBlock * kGramGroups) void k_blk_gram_dd(const Basi
   double hi[4][4] = {}, lo[4][4] = {};
   for (int64_t kk0 = k0; kk0 < k1; kk0 += kB) {
     __syncthreads();
-    constexpr int kLd = kB * kB / (kBlock * kGramGroups);
+    constexpr int kLd = kB * kB / (kBlock * NG);
     double v[kLd];
 #pragma unroll
     for (int u = 0; u < kLd; ++u) {
-      const int t = u * kBlock * kGramGroups + threadIdx.x, kk = t / kB, i = t % kB;
+      const int t = u * kBlock * NG + threadIdx.x, kk = t / kB, i = t % kB;
       v[u] = (kk0 + kk < k1 && i < width) ? Y[(kk0 + kk) * kB + i] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kLd; ++u) {
-      const int t = u * kBlock * kGramGroups + threadIdx.x;
+      const int t = u * kBlock * NG + threadIdx.x;
       Ys[t / kB][t % kB] = v[u];
     }
     __syncthreads();
     const int kn = (int)min((int64_t)kB, k1 - kk0);
-    for (int kk = grp; kk < kn; kk += kGramGroups) {
+    for (int kk = grp; kk < kn; kk += NG) {
       double x[4], y[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -567,7 +575,7 @@ __global__ __launch_bounds__(kBlock * kGramGroups) void k_blk_gram_dd(const Basi
   // groups 1, 2, 3 in turn park their sums in LDS and group 0 adds them
   double(*Yl)[kB + 1] = Ys;   // hi parked in Ys, lo in Yl2
   __shared__ double Yl2[kB][kB + 1];
-  for (int g = 1; g < kGramGroups; ++g) {
+  for (int g = 1; g < NG; ++g) {
     __syncthreads();
     if (grp == g) {
 #pragma unroll
@@ -1175,7 +1183,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_newm_part(const BasisDev* __restr
   }
   __syncthreads();
   if (grp == 1) return;
-  double* zp = Zp + js * ldw * kB;
+  double* zp = Zp + js * kmax_of(d.a) * kB;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int rr = rb + l / 16 + 4 * r;
@@ -1193,7 +1201,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_newm_fin(const BasisDev* __restri
   double* __restrict__ M = d.a.M;
   const double* __restrict__ Zp = d.Zp;
   const double* __restrict__ T = d.Tacc;
-  const int64_t ldm = d.a.ldm, ldw = d.a.cap;
+  const int64_t ldm = d.a.ldm;
   const DevScalars* sc = d.sc;
   constexpr int kR = 32;
   __shared__ double Zs[kR][kB + 1];
@@ -1217,6 +1225,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_newm_fin(const BasisDev* __restri
   const int64_t r0 = (int64_t)blockIdx.x * kR;
   if (r0 >= k) return;
   const int64_t js0 = r0 / jw, js1 = (k + jw - 1) / jw;
+  const int64_t zs = kmax_of(d.a) * kB;   // one split's partials
   // every partial's load issued before the sums, which run in order of js
   static_assert(kR * kB % kGemm == 0, "whole tile per pass");
 #pragma unroll
@@ -1225,7 +1234,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_newm_fin(const BasisDev* __restri
     double zv[kNewmSplits];
 #pragma unroll
     for (int q = 0; q < kNewmSplits; ++q)
-      zv[q] = (r0 + r < k && js0 + q < js1) ? Zp[(js0 + q) * ldw * kB + (r0 + r) * kB + a] : 0.0;
+      zv[q] = (r0 + r < k && js0 + q < js1) ? Zp[(js0 + q) * zs + (r0 + r) * kB + a] : 0.0;
     double z = 0.0;
 #pragma unroll
     for (int q = 0; q < kNewmSplits; ++q) z += zv[q];
@@ -1351,8 +1360,8 @@ __global__ void k_put_dev(BasisDev* __restrict__ out, BasisPack pk, int n) {
 // Room for the W2 partials at any block step of an input.
 size_t w2p_doubles(int64_t n_rows, int64_t cap) {
   size_t w2p = 0;
-  for (int64_t T = 1; T <= div_up(cap, kB); ++T)
-    w2p = std::max(w2p, (size_t)w2_splits(n_rows, T) * kB * kB * T);
+  for (int64_t T = 1; T <= div_up(std::min(cap, n_rows), kB); ++T)
+    w2p = std::max(w2p, (size_t)w2_splits(n_rows, T, 1) * kB * kB * T);
   return w2p;
 }
 
@@ -1366,7 +1375,7 @@ size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
          + 2 * kB                                   // g (two sets)
          + (size_t)2 * kB * n_rows                  // Ybuf (two sets)
          + 2                                        // kcut
-         + (size_t)newm_splits(cap) * cap * kB      // Zp
+         + (size_t)newm_splits(std::min(cap, n_rows)) * std::min(cap, n_rows) * kB   // Zp
          + 64;                                      // pos
 }
 
@@ -1403,7 +1412,7 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     d.Ybuf = d.g + 2 * kB;
     d.kcut = (int64_t*)(d.Ybuf + (size_t)2 * kB * a.n_rows);
     d.Zp = (double*)(d.kcut + 2);
-    d.pos = (int32_t*)(d.Zp + (size_t)newm_splits(a.cap) * a.cap * kB);
+    d.pos = (int32_t*)(d.Zp + (size_t)newm_splits(kmax_of(a)) * kmax_of(a) * kB);
     d.nsplit_dd = sp.dd;
     d.ntake = sp.take;
   }
@@ -1416,7 +1425,9 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
   }
   const int sums = kB * kB * kSumWays / kBlock;
   constexpr int kMaxZ = 65535;
-  const bool ahead = side && side->st;
+  // the side stream fills CUs that single-workgroup steps leave idle: with
+  // many inputs in a launch those steps fill the GPU by themselves
+  const bool ahead = side && side->st && count <= kFewInputs;
   for (int z0 = 0; z0 < count; z0 += kMaxZ) {
     const int nz_all = std::min(kMaxZ, count - z0);
     const BasisDev* bd = dd + z0;
@@ -1454,7 +1465,7 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       int w_max = 1;
       for (int i = z0; i < z0 + nz; ++i)
         w_max = std::max(w_max, w2_splits(hd[i].a.n_rows,
-                                          std::min<int64_t>(t_launch, div_up(hd[i].a.cap, kB))));
+                                          std::min<int64_t>(t_launch, div_up(kmax_of(hd[i].a), kB)), nz));
       const int par = (int)((b0 / kB) & 1);
       // first projection pass: at the first step all of it here; later, its
       // early part ran on the side stream during the previous step and the
@@ -1475,8 +1486,10 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
                          dim3(kBlock), 0, st, bd, b0, t_launch, 0);
       hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0,
                          kReproject);
-      hipLaunchKernelGGL(k_blk_gram_dd, dim3(bn.dd_max, 1, nz), dim3(kBlock * kGramGroups), 0, st,
-                         bd, b0);
+      if (nz <= kFewInputs)
+        hipLaunchKernelGGL(k_blk_gram_dd<4>, dim3(bn.dd_max, 1, nz), dim3(kBlock * 4), 0, st, bd, b0);
+      else
+        hipLaunchKernelGGL(k_blk_gram_dd<1>, dim3(bn.dd_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
       hipLaunchKernelGGL(k_blk_sum_dd, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd, b0);
       // early part of the next step's first pass, against the k columns held
       // at the start of this step (final once the previous step finished),
@@ -1501,7 +1514,8 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       if (ahead && b0 + kB < hd[z0].a.s_max) {
         const Bounds nx = bounds(b0 + kB);
         int w_late = 1;
-        for (int i = z0; i < z0 + nx.nz; ++i) w_late = std::max(w_late, w2_splits(hd[i].a.n_rows, 1));
+        for (int i = z0; i < z0 + nx.nz; ++i)
+          w_late = std::max(w_late, w2_splits(hd[i].a.n_rows, 1, nx.nz));
         (void)hipEventRecord(side->mid, st);
         (void)hipStreamWaitEvent(side->st, side->mid, 0);
         hipLaunchKernelGGL(k_blk_w2_part, dim3(1, w_late, nx.nz), dim3(kGemm), 0, side->st, bd,

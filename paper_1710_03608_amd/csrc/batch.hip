@@ -20,7 +20,9 @@ namespace ctd {
 namespace {
 constexpr int kBatchStreams = 8;
 constexpr int kMaxGroup = 4096;                      // tensors per group
-constexpr size_t kGroupBytes = size_t(64) << 30;     // workspace budget per group
+// workspace budget per group: under half of the 288 GB of HBM, so that a
+// group of hundreds of mid-sized tensors is one sequence of launches
+constexpr size_t kGroupBytes = size_t(128) << 30;
 
 #define BATCH_HIP(h, expr)                                                              \
   do {                                                                                  \
