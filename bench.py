@@ -156,6 +156,36 @@ def time_many(ctd, tensors, sizes, precision):
     return {"ms": ms, "mean_rel_err": float(sum(rel) / len(rel)), "kept_total": int(sum(kept))}
 
 
+SWEEP_S = (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000)
+
+
+def time_sweep(ctd, X, reps=5):
+    """The paper's Fig. 5 methodology: CTD-S over sample sizes s on one tensor
+    (mode 0, seed SEED, float64, C formed), reporting the error, the wall time
+    of one decomposition (mean of reps after a warm-up) and the memory usage of
+    Eq. 15 at every s."""
+    import torch
+    dims, idx, val = ctd.to_device(X, "cuda")
+    h = ctd.Ctd(precision="fp64", want_C=True)
+    out = []
+    for s in SWEEP_S:
+        h.decompose(dims, idx, val, 0, s, SEED)
+        h.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            h.decompose(dims, idx, val, 0, s, SEED)
+        h.sync()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        r = h.result(arrays=False)
+        m = h.memory_usage()
+        out.append({"s": s, "s_unique": r["s_unique"], "s_tilde": r["s_tilde"],
+                    "rel_err": r["rel_err"], "ms": ms, "memory_usage": m["usage"],
+                    "nnz_R": m["nnz_R"], "nnz_U": m["nnz_U"], "nnz_C": m["nnz_C"]})
+    h.close()
+    return out
+
+
 def calibrate_copy():
     """A plain device-to-device copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES), run
     three times, so that FETCH_SIZE / WRITE_SIZE of the same profiling pass can be scaled."""
@@ -222,6 +252,9 @@ def main():
                     help="comma-separated slices per update call for the stream leg")
     ap.add_argument("--no-many", action="store_true", help="skip the many-tensor batched leg")
     ap.add_argument("--many-only", action="store_true", help="run only the many-tensor batched leg")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the sample-size sweep (Fig. 5 methodology) on the Haggle-shaped "
+                         "tensor and print it as one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -236,6 +269,19 @@ def main():
 
     import paper_1710_03608_amd as ctd
     from workloads import synth
+
+    if args.sweep_only:
+        X = synth.small_shapes()[1]
+        torch.cuda.set_device(0)
+        log(f"sample-size sweep, {X.dims}, {X.nnz} nonzeros, s in {SWEEP_S}")
+        rows = time_sweep(ctd, X)
+        for r in rows:
+            log(f"  s={r['s']:5d} s~={r['s_tilde']:3d} rel_err={r['rel_err']:.6f} "
+                f"{r['ms']:.3f} ms usage={r['memory_usage']:.4f}")
+        print(json.dumps({"ctd_s_sweep": {
+            "workload": "haggle_shaped_77x274x1567_nnz27972_zipf1.2_mode0", "data": "synthetic",
+            "dtype": "f64", "rows": rows}}), flush=True)
+        return
 
     many_line = None
     if not args.no_many and not args.stream_only:

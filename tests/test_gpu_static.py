@@ -244,3 +244,30 @@ def test_general_order_and_mode(lib, dims, nnz, mode, s):
     if borderline(o):
         pytest.skip("candidate within rounding of the threshold")
     check_parity(g, o)
+
+
+def test_sample_size_sweep(lib):
+    """The paper's Fig. 5 methodology on the Haggle-shaped tensor (mode alpha =
+    1, s from 1 to 1000): at every s the GPU's draws, kept fibers and error
+    equal the oracle's, the error does not grow with s (nested draws), and the
+    memory usage of Eq. 15 equals the oracle's count from its own R and C."""
+    from oracle.metrics import memory_usage
+    X = synth.small_shapes()[1]
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd(precision="fp64", want_C=True)
+    prev = None
+    try:
+        for s in (1, 5, 20, 100, 400, 1000):
+            o = ora.ctd_s(X.dims, X.idx, X.val, 0, s, 3, want_C=True)
+            h.decompose(dims, idx, val, 0, s, 3)
+            g = h.result()
+            check_parity(g, o)
+            m = h.memory_usage()
+            nc, nu, nr, usage = memory_usage(o.R, o.C, X.nnz)
+            assert (m["nnz_C"], m["nnz_U"], m["nnz_R"]) == (nc, nu, nr), s
+            assert m["usage"] == pytest.approx(usage, rel=1e-15)
+            if prev is not None:
+                assert g["rel_err"] <= prev + 1e-9, (s, g["rel_err"], prev)
+            prev = g["rel_err"]
+    finally:
+        h.close()

@@ -415,3 +415,27 @@ def test_structural_U_matches_inverse_on_block_data():
     expect = int(np.count_nonzero(np.abs(U) > 1e-12 * np.abs(U).max()))
     assert structural_nnz_U(R) <= 16 + 9 + 25
     assert structural_nnz_U(R) == expect
+
+
+def test_error_nonincreasing_in_sample_size():
+    """Sample-size sweep on the Haggle-shaped tensor of Table 3 (the paper's
+    Fig. 5 methodology, mode alpha = 1, s from 1 to 1000).  Draw j depends only
+    on its Philox counter, so the draws for s1 < s2 are a prefix of those for
+    s2 and the candidate set only grows: the error, the distance of X_(alpha)
+    from the span of the kept fibers, cannot grow beyond the epsilon-skips
+    (each skipped fiber lies within eps ||x|| of the span).  The kept count is
+    bounded by rank X_(alpha), computed here from X X^T."""
+    X = synth.small_shapes()[1]
+    u = ctd.unfold(X.dims, X.idx, X.val, 0)
+    G = (u.mat @ u.mat.T).toarray()
+    rank = int(np.linalg.matrix_rank(G, tol=1e-9 * np.abs(G).max()))
+    prev_draws, prev_err = None, None
+    for s in (1, 5, 20, 100, 400, 1000):
+        o = ctd.ctd_s(X.dims, X.idx, X.val, 0, s, 3)
+        if prev_draws is not None:
+            assert np.array_equal(o.draws[:len(prev_draws)], prev_draws), s
+            assert o.rel_err <= prev_err + 1e-9, (s, o.rel_err, prev_err)
+        assert len(o.accepted) <= rank, (s, len(o.accepted), rank)
+        if len(o.accepted) == rank:   # the kept fibers span the column space
+            assert o.rel_err <= 1e-12, (s, o.rel_err)
+        prev_draws, prev_err = o.draws, o.rel_err
