@@ -186,6 +186,46 @@ def time_sweep(ctd, X, reps=5):
     return out
 
 
+SPARSE_S = 200
+
+
+def time_sparse_core(ctd, X, reps=3):
+    """ctd_sparse_core on the 5M traffic tensor after CTD-S with s = SPARSE_S:
+    wall time of one call (both passes, scans and workspace), nnz(C), and the
+    algorithmic work 2 sum_i deg_R(i) deg_X(i) flops of the SpGEMM R^T X."""
+    import numpy as np
+    import torch
+    dims, idx, val = ctd.to_device(X, "cuda")
+    h = ctd.Ctd(precision="fp64")
+    h.decompose(dims, idx, val, 0, SPARSE_S, SEED)
+    r = h.result()
+    f = X.idx[1].astype(np.int64) + X.idx[2].astype(np.int64) * X.dims[1]
+    rows = X.idx[0].astype(np.int64)
+    kept = np.isin(f, r["accepted"].astype(np.int64))
+    deg_x = np.bincount(rows, minlength=X.dims[0]).astype(np.float64)
+    deg_r = np.bincount(rows[kept], minlength=X.dims[0]).astype(np.float64)
+    pairs = float((deg_x * deg_r).sum())
+    col_ptr, row_idx, vals = h.sparse_core()   # sizes the arrays, warms up
+    nnz = int(col_ptr[-1])
+    cp = torch.empty(r["n_f"] + 1, dtype=torch.int64, device="cuda")
+    ri = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+    vv = torch.empty(max(nnz, 1), dtype=torch.float64, device="cuda")
+    import ctypes
+    n = ctypes.c_int64(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        h._check(h.lib.ctd_sparse_core(h.h, cp.data_ptr(), ri.data_ptr(), vv.data_ptr(), nnz,
+                                       ctypes.byref(n)))
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    h.close()
+    return {"workload": "ctd_s_traffic_10000x10000x1000_nnz5000000_zipf1.2_s200_sparse_C",
+            "s": SPARSE_S, "s_tilde": int(r["s_tilde"]), "n_f": int(r["n_f"]), "nnz_C": nnz,
+            "nnz_R": int(kept.sum()), "pairs": pairs, "ms": ms,
+            "gflops_algorithmic": 2 * pairs / (ms * 1e-3) / 1e9,
+            "output_GBps": nnz * 12 / (ms * 1e-3) / 1e9}
+
+
 def calibrate_copy():
     """A plain device-to-device copy of COPY_BYTES (read COPY_BYTES, write COPY_BYTES), run
     three times, so that FETCH_SIZE / WRITE_SIZE of the same profiling pass can be scaled."""
@@ -252,6 +292,8 @@ def main():
                     help="comma-separated slices per update call for the stream leg")
     ap.add_argument("--no-many", action="store_true", help="skip the many-tensor batched leg")
     ap.add_argument("--many-only", action="store_true", help="run only the many-tensor batched leg")
+    ap.add_argument("--sparse-only", action="store_true",
+                    help="run only the sparse C leg (ctd_sparse_core on the 5M tensor, s = 200)")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the sample-size sweep (Fig. 5 methodology) on the Haggle-shaped "
                          "tensor and print it as one JSON line")
@@ -269,6 +311,15 @@ def main():
 
     import paper_1710_03608_amd as ctd
     from workloads import synth
+
+    if args.sparse_only:
+        X = synth.traffic_5m()
+        torch.cuda.set_device(0)
+        r = time_sparse_core(ctd, X)
+        log(f"sparse C: {r['nnz_C']} entries, {r['ms']:.2f} ms, {r['gflops_algorithmic']:.1f} "
+            f"GFLOP/s algorithmic, {r['output_GBps']:.1f} GB/s written")
+        print(json.dumps({"ctd_s_sparse_core": r}), flush=True)
+        return
 
     if args.sweep_only:
         X = synth.small_shapes()[1]

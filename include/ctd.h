@@ -227,6 +227,27 @@ typedef struct {
 } ctd_memory;
 ctd_status ctd_memory_usage(ctd_handle* h, ctd_memory* out);
 
+/* The factor C_(alpha) = R^T X_(alpha) of Algorithm 1 as a sparse matrix (the
+ * sparse output of C whose nonzeros Eq. 15 counts).  R's columns are actual
+ * fibers, so entry (a, f) can be nonzero only where kept fiber a and fiber f
+ * share a row.  Compressed-column form over the n_f non-empty fibers of the
+ * last ctd_decompose, in the order of the dense C (ascending fiber id): column
+ * f holds its entries at [col_ptr[f], col_ptr[f + 1]) with row indices a (the
+ * kept fiber's position in R's order) increasing; only entries whose computed
+ * value is nonzero are stored, each summed over the fiber's nonzeros in fiber
+ * order (deterministic).  col_ptr: device int64[n_f + 1], written always;
+ * row_idx: device int32[cap] and vals: device float64[cap], written only when
+ * nnz(C) <= cap (they may be NULL when cap == 0).  *nnz_out receives nnz(C)
+ * in every case; nnz(C) > cap returns CTD_ERR_CAPACITY, so a caller can size
+ * the arrays from a first call with cap = 0.  Needs the dense R of a CTD-S
+ * handle after ctd_decompose (after ctd_update, CTD_ERR_STATE: the CTD-D C
+ * is a projection, not R^T X) and s~ <= 8192 (else CTD_ERR_CAPACITY: one
+ * column's accumulator lives in 64 KiB of LDS).  Waits for the handle's
+ * stream; allocates and frees a workspace of (I_alpha + 1) int64 and nnz(R)
+ * (int32, float64) pairs per call. */
+ctd_status ctd_sparse_core(ctd_handle* h, int64_t* col_ptr, int32_t* row_idx, double* vals,
+                        int64_t cap, int64_t* nnz_out);
+
 /* Wait for the stream and return the latched device status. */
 ctd_status ctd_sync(ctd_handle* h);
 

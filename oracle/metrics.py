@@ -42,3 +42,16 @@ def memory_usage(R, C, nnz_X):
     nnz_C = int(C.count_nonzero()) if hasattr(C, "count_nonzero") else int(np.count_nonzero(C))
     nnz_U = structural_nnz_U(R)
     return nnz_C, nnz_U, nnz_R, (nnz_C + nnz_U + nnz_R) / nnz_X
+
+
+def sparse_core(R, u):
+    """C_(alpha) = R^T X_(alpha) (the last step of Algorithm 1) as a sparse
+    matrix over the non-empty fibers of the unfolding `u` (u.mat, columns in
+    ascending fiber id): compressed-column (indptr, indices, data) with row
+    indices ascending in each column and entries whose value is exactly zero
+    dropped.  The product is scipy's sparse matrix product."""
+    import scipy.sparse as sp
+    C = (sp.csr_matrix(np.asarray(R)).T @ u.mat).tocsc()
+    C.eliminate_zeros()
+    C.sort_indices()
+    return C.indptr.astype(np.int64), C.indices.astype(np.int32), C.data.astype(np.float64)

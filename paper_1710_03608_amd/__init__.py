@@ -20,10 +20,11 @@ CTD_PREC_FP64, CTD_PREC_MIXED = 0, 1
 STATUS = {0: "CTD_OK", 1: "CTD_ERR_INVALID_ARG", 2: "CTD_ERR_EMPTY", 3: "CTD_ERR_INDEX_OOB",
           4: "CTD_ERR_DUPLICATE", 5: "CTD_ERR_NONFINITE", 6: "CTD_ERR_OOM", 7: "CTD_ERR_HIP",
           8: "CTD_ERR_STATE", 9: "CTD_ERR_CAPACITY"}
+CTD_ERR_CAPACITY = 9
 EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
            "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result", "ctd_sync",
            "ctd_get_result", "ctd_last_error", "ctd_destroy", "ctd_attack_candidates",
-           "ctd_memory_usage")
+           "ctd_memory_usage", "ctd_sparse_core")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -94,9 +95,11 @@ def load_library():
     lib.ctd_attack_candidates.argtypes = [c_vp, c_i32, c_vp, c_vp, c_i64,
                                           ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     lib.ctd_memory_usage.argtypes = [c_vp, ctypes.POINTER(MemoryStruct)]
+    lib.ctd_sparse_core.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]
     for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
                  "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
-                 "ctd_sync", "ctd_get_result", "ctd_attack_candidates", "ctd_memory_usage"):
+                 "ctd_sync", "ctd_get_result", "ctd_attack_candidates", "ctd_memory_usage",
+                 "ctd_sparse_core"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -252,6 +255,23 @@ class Ctd:
 
     def sync(self):
         self._check(self.lib.ctd_sync(self.h))
+
+    def sparse_core(self):
+        """C_(alpha) = R^T X_(alpha) in compressed-column form (col_ptr, row_idx,
+        vals as numpy arrays); device buffers sized from a first call with cap 0."""
+        import torch
+        n_f = self.result(arrays=False)["n_f"]
+        col_ptr = torch.empty(n_f + 1, dtype=torch.int64, device="cuda")
+        nnz = c_i64(0)
+        rc = self.lib.ctd_sparse_core(self.h, col_ptr.data_ptr(), None, None, 0, ctypes.byref(nnz))
+        if rc != CTD_ERR_CAPACITY or nnz.value == 0:
+            self._check(rc)
+        row_idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        vals = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
+        self._check(self.lib.ctd_sparse_core(self.h, col_ptr.data_ptr(), row_idx.data_ptr(),
+                                          vals.data_ptr(), nnz.value, ctypes.byref(nnz)))
+        n = nnz.value
+        return (col_ptr.cpu().numpy(), row_idx[:n].cpu().numpy(), vals[:n].cpu().numpy())
 
     def memory_usage(self):
         """Eq. 15: nnz of C, U (structural) and R, nnz of the input, and the ratio."""

@@ -21,7 +21,7 @@ def test_header_declares_the_boundary():
     assert names == sorted(["ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
                             "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
                             "ctd_sync", "ctd_get_result", "ctd_last_error", "ctd_destroy",
-                            "ctd_attack_candidates", "ctd_memory_usage"])
+                            "ctd_attack_candidates", "ctd_memory_usage", "ctd_sparse_core"])
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libctd.so not built")
@@ -45,3 +45,4 @@ def test_binding_struct_layout_matches_exports():
     assert lib.ctd_get_batch_result(None, 0, None) == 1
     assert lib.ctd_attack_candidates(None, 1, None, None, 0, None, None) == 1
     assert lib.ctd_memory_usage(None, None) == 1
+    assert lib.ctd_sparse_core(None, None, None, None, 0, None) == 1

@@ -138,3 +138,56 @@ def test_memory_usage_ctd_d(lib):
     nc, nu, nr, usage = memory_usage(o.R, o.C, total)
     assert (m["nnz_U"], m["nnz_R"], m["nnz_X"]) == (nu, nr, total)
     assert m["nnz_C"] == nc
+
+
+@pytest.mark.parametrize("which,precision", [("power", "fp64"), ("haggle", "mixed")])
+def test_sparse_core_matches_oracle(lib, which, precision):
+    """C_(alpha) = R^T X_(alpha) in compressed-column form (ctd_sparse_core)
+    against the oracle's sparse product from its own R: same column pointers
+    and row indices (positive values, so no entry cancels), values to
+    rounding, and as many entries as Eq. 15 counts in the dense C."""
+    import ctypes
+    import torch
+    from oracle.metrics import sparse_core
+    if which == "power":
+        X, s = synth.power_law_tensor((300, 400, 30), 20000, 9, zipf_a=1.2), 300
+    else:
+        X, s = synth.small_shapes()[1], 400
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, s, 4)
+    indptr, indices, data = sparse_core(o.R, ora.unfold(X.dims, X.idx, X.val, 0))
+    dims, idx, val = lib.to_device(X, "cuda")
+    h = lib.Ctd(precision=precision, want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, s, 4)
+        assert np.array_equal(h.result()["accepted"], o.accepted.astype(np.uint64))
+        col_ptr, row_idx, vals = h.sparse_core()
+        m = h.memory_usage()
+        # too small a cap: the count comes back with CTD_ERR_CAPACITY, nothing else written
+        cp = torch.empty(col_ptr.shape[0], dtype=torch.int64, device="cuda")
+        nnz = ctypes.c_int64(-1)
+        rc = h.lib.ctd_sparse_core(h.h, cp.data_ptr(), None, None, 0, ctypes.byref(nnz))
+        assert rc == lib.CTD_ERR_CAPACITY and nnz.value == len(row_idx)
+        assert np.array_equal(cp.cpu().numpy(), col_ptr)
+    finally:
+        h.close()
+    assert np.array_equal(col_ptr, indptr)
+    assert np.array_equal(row_idx, indices)
+    np.testing.assert_allclose(vals, data, rtol=1e-13, atol=0)
+    assert m["nnz_C"] == len(row_idx)
+
+
+def test_sparse_core_needs_a_static_decomposition(lib):
+    """After a CTD-D update the held C is a projection, not R^T X: state error."""
+    st = synth.traffic_stream(dims=(40, 30, 8), nnz0=800, n_slices=1, slice_nnz=(50, 100),
+                              zipf_a=1.1, n_anomalies=0, block=4, seed=2)
+    dims, idx, val = lib.to_device(st.initial, "cuda")
+    h = lib.Ctd(precision="fp64", want_C=True)
+    try:
+        h.decompose(dims, idx, val, 0, 30, 1)
+        h.sparse_core()
+        sd, si, sv = lib.to_device(st.slices[0], "cuda")
+        h.update(sd, si, sv, 4)
+        with pytest.raises(lib.CtdError):
+            h.sparse_core()
+    finally:
+        h.close()

@@ -439,3 +439,22 @@ def test_error_nonincreasing_in_sample_size():
         if len(o.accepted) == rank:   # the kept fibers span the column space
             assert o.rel_err <= 1e-12, (s, o.rel_err)
         prev_draws, prev_err = o.draws, o.rel_err
+
+
+def test_sparse_core_worked_example():
+    """The sparse C of the Eq. 15 worked example, by hand: R's fibers a (rows
+    0, 1; values 1, 2), b (rows 1, 2; values 3, 1), c (row 5; value 4);
+    X's columns e0, e2, e4 and e1 + e5.  C = R^T X has column 0 = (1, 0, 0),
+    column 1 = (0, 1, 0), column 2 empty (row 4 meets no kept fiber) and
+    column 3 = (2, 3, 4)."""
+    from oracle.metrics import sparse_core
+    R = np.zeros((6, 3))
+    R[[0, 1], 0] = [1.0, 2.0]
+    R[[1, 2], 1] = [3.0, 1.0]
+    R[5, 2] = 4.0
+    idx = np.array([[0, 2, 4, 1, 5], [0, 1, 2, 3, 3]], dtype=np.int32)
+    u = ctd.unfold((6, 4), idx, np.ones(5), 0)
+    indptr, indices, data = sparse_core(R, u)
+    assert indptr.tolist() == [0, 1, 2, 2, 5]
+    assert indices.tolist() == [0, 1, 0, 1, 2]
+    assert data.tolist() == [1.0, 1.0, 2.0, 3.0, 4.0]
