@@ -18,6 +18,12 @@
 // columns of M are M[:k, new] = -M W_A^T T and M[new, new] = T, T being the
 // product of the inverse transposed Cholesky factors.  Sizes are read on the
 // device, so one block is a fixed sequence of launches.
+//
+// For few inputs the first pass of the next block runs on a second stream:
+// its part against the columns already final while this block decides, its
+// part against this block's new columns (coefficients Q_new^T Y, equal to
+// Q_new^T x to working accuracy and exactly what is subtracted) while M and
+// the book-keeping finish.  Consecutive blocks use two sets of W, g and Y.
 #include <algorithm>
 #include <vector>
 
