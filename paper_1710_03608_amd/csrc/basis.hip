@@ -1387,6 +1387,16 @@ size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
 
 size_t basis_dev_bytes(int count) { return (size_t)std::max(count, 1) * sizeof(BasisDev); }
 
+// Orders later work on `waiter` after the work enqueued so far on `signaler`
+// (event record and wait); if either call fails, waits for `signaler` on the
+// host instead, which orders the same work.
+static void order_after(hipStream_t waiter, hipStream_t signaler, hipEvent_t ev) {
+  if (hipEventRecord(ev, signaler) == hipSuccess && hipStreamWaitEvent(waiter, ev, 0) == hipSuccess)
+    return;
+  (void)hipGetLastError();
+  (void)hipStreamSynchronize(signaler);
+}
+
 void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs, int count,
                   void* dev, BasisSide* side) {
   if (count <= 0) return;
@@ -1460,6 +1470,7 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     };
     const dim3 wthreads(kWWaves * kWave);
     hipLaunchKernelGGL(k_begin_basis, dim3(1, 1, nz_all), dim3(1), 0, st, bd);
+    bool done_ok[2] = {true, true};
     for (int64_t b0 = 0; b0 < hd[z0].a.s_max; b0 += kB) {
       const Bounds bn = bounds(b0);
       const int nz = bn.nz;
@@ -1477,7 +1488,11 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       // early part ran on the side stream during the previous step and the
       // late part (the previous step's new columns) follows here
       if (ahead && b0 > 0) {
-        (void)hipStreamWaitEvent(st, side->done[par], 0);   // both parts ran on the side
+        // both parts ran on the side; a failed record or wait falls back to the host
+        if (!done_ok[par] || hipStreamWaitEvent(st, side->done[par], 0) != hipSuccess) {
+          (void)hipGetLastError();
+          (void)hipStreamSynchronize(side->st);
+        }
       } else {
         hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nz), wthreads, 0, st, bd, b0,
                            (int)kPassAll);
@@ -1503,8 +1518,7 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       // the other set of W, g and Ybuf
       if (ahead && b0 + kB < hd[z0].a.s_max) {
         const Bounds nx = bounds(b0 + kB);
-        (void)hipEventRecord(side->start, st);
-        (void)hipStreamWaitEvent(side->st, side->start, 0);
+        order_after(side->st, st, side->start);
         hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nx.nz), wthreads, 0, side->st, bd,
                            b0 + kB, (int)kPassEarly);
         hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0,
@@ -1522,15 +1536,15 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
         int w_late = 1;
         for (int i = z0; i < z0 + nx.nz; ++i)
           w_late = std::max(w_late, w2_splits(hd[i].a.n_rows, 1, nx.nz));
-        (void)hipEventRecord(side->mid, st);
-        (void)hipStreamWaitEvent(side->st, side->mid, 0);
+        order_after(side->st, st, side->mid);
         hipLaunchKernelGGL(k_blk_w2_part, dim3(1, w_late, nx.nz), dim3(kGemm), 0, side->st, bd,
                            b0 + kB, (int64_t)1, 1);
         hipLaunchKernelGGL(k_blk_w2_sum, dim3(div_up((int64_t)kB * kB, kW2Per), 1, nx.nz),
                            dim3(kBlock), 0, side->st, bd, b0 + kB, (int64_t)1, 1);
         hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0,
                            side->st, bd, b0 + kB, (int)kPassLate);
-        (void)hipEventRecord(side->done[1 - par], side->st);
+        done_ok[1 - par] = hipEventRecord(side->done[1 - par], side->st) == hipSuccess;
+        if (!done_ok[1 - par]) (void)hipGetLastError();
       }
       const int64_t jw = newm_jw(k1);
       hipLaunchKernelGGL(k_blk_newm_part, dim3(div_up(k1, 32), div_up(k1, jw), nz), dim3(kGemm), 0,
