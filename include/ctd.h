@@ -180,7 +180,9 @@ ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B, i
 /* Many independent tensors in one call (the batched execution form of
  * CTD-S): tensor b of the host array Xs[0..B) gets Algorithm 1 with s[b]
  * draws in mode `mode`, its draws using Philox counter word tensor = b
- * (tensor 0 reproduces ctd_decompose).  Tensors go in groups within a
+ * (tensor 0 has the draws and kept fibers of ctd_decompose, its floating-point
+ * results equal to rounding: how a launch splits its reductions depends on how
+ * many tensors share it).  Tensors go in groups within a
  * workspace budget (128 GiB): the per-tensor stages run concurrently on internal
  * streams of default priority, and the independence filter and basis of a
  * whole group run as one sequence of launches on the handle's stream.  All
