@@ -108,11 +108,12 @@ def time_stream(ctd, st, precision, batch=1):
     return out
 
 
-def stream_cross_roofline(ctd, st, precision, n_slices=60):
-    """HBM roofline of the CTD-D cross term (Eq. 13), unbatched: per slice that keeps
-    fibers, one pass reads the d~_t x n_cols_t block of C held before the slice and
-    writes the new rows over those columns.  Algorithmic bytes / the cross-term stage
-    time (HIP events on the library's stream), over the first n_slices slices."""
+def stream_cross_roofline(ctd, st, precision, n_slices=64, batch=1):
+    """HBM roofline of the CTD-D cross term (Eq. 13): per update (one slice, or a
+    batch of slices) that keeps fibers, one pass reads the d~_t x n_cols_t block of C
+    held before it and writes the new rows over those columns.  Algorithmic bytes / the
+    cross-term stage time (HIP events on the library's stream), over the first n_slices
+    slices."""
     dims0, idx0, val0 = ctd.to_device(st.initial, "cuda")
     slices = [ctd.to_device(sl, "cuda") for sl in st.slices[:n_slices]]
     h = ctd.Ctd(precision=precision, want_C=True, profile=True)
@@ -121,8 +122,11 @@ def stream_cross_roofline(ctd, st, precision, n_slices=60):
     width = 8 if precision == "fp64" else 4
     k0, n0 = r["s_tilde"], r["n_cols"]
     nbytes, ms, passes = 0, 0.0, 0
-    for sd, si, sv in slices:
-        h.update(sd, si, sv, STREAM_D)
+    for i in range(0, len(slices), batch):
+        if batch == 1:
+            h.update(*slices[i], STREAM_D)
+        else:
+            h.update_batched(slices[i:i + batch], STREAM_D)
         r = h.result(arrays=False)
         k1, n1 = r["s_tilde"], r["n_cols"]
         if k1 > k0:
@@ -134,7 +138,8 @@ def stream_cross_roofline(ctd, st, precision, n_slices=60):
     gbps = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     return {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM, "unit": "GB/s",
             "frac": gbps / PEAK_HBM, "kernel": "k_cross_term (float64) / k_cross_term32 (float32 C)",
-            "sample": f"first {len(slices)} slices unbatched, {passes} cross-term passes, "
+            "sample": f"first {len(slices)} slices, " + ("unbatched" if batch == 1 else
+                      f"in batches of {batch}") + f", {passes} cross-term passes, "
                       f"{nbytes / 1e9:.1f} GB read and written"}
 
 
@@ -370,10 +375,9 @@ def main():
                 log(f"CTD-D stream, {key}")
                 r = time_stream(ctd, st, mode, batch)
                 r["batch"] = batch
-                if batch == 1:
-                    r["cross_term_roofline"] = stream_cross_roofline(ctd, st, mode)
-                    log(f"  cross term: {r['cross_term_roofline']['achieved']:.0f} GB/s "
-                        f"({100 * r['cross_term_roofline']['frac']:.1f}% of HBM)")
+                r["cross_term_roofline"] = stream_cross_roofline(ctd, st, mode, batch=batch)
+                log(f"  cross term: {r['cross_term_roofline']['achieved']:.0f} GB/s "
+                    f"({100 * r['cross_term_roofline']['frac']:.1f}% of HBM)")
                 r["slice_nnz_per_s"] = slice_nnz / (r["slices_ms"] * 1e-3)
                 r["slices_per_s"] = len(st.slices) / (r["slices_ms"] * 1e-3)
                 stream_line["modes"][key] = r

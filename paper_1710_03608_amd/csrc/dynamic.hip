@@ -442,6 +442,149 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term32(float* __restrict__
   }
 }
 
+// The float32 product for more than 16 new rows (batches of slices), which
+// the float32 MFMA rate bounds, on bfloat16 MFMAs (v_mfma_f32_16x16x32_bf16,
+// float32 accumulation).  Each float32 operand is split into three bfloat16
+// parts x ~ hi + mid + lo (each the rounded remainder of the ones before it;
+// the remainders are exact in float32, and the three parts carry x to about
+// 2^-24 relative).  Of the nine partial products the six of relative size
+// 2^-16 or more (mid mid, lo hi, hi lo, mid hi, hi mid, hi hi, added in that
+// order) are taken, so a product keeps about float32 accuracy; the six 16 x
+// 16 x 32 MFMAs of a 32-row chunk take about 3/8 of the cycles of the eight
+// 16 x 16 x 4 float32 MFMAs they replace.  The splitting costs vector-ALU work
+// per element of C, so for the few new rows of a single slice, where HBM
+// bounds the pass, the float32 form above stays.  A chunk is 32 rows of C:
+// lane (i, g) reads rows k0 + 8 g .. + 8 of its column (32 bytes) as the B
+// operand as laid out (no permutation); Y is rounded to float32 and split as
+// it is staged in LDS.  Lane l holds D[4 (l / 16) + r][l % 16] of a 16 x 16
+// float32 tile.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+struct Split3 {
+  bf8 hi, mid, lo;
+};
+__device__ inline Split3 split3(const float* x) {
+  Split3 s;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 h = (__bf16)x[j];
+    const float r1 = x[j] - (float)h;
+    const __bf16 m = (__bf16)r1;
+    const float r2 = r1 - (float)m;
+    s.hi[j] = h;
+    s.mid[j] = m;
+    s.lo[j] = (__bf16)r2;
+  }
+  return s;
+}
+template <int RT>
+__global__ __launch_bounds__(kCrossCols) void k_cross_term_bf3(float* __restrict__ C, int64_t ldc,
+                                                             const double* __restrict__ Yall,
+                                                             int64_t ldy, int64_t ystride,
+                                                             const int64_t* rng_all) {
+  typedef float flt4 __attribute__((ext_vector_type(4)));
+  typedef float flt8 __attribute__((ext_vector_type(8)));
+  constexpr int kRows = 16 * RT;
+  __shared__ Split3 Ys[2][kRows][5];   // [buf][row a][g]: Y[a][k0 + 8 g .. + 8] split, padded
+  const int64_t* rng = rng_all + 5 * blockIdx.y;
+  const double* Y = Yall + blockIdx.y * ystride;
+  const int64_t d = rng[0], na = rng[2], ncols = rng[4];
+  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
+  if (na <= 0 || f0 >= ncols) return;
+  const int t = threadIdx.x, w = t / kWave, l = lane_id(), i = l % 16, g = l / 16;
+  const int64_t nch = (d + 31) / 32;
+  const float* cp[4];
+  bool cin[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int64_t f = f0 + 64 * w + 16 * ct + i;
+    cin[ct] = f < ncols;
+    cp[ct] = C + (cin[ct] ? f : f0) * ldc + 8 * g;
+  }
+  const int yr = t / 4, yg = t % 4;
+  auto mask8 = [&](flt8 v, int64_t k) -> flt8 {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = k + e < d ? v[e] : 0.0f;
+    return v;
+  };
+  for (int64_t a0 = 0; a0 < na; a0 += kRows) {
+    const int nr = (int)min<int64_t>(kRows, na - a0);
+    const bool yin = yr < nr;
+    const double* yrow = Y + (a0 + (yin ? yr : 0)) * ldy + 8 * yg;
+    flt4 acc[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = flt4{0, 0, 0, 0};
+    flt8 cf[4], yv;
+    auto load = [&](int64_t ch) {
+      const int64_t k = ch * 32 + 8 * g;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const flt8*)(cp[ct] + ch * 32)
+                                                 : flt8{0, 0, 0, 0, 0, 0, 0, 0};
+        cf[ct] = mask8(cf[ct], k);
+      }
+      const int64_t ky = ch * 32 + 8 * yg;
+      dbl4 ya = {0, 0, 0, 0}, yb = {0, 0, 0, 0};
+      if (ch < nch && yin && ky < d) {
+        ya = *(const dbl4*)(yrow + ch * 32);
+        yb = *(const dbl4*)(yrow + ch * 32 + 4);
+      }
+      yv = mask8(flt8{(float)ya[0], (float)ya[1], (float)ya[2], (float)ya[3],
+                      (float)yb[0], (float)yb[1], (float)yb[2], (float)yb[3]}, ky);
+    };
+    load(0);
+    int buf = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      if (yr < kRows) {
+        float yf[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) yf[e] = yv[e];
+        Ys[buf][yr][yg] = split3(yf);
+      }
+      Split3 cs[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        float cf8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cf8[e] = cf[ct][e];
+        cs[ct] = split3(cf8);
+      }
+      __syncthreads();
+      load(ch + 1);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const Split3 ya = Ys[buf][rt * 16 + i][g];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          flt4 c = acc[rt][ct];
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.mid, cs[ct].mid, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.lo, cs[ct].hi, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.hi, cs[ct].lo, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.mid, cs[ct].hi, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.hi, cs[ct].mid, c, 0, 0, 0);
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.hi, cs[ct].hi, c, 0, 0, 0);
+        }
+      }
+      buf ^= 1;
+    }
+    // lane (i, g) holds D[4 g + r][i] of tile (rt, ct): new row rt * 16 + 4 g + r, column ct * 16 + i
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (!cin[ct]) continue;
+      float* col = C + (f0 + 64 * w + 16 * ct + i) * ldc + d + a0;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = rt * 16 + 4 * g + r;
+          if (a < nr) col[a] = acc[rt][ct][r];
+        }
+    }
+    __syncthreads();   // the next row block reuses Ys
+  }
+}
+
 // dst[f * ldd + k] = (float)src[f * lds + k] for k < rows, f < cols (a
 // column-major float64 block converted to float32).
 __global__ __launch_bounds__(kBlock) void k_cols_to_f32(const double* __restrict__ src,
@@ -955,7 +1098,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
         hipLaunchKernelGGL((k_cross_term32<1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
                            S.capD, Y, S.capD, ystride, rng);
       else
-        hipLaunchKernelGGL((k_cross_term32<4>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
+        hipLaunchKernelGGL((k_cross_term_bf3<4>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
                            S.capD, Y, S.capD, ystride, rng);
     } else if (tiles > 0) {
       if (kept_max <= 16)

@@ -196,11 +196,12 @@ def test_four_way_stream_matches_oracle(lib):
         h.close()
 
 
-@pytest.mark.parametrize("B", [1, 4])
+@pytest.mark.parametrize("B", [1, 4, 8])
 def test_mixed_core_held_in_float32(lib, B):
     """A mixed-precision handle holds the CTD-D C in float32 (new columns and the
-    cross term on float32 MFMAs): the same kept fibers as float64, and C within
-    float32 rounding amplified by the conditioning of R."""
+    cross term on float32 MFMAs; batches of more than 16 new rows on bfloat16
+    MFMAs with three-part operands): the same kept fibers as float64, and C
+    within float32 rounding amplified by the conditioning of R."""
     st = _stream(5, dims=(60, 50, 12), n_slices=8)
     _, ref = _run(lib, st, 50, 8, 5)
     dims, idx, val = lib.to_device(st.initial, "cuda")
