@@ -1502,9 +1502,11 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       // second projection against Q (block classical Gram-Schmidt, twice)
       hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(k1, kB), w_max, nz), dim3(kGemm), 0, st, bd, b0,
                          t_launch, 0);
-      hipLaunchKernelGGL(k_blk_w2_sum,
-                         dim3(std::max(1, std::min(4096, div_up((int64_t)kB * k1, kW2Per))), 1, nz),
-                         dim3(kBlock), 0, st, bd, b0, t_launch, 0);
+      // (workgroups loop over their entries: with many inputs a few per input suffice)
+      const int sum_grid = std::max(1, std::min({4096, div_up((int64_t)kB * k1, kW2Per),
+                                                 std::max(8, 65536 / nz)}));
+      hipLaunchKernelGGL(k_blk_w2_sum, dim3(sum_grid, 1, nz), dim3(kBlock), 0, st, bd, b0, t_launch,
+                         0);
       hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0,
                          kReproject);
       if (nz <= kFewInputs)
@@ -1546,7 +1548,8 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
         done_ok[1 - par] = hipEventRecord(side->done[1 - par], side->st) == hipSuccess;
         if (!done_ok[1 - par]) (void)hipGetLastError();
       }
-      const int64_t jw = newm_jw(k1);
+      // M's new columns: split over j for few inputs, whole for many
+      const int64_t jw = nz <= kFewInputs ? newm_jw(k1) : std::max<int64_t>(k1, kNewmJMin);
       hipLaunchKernelGGL(k_blk_newm_part, dim3(div_up(k1, 32), div_up(k1, jw), nz), dim3(kGemm), 0,
                          st, bd, b0, jw);
       hipLaunchKernelGGL(k_blk_newm_fin, dim3(div_up(k1, 32), 1, nz), dim3(kGemm), 0, st, bd, jw);
