@@ -1484,9 +1484,10 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
         w_max = std::max(w_max, w2_splits(hd[i].a.n_rows,
                                           std::min<int64_t>(t_launch, div_up(kmax_of(hd[i].a), kB)), nz));
       const int par = (int)((b0 / kB) & 1);
-      // first projection pass: at the first step all of it here; later, its
-      // early part ran on the side stream during the previous step and the
-      // late part (the previous step's new columns) follows here
+      // first projection pass: at the first step (or without the side
+      // stream) all of it here; later both its parts ran on the side stream
+      // during the previous step (early: the columns then final; late: that
+      // step's new columns), and this step waits for them
       if (ahead && b0 > 0) {
         // both parts ran on the side; a failed record or wait falls back to the host
         if (!done_ok[par] || hipStreamWaitEvent(st, side->done[par], 0) != hipSuccess) {
