@@ -11,10 +11,10 @@ high halves with the other two counter words and the two key words, and
 permutes the words; between rounds the key is advanced by two Weyl
 increments (the golden ratio and sqrt(3)-1 scaled to 32 bits).
 
-Parity with the published generator's known-answer vectors is UNPINNED here
-(the vectors are not available offline); the statistical properties the
-decomposition relies on (uniformity, independence across counters) are pinned
-in tests/test_oracle_philox.py.
+Pinned in tests/test_oracle_philox.py against the three known-answer cases
+published with the generator (tests/golden/philox4x32_10_kat.json), and for
+the statistical properties the decomposition relies on (uniformity,
+independence across counters).
 """
 from __future__ import annotations
 

@@ -1,10 +1,24 @@
-"""Statistical pins of the oracle's Philox4x32-10 (the generator's known-answer
-vectors are not available offline, so its exact identity is parity-unpinned)."""
+"""Pins of the oracle's Philox4x32-10: the generator's published known-answer
+values (tests/golden/philox4x32_10_kat.json), and statistical checks."""
+import json
 import math
+import os
 
 import numpy as np
 
 from oracle.philox import philox4x32_10, draw_u128
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_known_answer_values():
+    """The three known-answer cases published with Philox4x32-10 (SC'11):
+    zero counter and key, all-ones counter and key, and the digits of pi."""
+    kat = json.load(open(os.path.join(GOLDEN, "philox4x32_10_kat.json")))
+    for case in kat["cases"]:
+        c = [int(x, 16) for x in case["counter"]]
+        k = [int(x, 16) for x in case["key"]]
+        assert [f"{w:08x}" for w in philox4x32_10(c, k)] == case["out"]
 
 
 def test_outputs_uniform_over_counters():
