@@ -853,6 +853,129 @@ __device__ uint64_t wg_chol_inv(const LdsMat& Ah, const LdsMat* Al, LdsMat& X, d
   return mask;
 }
 
+// The value of lane `src` (wave-uniform) in every lane.
+__device__ inline double bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// Double-double Cholesky with drop of the leading n x n block of (Ah, Al)
+// (lower triangle, kChol threads), blocked by panels of kPanel columns: wave
+// 0 factors a panel on its own (lane i holds row i of the panel's columns;
+// the pivot and L[c][j] come from their lanes by readlane, so a panel's steps
+// need no barrier), then all waves subtract the panel's rank-kPanel product
+// from the trailing columns (wave w: columns w + 16 q, lane i: row i), two
+// barriers per panel instead of one per column.  Candidate j is kept iff
+// its Schur pivot exceeds eps2 * gs[j] and fewer than `room` are kept so far;
+// a dropped candidate's column of L is zero.  L replaces (Ah, Al) in place;
+// returns the kept mask (same in every thread).
+constexpr int kPanel = 8;
+__device__ uint64_t wg_chol_drop_blocked(LdsMat& Ah, LdsMat& Al, const double* gs, int n,
+                                         double eps2, int64_t room, uint64_t* s_mask) {
+  constexpr int kWaves = kChol / kWave;
+  const int w = threadIdx.x / kWave, i = lane_id();
+  uint64_t mask = 0;   // wave 0's
+  int kept = 0;
+  for (int c0 = 0; c0 < n; c0 += kPanel) {
+    if (w == 0) {
+      double h[kPanel], l[kPanel];
+#pragma unroll
+      for (int cc = 0; cc < kPanel; ++cc) {
+        const int c = c0 + cc;
+        const bool in = c < n && i >= c && i < n;
+        h[cc] = in ? Ah[i][c] : 0.0;
+        l[cc] = in ? Al[i][c] : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < kPanel; ++jj) {
+        const int j = c0 + jj;
+        if (j >= n) break;
+        const double dh = bcast(h[jj], j), dl = bcast(l[jj], j);
+        const bool keep = ((dh - eps2 * gs[j]) + dl > 0.0) && kept < room;
+        if (keep) {
+          double rh, rl;
+          dd_rsqrt(dh, dl, rh, rl);
+          if (i >= j && i < n) dd_mul(h[jj], l[jj], rh, rl);   // L[i][j], L[j][j] = sqrt(pivot)
+#pragma unroll
+          for (int cc = jj + 1; cc < kPanel; ++cc) {
+            const int c = c0 + cc;
+            const double lch = bcast(h[jj], c), lcl = bcast(l[jj], c);   // L[c][j]
+            if (c < n && i >= c && i < n) dd_fnma(h[cc], l[cc], h[jj], l[jj], lch, lcl);
+          }
+          ++kept;
+          mask |= 1ull << j;
+        } else {
+          h[jj] = 0.0;
+          l[jj] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < kPanel; ++cc) {
+        const int c = c0 + cc;
+        if (c < n && i < n) {
+          Ah[i][c] = h[cc];
+          Al[i][c] = l[cc];
+        }
+      }
+    }
+    __syncthreads();
+    // A[i][c] -= sum_{j in panel} L[i][j] L[c][j] for c past the panel, i >= c
+    for (int c = c0 + kPanel + w; c < n; c += kWaves) {
+      if (i >= c && i < n) {
+        double ah = Ah[i][c], al = Al[i][c];
+#pragma unroll
+        for (int jj = 0; jj < kPanel; ++jj) {
+          const int j = c0 + jj;
+          dd_fnma(ah, al, Ah[i][j], Al[i][j], Ah[c][j], Al[c][j]);
+        }
+        Ah[i][c] = ah;
+        Al[i][c] = al;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *s_mask = mask;
+  __syncthreads();
+  return *s_mask;
+}
+
+// X = L^{-1} in float64 for the factor of wg_chol_drop_blocked, a dropped
+// candidate (and each row past n) taking a unit row and column so that X
+// restricted to the kept set is the inverse of the kept factor.  Ld (the
+// float64 L, built here) and X are kB x kB; wave w solves L x = e_c for its
+// columns c = w + 16 q by forward substitution, lane i holding row i, x_m
+// reaching the other lanes by readlane: no barrier inside the solve.
+__device__ void wg_lower_inverse(const LdsMat& Ah, LdsMat& Ld, LdsMat& X, uint64_t mask, int n) {
+  constexpr int kWaves = kChol / kWave;
+  const int tid = threadIdx.x, w = tid / kWave, i = lane_id();
+  for (int e = tid; e < kB * kB; e += kChol) {
+    const int r = e / kB, c = e % kB;
+    const bool kr = r < n && ((mask >> r) & 1ull), kc = c < n && ((mask >> c) & 1ull);
+    double v = 0.0;
+    if (r == c)
+      v = kr ? Ah[r][c] : 1.0;
+    else if (c < r && kr && kc)
+      v = Ah[r][c];
+    Ld[r][c] = v;
+  }
+  __syncthreads();
+  const double inv_d = 1.0 / Ld[i][i];
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) {
+    const int c = w + kWaves * q;
+    double acc = i == c ? 1.0 : 0.0;
+    for (int m = c; m < kB; ++m) {
+      const double xm = bcast(acc * inv_d, m);
+      if (i > m) acc = fma(-Ld[i][m], xm, acc);
+      if (i == m) X[m][c] = xm;
+    }
+    if (i < c) X[i][c] = 0.0;
+  }
+  __syncthreads();
+}
+
 // The block's residual Gram G (double-double): Cholesky with column drop in
 // candidate order (pivot vs eps^2 ||x||^2); kept positions compacted into
 // pos[0..na), na into sc->blk_na; Tacc = L_A^{-T} over the kept rows/columns
@@ -869,8 +992,9 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const BasisDev* __restrict
   double* __restrict__ Tacc = d.Tacc;
   DevScalars* sc = d.sc;
   __shared__ LdsMat Ah, Al, X;
-  __shared__ double ch[2 * kB], cl[2 * kB], xrow[2 * kB], gs[kB], piv[8];
+  __shared__ double gs[kB];
   __shared__ int32_t ps[kB];
+  __shared__ uint64_t s_mask;
   const int64_t nb_all = blk_count(sc, b0);
   const int64_t nb = blk_work(sc, b0, n_rows);
   const int tid = threadIdx.x;
@@ -889,7 +1013,8 @@ __global__ __launch_bounds__(kChol) void k_blk_decide(const BasisDev* __restrict
   }
   if (tid < kB) gs[tid] = tid < nb ? g[tid] : 0.0;
   __syncthreads();
-  const uint64_t m = wg_chol_inv<true>(Ah, &Al, X, ch, cl, xrow, piv, gs, (int)nb, true, eps2, room);
+  const uint64_t m = wg_chol_drop_blocked(Ah, Al, gs, (int)nb, eps2, room, &s_mask);
+  wg_lower_inverse(Ah, Al, X, m, (int)nb);   // Al is free once L is formed: it holds L in float64
   const int na = (int)__popcll(m);
   if (tid < kB) {
     const bool my_keep = (m >> tid) & 1ull;
