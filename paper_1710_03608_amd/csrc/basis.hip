@@ -962,17 +962,24 @@ __device__ void wg_lower_inverse(const LdsMat& Ah, LdsMat& Ld, LdsMat& X, uint64
   }
   __syncthreads();
   const double inv_d = 1.0 / Ld[i][i];
+  double acc[kSlots];   // the wave's four columns advance together (independent chains)
 #pragma unroll
-  for (int q = 0; q < kSlots; ++q) {
-    const int c = w + kWaves * q;
-    double acc = i == c ? 1.0 : 0.0;
-    for (int m = c; m < kB; ++m) {
-      const double xm = bcast(acc * inv_d, m);
-      if (i > m) acc = fma(-Ld[i][m], xm, acc);
-      if (i == m) X[m][c] = xm;
+  for (int q = 0; q < kSlots; ++q) acc[q] = i == w + kWaves * q ? 1.0 : 0.0;
+  for (int m = w; m < kB; ++m) {
+    const double lim = Ld[i][m];
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+      const int c = w + kWaves * q;
+      if (m >= c) {
+        const double xm = bcast(acc[q] * inv_d, m);
+        if (i > m) acc[q] = fma(-lim, xm, acc[q]);
+        if (i == m) X[m][c] = xm;
+      }
     }
-    if (i < c) X[i][c] = 0.0;
   }
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q)
+    if (i < w + kWaves * q) X[i][w + kWaves * q] = 0.0;
   __syncthreads();
 }
 
