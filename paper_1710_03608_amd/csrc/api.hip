@@ -155,9 +155,10 @@ void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_
   add(&b->fiber_mark, n);
   add(&b->resid, n * 8);
   const int64_t n_long = n / (kLongFiber + 1) + 1;
-  const int64_t long_ld = std::max<int64_t>(1, (std::max(max_cols, ld) + kChunkCols - 1) / kChunkCols);
+  const int64_t long_ld = kProjSlices;
   add(&b->long_list, n_long * 4);
   add(&b->long_part, n_long * long_ld * 8);
+  add(&b->zpart, (size_t)kProjSlices * n * 8);
   add(&b->partial, ((n + 8191) / 8192 + 1) * 8);
   add(&b->Rs, want_R ? n_rows * ld * 8 : 8);
   add(&b->C, want_C ? (size_t)ld * n * 8 : 8);
@@ -180,7 +181,7 @@ ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bo
   Arena& A = h->arena;
   A.reset();
   const int64_t ld = round8(s);
-  const int64_t long_ld = std::max<int64_t>(1, (std::max(max_cols, ld) + kChunkCols - 1) / kChunkCols);
+  const int64_t long_ld = kProjSlices;
   std::vector<PlanItem> items;
   static_items(nnz, s, n_rows, mixed, want_C, want_R, max_cols, b, items);
   std::vector<size_t> offs;
@@ -204,6 +205,7 @@ ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bo
   b->ld = ld;
   b->s_max = s;
   b->long_ld = long_ld;
+  b->zpart_ld = std::max<int64_t>(nnz, 1);
   return CTD_OK;
 }
 
@@ -288,6 +290,8 @@ ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const fl
   pa.long_list = b.long_list;
   pa.long_part = b.long_part;
   pa.long_ld = b.long_ld;
+  pa.zpart = b.zpart;
+  pa.zpart_ld = b.zpart_ld;
   pa.partial = b.partial;
   pa.mixed = mixed;
   return pa;

@@ -14,10 +14,10 @@ constexpr int kWave = 64;
 // Scalars produced on the device and read back only by ctd_get_result /
 // ctd_sync, so a whole decomposition runs without host round trips.
 // Fibers with more than kLongFiber nonzeros are gathered by a workgroup of
-// kLongWaves waves per column chunk of kChunkCols (float64) columns.
+// kLongWaves waves per column slice (at most kProjSlices slices, one per XCD).
 constexpr int kLongFiber = 64;
 constexpr int kLongWaves = 8;
-constexpr int kChunkCols = 256;
+constexpr int kProjSlices = 8;
 
 struct DevScalars {
   uint64_t W;            // total integer sampling weight of the last input

@@ -163,8 +163,10 @@ struct ProjectArgs {
   int64_t ncols_max;
   double* resid;           // [n_f] out
   int32_t* long_list;      // [nnz / (kLongFiber + 1) + 1] workspace: long fibers
-  double* long_part;       // [long_list size x long_ld] per-chunk ||z||^2 of long fibers
-  int64_t long_ld;         // column chunks held per long fiber
+  double* long_part;       // [long_list size x long_ld] per-slice ||z||^2 of long fibers
+  int64_t long_ld;         // column slices held per long fiber (>= kProjSlices)
+  double* zpart;           // [kProjSlices x zpart_ld] per-slice ||z||^2 of the other fibers
+  int64_t zpart_ld;        // >= number of fibers
   double* partial;         // workspace
   bool mixed;
 };

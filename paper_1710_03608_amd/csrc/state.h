@@ -53,6 +53,8 @@ struct StaticBufs {
   int32_t* long_list;
   double* long_part;
   int64_t long_ld;
+  double* zpart;
+  int64_t zpart_ld;
   double* partial;
   double* Rs;
   double* C;
