@@ -84,7 +84,8 @@ __device__ inline void slice_cols(int64_t ncols, int S, int slice, int64_t& lo, 
 // wave writes resid[f] = ||x_f||^2 - ||z_f||^2 itself; with several, the
 // slice's ||z||^2 goes to zpart[slice][f], slice 0 puts ||x_f||^2 into
 // resid[f] and k_proj_multi_fin subtracts the slices.
-template <typename T, int VEC>
+// kSliced: gridDim.x column slices (partials to zpart) rather than whole rows.
+template <typename T, int VEC, bool kSliced>
 __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars* sc, int fpw) {
   constexpr int kCols = VEC * kWave;
   if (sc->status != 0) return;
@@ -138,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars
       const int32_t rr = lane < n ? a.row[e0 + lane] : 0;
       const T vv = lane < n ? vals[e0 + lane] : T(0);
       double z2 = 0.0;
-      if (hi - lo > kCols) {
-        // a wide slice: two chunks times two nonzeros in flight
+      if (!kSliced || hi - lo > kCols) {
+        // whole rows or a wide slice: two chunks times two nonzeros in flight
         for (int64_t c0 = lo; c0 < hi; c0 += 2 * kCols) {
           const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
           const bool ina = ca < hi, inb = cb < hi;
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars
             z2 += (cb + j < hi) ? d1 * d1 : 0.0;
           }
         }
-      } else {
+      } else if constexpr (kSliced) {
         // one chunk: four nonzeros in flight
         const int64_t ca = lo + (int64_t)VEC * lane;
         const bool in = ca < hi;
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi(ProjectArgs a, DevScalars
         }
       }
       z2 = wave_sum(z2);
-      if (gridDim.x == 1) {
+      if (!kSliced) {
         const double v64 = lane < n ? a.val[e0 + lane] : 0.0;
         const double x2 = wave_sum(v64 * v64);
         if (lane == 0) a.resid[f] = x2 - z2;
@@ -318,12 +319,13 @@ void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevSc
                     hipEvent_t ev0, hipEvent_t ev1) {
   // Candidates for the fibers of up to kLongFiber nonzeros: fibers per wave
   // (few for a small input such as a time slice, whose few thousand fibers
-  // must still spread over many waves; 64 for a large one), times whole rows
-  // or XCD column slices (more waves for a small input, but every fiber's
-  // bookkeeping repeated per slice).  The autotuner picks per input-size
-  // bucket.
-  static const int kFpw[] = {2, 8, kWave, 2, 8, kWave};
-  constexpr int kNCand = 6;
+  // must still spread over many waves; 64 for a large one) and column slices
+  // (each XCD's L2 then caches a smaller part of every row, and a small input
+  // gets more waves, but every fiber's bookkeeping is repeated per slice).
+  // The autotuner picks per input-size bucket.
+  static const int kFpw[] = {2, 8, kWave, 2, 8, kWave, kWave, kWave};
+  static const int kSl[] = {1, 1, 1, kProjSlices, kProjSlices, 2, 4, kProjSlices};
+  constexpr int kNCand = 8;
   const int prec = a.mixed ? 1 : 0, bucket = tune_bucket(nnz_max);
   int choice = tune_get(TUNE_PROJ_FPW, prec, bucket, kNCand);
   std::vector<hipEvent_t> tev;
@@ -331,16 +333,19 @@ void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevSc
   if (choice < 0) choice = nnz_max <= (int64_t(1) << 18) ? 3 : 2;
   const int s_multi = proj_slices(a.ncols_max, 4 * kWave);
   auto multi = [&](int c) {
-    const int fpw = kFpw[c], S = c < 3 ? 1 : s_multi;
+    const int fpw = kFpw[c], S = std::min(kSl[c], s_multi);
     hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
     const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
     const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
-    if (a.mixed && S == 1)
-      hipLaunchKernelGGL((k_proj_multi<float, 8>), dim3(S, gm), dim3(kBlock), 0, st, a, sc, fpw);
+    const dim3 grid(S, gm);
+    if (S > 1 && a.mixed)
+      hipLaunchKernelGGL((k_proj_multi<float, 4, true>), grid, dim3(kBlock), 0, st, a, sc, fpw);
+    else if (S > 1)
+      hipLaunchKernelGGL((k_proj_multi<double, 4, true>), grid, dim3(kBlock), 0, st, a, sc, fpw);
     else if (a.mixed)
-      hipLaunchKernelGGL((k_proj_multi<float, 4>), dim3(S, gm), dim3(kBlock), 0, st, a, sc, fpw);
+      hipLaunchKernelGGL((k_proj_multi<float, 8, false>), grid, dim3(kBlock), 0, st, a, sc, fpw);
     else
-      hipLaunchKernelGGL((k_proj_multi<double, 4>), dim3(S, gm), dim3(kBlock), 0, st, a, sc, fpw);
+      hipLaunchKernelGGL((k_proj_multi<double, 4, false>), grid, dim3(kBlock), 0, st, a, sc, fpw);
     return S;
   };
   const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
