@@ -317,23 +317,27 @@ static int proj_slices(int64_t ncols_max, int chunk) {
 
 void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,
                     hipEvent_t ev0, hipEvent_t ev1) {
-  // Candidates for the fibers of up to kLongFiber nonzeros: fibers per wave
-  // (few for a small input such as a time slice, whose few thousand fibers
-  // must still spread over many waves; 64 for a large one) and column slices
-  // (each XCD's L2 then caches a smaller part of every row, and a small input
-  // gets more waves, but every fiber's bookkeeping is repeated per slice).
-  // The autotuner picks per input-size bucket.
-  static const int kFpw[] = {2, 8, kWave, 2, 8, kWave, kWave, kWave};
-  static const int kSl[] = {1, 1, 1, kProjSlices, kProjSlices, 2, 4, kProjSlices};
-  constexpr int kNCand = 8;
+  // Fibers of up to kLongFiber nonzeros.  Column slices: each XCD's L2 then
+  // caches a smaller part of every row and a small input gets more waves, but
+  // every fiber's bookkeeping is repeated per slice.  A small input (a time
+  // slice) takes the most slices; a large one two in float64 and whole rows
+  // in float32, where the rows are half as long.  The slice count is fixed
+  // by this rule rather than measured, because the sum over slices rounds
+  // differently: the autotuner's candidates, the fibers per wave (few for a
+  // small input, whose few thousand fibers must still spread over many
+  // waves; 64 for a large one), all give bit-identical results.
+  static const int kFpw[] = {2, 8, kWave};
+  constexpr int kNCand = 3;
+  const bool small = nnz_max <= (int64_t(1) << 18);
   const int prec = a.mixed ? 1 : 0, bucket = tune_bucket(nnz_max);
   int choice = tune_get(TUNE_PROJ_FPW, prec, bucket, kNCand);
   std::vector<hipEvent_t> tev;
   const bool measure = choice < 0 && tune_begin(TUNE_PROJ_FPW, prec, bucket, kNCand, &tev);
-  if (choice < 0) choice = nnz_max <= (int64_t(1) << 18) ? 3 : 2;
-  const int s_multi = proj_slices(a.ncols_max, 4 * kWave);
+  if (choice < 0) choice = small ? 0 : 2;
+  const int s_max = proj_slices(a.ncols_max, 4 * kWave);
+  const int S = small ? s_max : std::min(a.mixed ? 1 : 2, s_max);
   auto multi = [&](int c) {
-    const int fpw = kFpw[c], S = std::min(kSl[c], s_multi);
+    const int fpw = kFpw[c];
     hipLaunchKernelGGL(k_zero_long, dim3(1), dim3(1), 0, st, sc);
     const int64_t waves = (std::max<int64_t>(nnz_max, 1) + fpw - 1) / fpw;
     const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (waves + 3) / 4));
@@ -346,22 +350,20 @@ void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevSc
       hipLaunchKernelGGL((k_proj_multi<float, 8, false>), grid, dim3(kBlock), 0, st, a, sc, fpw);
     else
       hipLaunchKernelGGL((k_proj_multi<double, 4, false>), grid, dim3(kBlock), 0, st, a, sc, fpw);
-    return S;
   };
   const int64_t max_long = nnz_max / (kLongFiber + 1) + 1;
   const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(1024, max_long));
   if (ev0) (void)hipEventRecord(ev0, st);
-  int S = 1;
   if (measure) {
     // every candidate once, timed; the last run's residuals, slice partials
     // and long-fiber list are the ones used (all runs write the same values)
     for (int c = 0; c < kNCand; ++c) {
       (void)hipEventRecord(tev[2 * c], st);
-      S = multi(c);
+      multi(c);
       (void)hipEventRecord(tev[2 * c + 1], st);
     }
   } else {
-    S = multi(choice);
+    multi(choice);
   }
   if (S > 1)
     hipLaunchKernelGGL(k_proj_multi_fin,

@@ -116,6 +116,43 @@ def test_runs_are_bit_identical(lib):
     assert np.array_equal(a["accepted"], b["accepted"])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_projection_in_column_slices(lib, precision):
+    """At most 2^18 nonzeros and s >= 1536: the fibers of 2..64 nonzeros are
+    projected in eight column slices of one gather chunk each, the longer
+    fibers in eight (float64) or four (float32) slices."""
+    X = synth.power_law_tensor((2000, 400, 30), 200000, 31, zipf_a=1.1)
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 1600, 5)
+    lens = np.bincount(np.unique(ora.fiber_ids(X.dims, X.idx, 0), return_inverse=True)[1])
+    assert (lens > 64).any() and ((lens >= 2) & (lens <= 64)).any()
+    g = run_gpu(lib, X, 0, 1600, 5, precision=precision)
+    if borderline(o):
+        pytest.skip("candidate within rounding of the threshold")
+    if precision == "fp64":
+        check_parity(g, o)
+    else:
+        check_parity(g, o, rtol=RTOL_MIXED, atol=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_input_runs_are_bit_identical(lib, precision):
+    """Above 2^18 nonzeros the projection uses two column slices in float64
+    and whole rows in float32; the first call of a size (which times every
+    fibers-per-wave variant) and later calls agree bit for bit."""
+    X = synth.power_law_tensor((2000, 600, 40), 400000, 32, zipf_a=1.1)
+    runs = [run_gpu(lib, X, 0, 1200, 6, precision=precision) for _ in range(3)]
+    for r in runs[1:]:
+        assert r["err2"] == runs[0]["err2"]
+        assert np.array_equal(r["accepted"], runs[0]["accepted"])
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 1200, 6)
+    if borderline(o):
+        pytest.skip("candidate within rounding of the threshold")
+    if precision == "fp64":
+        check_parity(runs[0], o)
+    else:
+        check_parity(runs[0], o, rtol=RTOL_MIXED, atol=1e-6)
+
+
 def test_all_fibers_drawn_gives_zero_residual(lib):
     X = synth.uniform_tensor((40, 30, 10), 1500, 5)
     u = ora.unfold(X.dims, X.idx, X.val, 0)
