@@ -28,6 +28,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRedBlock = 1024;
 constexpr int kRedItems = 8;
+constexpr int kLongBatch = 16;   // nonzeros per wave and step in k_proj_long
 
 // z += sum_e v_e A[r_e, c .. c + VEC) over the n (<= 64) nonzeros whose
 // (row, value) are held one per lane in (rr, vv), four rows in flight.
@@ -205,8 +206,9 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi_fin(ProjectArgs a, const 
 
 // Long fibers: workgroup (slice, i) forms z of listed fiber i over column
 // slice blockIdx.x with all its waves (wave wv takes the nonzeros in
-// interleaved batches of 64; the waves' partial z are added in LDS in wave
-// order) and stores the slice's ||z||^2.
+// interleaved batches of kLongBatch, so that a fiber of a few hundred
+// nonzeros still keeps all eight waves busy; the waves' partial z are added
+// in LDS in wave order) and stores the slice's ||z||^2.
 template <typename T, int VEC>
 __global__ __launch_bounds__(kLongWaves * kWave) void k_proj_long(ProjectArgs a,
                                                                   const DevScalars* sc) {
@@ -229,8 +231,8 @@ __global__ __launch_bounds__(kLongWaves * kWave) void k_proj_long(ProjectArgs a,
       T acc[VEC];
 #pragma unroll
       for (int j = 0; j < VEC; ++j) acc[j] = T(0);
-      for (int32_t eb = e0 + wv * kWave; eb < e1; eb += kLongWaves * kWave) {
-        const int n = min(kWave, e1 - eb);
+      for (int32_t eb = e0 + wv * kLongBatch; eb < e1; eb += kLongWaves * kLongBatch) {
+        const int n = min(kLongBatch, e1 - eb);
         const int32_t rr = lane < n ? a.row[eb + lane] : 0;
         const T vv = lane < n ? vals[eb + lane] : T(0);
         gather_seg<T, VEC>(rr, vv, n, Qb + (in ? c : 0), in, a.ldq, acc);
