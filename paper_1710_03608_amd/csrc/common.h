@@ -14,7 +14,8 @@ constexpr int kWave = 64;
 // Scalars produced on the device and read back only by ctd_get_result /
 // ctd_sync, so a whole decomposition runs without host round trips.
 // Fibers with more than kLongFiber nonzeros are gathered by a workgroup of
-// kLongWaves waves per column slice (at most kProjSlices slices, one per XCD).
+// kLongWaves waves per column slice of the projection (at most kProjSlices
+// slices, one per XCD) or per column chunk of C's columns.
 constexpr int kLongFiber = 64;
 constexpr int kLongWaves = 8;
 constexpr int kProjSlices = 8;
