@@ -100,20 +100,21 @@ __global__ __launch_bounds__(kSegBlock) void k_seg_reduce(SegmentBuffers b, int6
   __shared__ double tv[kSegBlock / kWave + 1];
   const int sigma = sc->sigma;
   const uint64_t rmask = rbits ? ((~0ull) >> (64 - rbits)) : 0ull;
-  const int64_t base = (int64_t)blockIdx.x * kSegTile + (int64_t)threadIdx.x * kSegItems;
+  // only the tile's totals are needed here, so its elements are taken in
+  // strided order (neighbouring lanes on neighbouring elements)
+  const int64_t tile = (int64_t)blockIdx.x * kSegTile;
   uint32_t cnt = 0;
   uint64_t qs = 0;
   double v2s = 0.0;
-  uint64_t prev = base > 0 && base < nnz ? b.keys[base - 1] : ~0ull;
   bool dup = false;
 #pragma unroll
   for (int i = 0; i < kSegItems; ++i) {
-    const int64_t e = base + i;
+    const int64_t e = tile + (int64_t)i * kSegBlock + threadIdx.x;
     if (e < nnz) {
       const uint64_t key = b.keys[e];
+      const uint64_t prev = e > 0 ? b.keys[e - 1] : ~0ull;
       const bool start = (e == 0) || ((key >> rbits) != (prev >> rbits));
       dup |= (e > 0) && (key == prev);
-      prev = key;
       const double v = load_val(b.val_in, b.val_dtype, b.perm[e]);
       b.val[e] = v;
       if (b.val32) b.val32[e] = (float)v;
