@@ -386,7 +386,8 @@ ctd_status static_back(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, 
   const int64_t n_rows = lay.n_rows;
   StaticBufs& b = h->sb;
   DevScalars* sc = h->d_sc;
-  ProjectArgs pa = project_args(h, b, b.Q, b.Qf, b.ld, b.lev, &sc->s_tilde, s);
+  // s~ <= min(s, I_alpha): the bound sets the projection's column slices
+  ProjectArgs pa = project_args(h, b, b.Q, b.Qf, b.ld, b.lev, &sc->s_tilde, std::min(s, n_rows));
   if (h->opt.profile) {
     mark(h, MARK_PROJ0);
     mark(h, MARK_SPMM0);
