@@ -181,15 +181,23 @@ def unique_with_scale(draws, w, W, s):
 
 @dataclasses.dataclass
 class Basis:
-    """R (actual fibers as dense columns), U, and an orthonormal basis of span(R)."""
+    """R (actual fibers as dense columns) and an orthonormal basis of span(R).
+
+    `Ub`, when tracked, is Algorithm 1's literal bordered-inverse update of U.
+    It equals (R^T R)^{-1} in exact arithmetic but drifts from it (and can
+    overflow) once R is ill-conditioned, so it is kept only for the
+    cross-check on well-conditioned inputs; U itself is taken from its
+    definition by `inverse_gram`.
+    """
     R: np.ndarray          # I_alpha x cap
-    U: np.ndarray          # cap x cap
     Qb: np.ndarray         # I_alpha x cap, orthonormal columns spanning span(R[:, :k])
     k: int                 # number of columns in use
+    Ub: np.ndarray | None = None   # cap x cap bordered-update U, if tracked
 
     @staticmethod
-    def empty(n_rows, cap):
-        return Basis(np.zeros((n_rows, cap)), np.zeros((cap, cap)), np.zeros((n_rows, cap)), 0)
+    def empty(n_rows, cap, bordered=False):
+        return Basis(np.zeros((n_rows, cap)), np.zeros((n_rows, cap)), 0,
+                     np.zeros((cap, cap)) if bordered else None)
 
     def grow(self, extra):
         cap = self.R.shape[1]
@@ -200,9 +208,23 @@ class Basis:
         R[:, :self.k] = self.R[:, :self.k]
         Qb = np.zeros((self.R.shape[0], new_cap))
         Qb[:, :self.k] = self.Qb[:, :self.k]
-        U = np.zeros((new_cap, new_cap))
-        U[:self.k, :self.k] = self.U[:self.k, :self.k]
-        self.R, self.U, self.Qb = R, U, Qb
+        if self.Ub is not None:
+            Ub = np.zeros((new_cap, new_cap))
+            Ub[:self.k, :self.k] = self.Ub[:self.k, :self.k]
+            self.Ub = Ub
+        self.R, self.Qb = R, Qb
+
+
+def inverse_gram(R) -> np.ndarray:
+    """U = (R^T R)^{-1}, the definition in the proof of Lemma 2.
+
+    Taken from the singular value decomposition R = W S V^T as V S^-2 V^T, an
+    algebra that shares nothing with the basis the independence test uses.
+    """
+    if R.shape[1] == 0:
+        return np.zeros((0, 0))
+    _, sv, Vt = np.linalg.svd(R, full_matrices=False)
+    return (Vt.T / (sv * sv)) @ Vt
 
 
 def residual_against_span(Qb, x):
@@ -223,7 +245,8 @@ def independence_loop(basis: Basis, candidates, eps):
     `candidates` yields dense I_alpha vectors.  Returns (kept flags,
     rho = ||res||^2 / ||x||^2 for every candidate).  A fresh basis (k == 0)
     takes the first candidate unconditionally (Algorithm 1).  Kept
-    fibers extend R and U by the bordered-inverse update of Algorithm 1.
+    fibers extend R; if the basis tracks it, also the literal
+    bordered-inverse update of U from Algorithm 1.
     """
     kept, rho = [], []
     for x in candidates:
@@ -232,28 +255,29 @@ def independence_loop(basis: Basis, candidates, eps):
         if k == 0:
             basis.grow(1)
             basis.R[:, 0] = x
-            basis.U[0, 0] = 1.0 / xx
+            if basis.Ub is not None:
+                basis.Ub[0, 0] = 1.0 / xx
             basis.Qb[:, 0] = x / math.sqrt(xx)
             basis.k = 1
             kept.append(True)
             rho.append(1.0)
             continue
-        R = basis.R[:, :k]
-        U = basis.U[:k, :k]
         res = residual_against_span(basis.Qb[:, :k], x)
         nres = float(np.linalg.norm(res))
         rho.append(nres * nres / xx)
         if nres <= eps * math.sqrt(xx):
             kept.append(False)
             continue
-        delta = nres * nres
-        y = U @ (R.T @ x)
         basis.grow(1)
-        Unew = basis.U
-        Unew[:k, :k] = U + np.outer(y, y) / delta
-        Unew[:k, k] = -y / delta
-        Unew[k, :k] = -y / delta
-        Unew[k, k] = 1.0 / delta
+        if basis.Ub is not None:
+            # Algorithm 1's bordered update with delta = ||res||^2, y = U R^T x
+            delta = nres * nres
+            U = basis.Ub[:k, :k].copy()
+            y = U @ (basis.R[:, :k].T @ x)
+            basis.Ub[:k, :k] = U + np.outer(y, y) / delta
+            basis.Ub[:k, k] = -y / delta
+            basis.Ub[k, :k] = -y / delta
+            basis.Ub[k, k] = 1.0 / delta
         basis.R[:, k] = x
         basis.Qb[:, k] = res / nres
         basis.k = k + 1
@@ -317,12 +341,13 @@ class StaticResult:
     accepted: np.ndarray     # fiber ids kept in R, in order of acceptance (ascending)
     rho: np.ndarray          # per unique candidate, ||res||^2/||x||^2
     R: np.ndarray            # I_alpha x s~
-    U: np.ndarray            # s~ x s~
+    U: np.ndarray            # s~ x s~, (R^T R)^{-1} from its definition
     C: np.ndarray | None     # s~ x n_f, if requested
     err2: float              # ||X - X~||_F^2
     norm2: float             # ||X||_F^2
     proj: np.ndarray | None  # per non-empty fiber ||P x_f||^2 (projection algebra)
     Qb: np.ndarray | None = None  # orthonormal basis of span(R)
+    U_bordered: np.ndarray | None = None  # Algorithm 1's literal update of U, if tracked
 
     @property
     def rel_err(self):
@@ -330,25 +355,26 @@ class StaticResult:
 
 
 def ctd_s_given(u: Unfolding, draw_pos, eps=1e-6, want_C=False, residual="auto",
-                w=None, W=None, s=None):
+                w=None, W=None, s=None, bordered=False):
     """CTD-S from given draws (positions into u.fids; duplicates allowed).
 
     The error is ||X - X~||_F^2 with X~ = R U C_(alpha), which by Lemma 2
     (Eq. 7) is the orthogonal projection of X_(alpha) onto span(R).  The
     default ("projection") evaluates it with a Householder QR of R, which
     stays accurate when R is ill-conditioned; "literal" multiplies out
-    R U C with the incrementally updated U (small inputs only).
+    R U C with U = (R^T R)^{-1} (small, well-conditioned inputs only).
+    `bordered` also tracks Algorithm 1's literal update of U (U_bordered).
     """
     draw_pos = np.asarray(draw_pos, dtype=np.int64)
     s = draw_pos.shape[0] if s is None else s
     if w is None:
         w, W = quantized_weights(u)
     uniq, counts, p, omega = unique_with_scale(draw_pos, w, W, s)
-    basis = Basis.empty(u.n_rows, max(1, min(uniq.shape[0], u.n_rows) + 1))
+    basis = Basis.empty(u.n_rows, max(1, min(uniq.shape[0], u.n_rows) + 1), bordered)
     kept, rho = independence_loop(basis, (u.column(j) for j in uniq.tolist()), eps)
     kept = np.array(kept, dtype=bool)
     R = basis.R[:, :basis.k].copy()
-    U = basis.U[:basis.k, :basis.k].copy()
+    U = inverse_gram(R)
     Qb = basis.Qb[:, :basis.k].copy()
     C = core_matrix(R, u) if want_C else None
     if residual == "auto":
@@ -359,11 +385,13 @@ def ctd_s_given(u: Unfolding, draw_pos, eps=1e-6, want_C=False, residual="auto",
         err2 = error_literal(R, U, Cm, u)
     else:
         err2, proj = error_projection(R, u)
+    Ub = basis.Ub[:basis.k, :basis.k].copy() if bordered else None
     return StaticResult(u, u.fids[draw_pos], u.fids[uniq], counts, p, omega,
-                        u.fids[uniq[kept]], np.array(rho), R, U, C, err2, u.norm2, proj, Qb)
+                        u.fids[uniq[kept]], np.array(rho), R, U, C, err2, u.norm2, proj, Qb, Ub)
 
 
-def ctd_s(dims, idx, val, mode, s, seed, eps=1e-6, want_C=False, residual="auto", tensor=0):
+def ctd_s(dims, idx, val, mode, s, seed, eps=1e-6, want_C=False, residual="auto", tensor=0,
+          bordered=False):
     """Algorithm 1 end to end with the Philox draw specification above.
 
     `tensor` is the counter word that tells the tensors of one batched call
@@ -374,7 +402,7 @@ def ctd_s(dims, idx, val, mode, s, seed, eps=1e-6, want_C=False, residual="auto"
         raise ValueError("sample size out of range")
     w, W = quantized_weights(u)
     draw_pos = sample_columns(w, W, s, seed, step=0, tensor=tensor)
-    return ctd_s_given(u, draw_pos, eps, want_C, residual, w=w, W=W, s=s)
+    return ctd_s_given(u, draw_pos, eps, want_C, residual, w=w, W=W, s=s, bordered=bordered)
 
 
 # ---------------------------------------------------------------------------
@@ -388,16 +416,22 @@ class Dynamic:
     of the tensor and length 1 in the time mode; its fiber j becomes column
     j + T * dN_alpha of the grown matricization, T being the number of time
     steps already held.
+
+    With keep_C=False the block update of C is not carried (long streams
+    whose C would not fit); `core_columns` still gives any column of C from
+    its closed form.
     """
 
     def __init__(self, dims, idx, val, mode, s, seed, eps=1e-6, keep_dense=False,
-                 draw_pos=None):
+                 draw_pos=None, keep_C=True):
         if mode == len(dims) - 1:
             raise ValueError("mode must not be the time mode")
+        if keep_dense and not keep_C:
+            raise ValueError("the literal error needs C")
         if draw_pos is None:
-            st = ctd_s(dims, idx, val, mode, s, seed, eps, want_C=True)
+            st = ctd_s(dims, idx, val, mode, s, seed, eps, want_C=keep_C)
         else:
-            st = ctd_s_given(unfold(dims, idx, val, mode), draw_pos, eps, want_C=True)
+            st = ctd_s_given(unfold(dims, idx, val, mode), draw_pos, eps, want_C=keep_C)
         self.dims = tuple(int(d) for d in dims)
         self.mode, self.seed, self.eps = mode, seed, eps
         self.static = st
@@ -405,12 +439,14 @@ class Dynamic:
         self.dN = st.unfolding.n_cols_total // self.T
         self.basis = Basis.empty(st.R.shape[0], st.R.shape[1] + 64)
         self.basis.R[:, :st.R.shape[1]] = st.R
-        self.basis.U[:st.R.shape[1], :st.R.shape[1]] = st.U
         self.basis.Qb[:, :st.R.shape[1]] = st.Qb
         self.basis.k = st.R.shape[1]
         self.accepted = list(st.accepted.tolist())
+        self.keep_C = keep_C
         self.C = st.C
         self.col_fids = st.unfolding.fids.copy()
+        # every input with the size of R right after it was taken in
+        self.inputs = [(st.R.shape[1], st.unfolding)]
         self.err2 = st.err2
         self.norm2 = st.norm2
         self.step = 0
@@ -423,7 +459,30 @@ class Dynamic:
 
     @property
     def U(self):
-        return self.basis.U[:self.basis.k, :self.basis.k]
+        """U^(t) = (R^(t)T R^(t))^{-1} (proof of Lemma 2)."""
+        return inverse_gram(self.R)
+
+    def core_columns(self, cols) -> np.ndarray:
+        """Columns `cols` of C^(t)_(alpha) from their closed form.
+
+        Unrolling Eqs. 8-13: a fiber x taken in at step tau gets the column
+        R^(tau)T x, R^(tau) being R right after that step; a later step that
+        adds the fibers dR appends dR^T R U C = dR^T P_tau x to it, P_tau the
+        orthogonal projector onto span(R^(tau)), because span(R) only grows.
+        Since R^(tau)T x = R^(tau)T P_tau x, the column is R^(t)T P_tau x.
+        P_tau is taken from a Householder QR of R^(tau).
+        """
+        cols = np.asarray(cols, dtype=np.int64)
+        out = np.zeros((self.basis.k, cols.shape[0]))
+        start = 0
+        for k_tau, u in self.inputs:
+            sel = np.nonzero((cols >= start) & (cols < start + u.n_f))[0]
+            if sel.shape[0]:
+                Qt, _ = np.linalg.qr(self.R[:, :k_tau])
+                Xs = u.mat[:, cols[sel] - start].toarray()
+                out[:, sel] = self.R.T @ (Qt @ (Qt.T @ Xs))
+            start += u.n_f
+        return out
 
     def update(self, sdims, sidx, sval, d, draw_pos=None):
         """Algorithm 2 on one slice; returns a dict describing the step.
@@ -440,7 +499,6 @@ class Dynamic:
         self.step += 1
         k_old = self.basis.k
         R_old = self.R.copy()
-        U_old = self.U.copy()
         if u.norm2 == 0.0 or u.n_f == 0:
             draws = np.zeros(0, np.int64)
             uniq = np.zeros(0, np.int64)
@@ -458,20 +516,26 @@ class Dynamic:
             kept = np.array(kept, dtype=bool)
         dR = self.R[:, k_old:]
         dX = u.mat
-        # Eq. 13: block update, cross term parenthesized from the left
-        top_new = np.asarray((dX.T @ R_old).T)              # R^(t)T dX
-        if dR.shape[1]:
-            cross = ((dR.T @ R_old) @ U_old) @ self.C       # ((dR^T R) U) C
-            bot_new = np.asarray((dX.T @ dR).T)             # dR^T dX
-            self.C = np.block([[self.C, top_new], [cross, bot_new]])
-        else:
-            self.C = np.hstack([self.C, top_new])
+        U_old = None
+        if self.keep_C:
+            # Eq. 13: block update, cross term parenthesized from the left
+            top_new = np.asarray((dX.T @ R_old).T)              # R^(t)T dX
+            if dR.shape[1]:
+                U_old = inverse_gram(R_old)                     # U^(t)
+                cross = ((dR.T @ R_old) @ U_old) @ self.C       # ((dR^T R) U) C
+                bot_new = np.asarray((dX.T @ dR).T)             # dR^T dX
+                self.C = np.block([[self.C, top_new], [cross, bot_new]])
+            else:
+                self.C = np.hstack([self.C, top_new])
         offset = self.T * self.dN
         new_fids = u.fids + offset
         self.col_fids = np.concatenate([self.col_fids, new_fids])
         self.T += 1
         self.norm2 += u.norm2
         self.accepted.extend((new_fids[uniq[kept]]).tolist() if len(uniq) else [])
+        self.inputs.append((self.basis.k, u))
+        if self.keep_C and U_old is None:
+            U_old = inverse_gram(R_old)
         self.last_blocks = dict(R_old=R_old, U_old=U_old, dR=dR.copy(), dX=dX)
         if self.X is not None:
             self.X = np.hstack([self.X, dX.toarray()])

@@ -203,40 +203,55 @@ class Ctd:
         if rc != 0:
             raise CtdError(rc, self.lib.ctd_last_error(self.h).decode())
 
+    def _hold(self, *objs):
+        """Keep a call's input buffers alive until the stream has passed the call.
+
+        Each call's buffers are held with an event recorded after it; holdings
+        whose events have completed are released at the next call, so a long
+        CTD-D stream does not accumulate its slices."""
+        import torch
+        self._keep = [(ev, o) for ev, o in self._keep if ev is not None and not ev.query()]
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        self._keep.append((ev, objs))
+
     def decompose(self, dims, idx, val, mode, s, seed):
         coo = Coo(dims, idx, val)
-        self._keep = [coo]
-        self._check(self.lib.ctd_decompose(self.h, ctypes.byref(coo.struct), int(mode), int(s),
-                                           int(seed)))
+        rc = self.lib.ctd_decompose(self.h, ctypes.byref(coo.struct), int(mode), int(s), int(seed))
+        self._hold(coo)
+        self._check(rc)
 
     def decompose_given(self, dims, idx, val, mode, draws):
         coo = Coo(dims, idx, val)
-        self._keep = [coo]
         arr = np.ascontiguousarray(np.asarray(draws, dtype=np.uint64))
         ptr = arr.ctypes.data_as(ctypes.POINTER(c_u64))
-        self._check(self.lib.ctd_decompose_given(self.h, ctypes.byref(coo.struct), int(mode), ptr,
-                                                 int(arr.shape[0])))
+        rc = self.lib.ctd_decompose_given(self.h, ctypes.byref(coo.struct), int(mode), ptr,
+                                          int(arr.shape[0]))
+        self._hold(coo)
+        self._check(rc)
 
     def update(self, dims, idx, val, d):
         coo = Coo(dims, idx, val)
-        self._keep.append(coo)
-        self._check(self.lib.ctd_update(self.h, ctypes.byref(coo.struct), int(d)))
+        rc = self.lib.ctd_update(self.h, ctypes.byref(coo.struct), int(d))
+        self._hold(coo)
+        self._check(rc)
 
     def update_batched(self, slices, d):
         """CTD-D on consecutive slices [(dims, idx, val), ...] in one call."""
         coos = [Coo(dims, idx, val) for dims, idx, val in slices]
-        self._keep.extend(coos)
         arr = (CooStruct * len(coos))(*[c.struct for c in coos])
-        self._keep.append(arr)
-        self._check(self.lib.ctd_update_batched(self.h, arr, len(coos), int(d)))
+        rc = self.lib.ctd_update_batched(self.h, arr, len(coos), int(d))
+        self._hold(coos, arr)
+        self._check(rc)
 
     def decompose_batched(self, tensors, mode, s, seed):
         """CTD-S of many tensors [(dims, idx, val), ...] with s[b] draws each."""
         coos = [Coo(dims, idx, val) for dims, idx, val in tensors]
         arr = (CooStruct * len(coos))(*[c.struct for c in coos])
         sz = (c_i64 * len(coos))(*[int(x) for x in s])
-        self._keep = [coos, arr, sz]
-        self._check(self.lib.ctd_decompose_batched(self.h, arr, len(coos), int(mode), sz, int(seed)))
+        rc = self.lib.ctd_decompose_batched(self.h, arr, len(coos), int(mode), sz, int(seed))
+        self._hold(coos, arr, sz)
+        self._check(rc)
 
     def batch_result(self, b, arrays=True):
         """Scalars (and index arrays) of tensor b of the last batched call."""
@@ -307,8 +322,9 @@ class Ctd:
         return device_columns(r.C, r.ldc, r.s_tilde, cols,
                               np.float32 if r.C_dtype == 1 else np.float64)
 
-    def result(self, arrays=True, factors=False):
-        """Scalars plus host copies of the index arrays (and factors if asked)."""
+    def result(self, arrays=True, factors=False, core=True):
+        """Scalars plus host copies of the index arrays (and factors if asked;
+        core=False leaves out C itself, keeping its column ids)."""
         r = self.raw_result()
         out = {k: getattr(r, k) for k in ("s", "s_unique", "s_tilde", "n_f", "n_rows", "step",
                                           "weight_total", "norm2", "err2", "rel_err",
@@ -331,8 +347,9 @@ class Ctd:
             if r.R:
                 out["R"] = device_matrix(r.R, r.n_rows, k, r.ldr)
             if r.C:
-                out["C"] = device_matrix(r.C, k, r.n_cols, r.ldc, row_major=False,
-                                         dtype=np.float32 if r.C_dtype == 1 else np.float64)
+                if core:
+                    out["C"] = device_matrix(r.C, k, r.n_cols, r.ldc, row_major=False,
+                                             dtype=np.float32 if r.C_dtype == 1 else np.float64)
                 out["col_ids"] = device_to_numpy(r.col_ids, r.n_cols, np.uint64)
         return out
 

@@ -10,6 +10,8 @@ from workloads import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
+pytestmark = pytest.mark.filterwarnings("error::RuntimeWarning")
+
 
 def _stream(seed=3, dims=(24, 18, 6), nnz0=500, n_slices=6):
     st = synth.traffic_stream(dims=dims, nnz0=nnz0, n_slices=n_slices,
@@ -36,6 +38,22 @@ def test_block_update_equals_direct_product():
             # empty dR: only new columns are added (Algorithm 2)
             assert dyn.C.shape[0] == C_old.shape[0]
     assert saw_growth
+
+
+def test_core_columns_closed_form_equals_block_update():
+    """Every column of C^(t) from its closed form R^(t)T P_tau x (a QR projector)
+    equals the block update of Eq. 13 with U = (R^T R)^{-1}, after every step."""
+    st = _stream(seed=13, n_slices=8)
+    dyn = ctd.Dynamic(st.initial.dims, st.initial.idx, st.initial.val, 0, 30, seed=3)
+    grew = 0
+    for sl in st.slices:
+        info = dyn.update(sl.dims, sl.idx, sl.val, d=4)
+        grew += info["added"] > 0
+        ref = dyn.core_columns(np.arange(dyn.C.shape[1]))
+        cond = np.linalg.cond(dyn.R)
+        tol = max(1e-13, 2.0 ** -52 * cond ** 2 * 10)
+        assert np.abs(dyn.C - ref).max() <= tol * np.abs(ref).max()
+    assert grew >= 2
 
 
 def test_empty_delta_R_adds_columns_only():

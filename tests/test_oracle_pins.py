@@ -18,6 +18,8 @@ from workloads import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
+pytestmark = pytest.mark.filterwarnings("error::RuntimeWarning")
+
 
 def _dense(t):
     X = np.zeros(t.dims)
@@ -263,8 +265,19 @@ def test_planted_rank_is_recovered_exactly():
     assert r.R.shape[1] == 5
     assert r.rel_err <= 1e-12
     rn = ctd.ctd_s(noisy.dims, noisy.idx, noisy.val, 0, 200, seed=0)
-    # the noise floor: the projection can remove at most all of the signal
-    assert rn.rel_err <= 1.5 * 1e-4 * 1.01 + 0.5
+    # the noise floor: with X = S + N and span(R) holding the columns of the signal's
+    # unfolding S_(alpha), (I - P) X = (I - P) N, so the error is at most ||N||^2
+    un = rn.unfolding
+    uc = ctd.unfold(clean.dims, clean.idx, clean.val, 0)
+    S = np.zeros((un.n_rows, un.n_cols_total))
+    S[:, uc.fids] = uc.mat.toarray()
+    D = -S
+    D[:, un.fids] += un.mat.toarray()
+    Qh, _ = np.linalg.qr(rn.R)
+    assert np.linalg.norm(S - Qh @ (Qh.T @ S)) <= 1e-12 * np.linalg.norm(S)
+    noise_floor = float(np.sum(D * D)) / un.norm2
+    assert 0.5e-4 < noise_floor < 2e-4          # ||N|| = 1% of ||S|| by construction
+    assert rn.rel_err <= noise_floor * (1 + 1e-9)
 
 
 def test_figure2_example():
