@@ -177,6 +177,31 @@ ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d);
  * instead of once per slice.  1 <= B <= CTD_MAX_BATCH. */
 ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B, int64_t d);
 
+/* Checkpoint of a CTD-D stream.  Algorithm 2 (Section 3.2) carries R, U and C
+ * and the stream's error from each time step to the next; this call copies
+ * that state (R, the orthonormal Q = R M and M with U = M M^T, the row
+ * leverages, C, the fiber ids of R's and C's columns, the step t, the totals
+ * of Eq. 14 and the handle's internal sizes) into the host buffer `host_buf`
+ * of *bytes bytes, after waiting for the handle's stream.  On return *bytes
+ * holds the size the state needs (about (2 I_alpha + n_cols) d~ values plus
+ * the ids); host_buf == NULL only reports it (CTD_OK); a buffer smaller than
+ * that returns CTD_ERR_CAPACITY and writes nothing.  The buffer is plain
+ * bytes in this build's native layout (versioned header, then the arrays),
+ * owned by the caller.  Needs a CTD-D stream: a ctd_decompose with want_C on
+ * a non-time mode, with or without updates after it (else CTD_ERR_STATE). */
+ctd_status ctd_save_state(ctd_handle* h, void* host_buf, size_t* bytes);
+
+/* Resume a CTD-D stream from a checkpoint of ctd_save_state: the handle drops
+ * any stream it held and continues the saved one, so later ctd_update calls
+ * give the same draws, kept fibers and bits as on the handle that saved it.
+ * The handle must have been created with the saved precision and eps and
+ * with want_C (else CTD_ERR_STATE); a buffer that is not a complete state of
+ * this library version returns CTD_ERR_INVALID_ARG.  The host buffer is read
+ * before the call returns.  Afterwards ctd_get_result reports the stream's
+ * step, kept fibers, factors, C and error; the per-input fields of the last
+ * call before the save (draws, unique fibers, s, s', n_f) are empty. */
+ctd_status ctd_load_state(ctd_handle* h, const void* host_buf, size_t bytes);
+
 /* Many independent tensors in one call (the batched execution form of
  * CTD-S): tensor b of the host array Xs[0..B) gets Algorithm 1 with s[b]
  * draws in mode `mode`, its draws using Philox counter word tensor = b
@@ -256,7 +281,9 @@ ctd_status ctd_sync(ctd_handle* h);
 /* Wait for the stream and fill `out` (see ctd_result). */
 ctd_status ctd_get_result(ctd_handle* h, ctd_result* out);
 
-/* Message for the last error on this handle ("" if none). */
+/* Message for the last error on this handle ("" if none).  With h == NULL:
+ * the message of this thread's last failed ctd_create, if it failed for a
+ * runtime reason, else "null handle". */
 const char* ctd_last_error(const ctd_handle* h);
 
 void ctd_destroy(ctd_handle* h);

@@ -24,7 +24,8 @@ CTD_ERR_CAPACITY = 9
 EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
            "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result", "ctd_sync",
            "ctd_get_result", "ctd_last_error", "ctd_destroy", "ctd_attack_candidates",
-           "ctd_memory_usage", "ctd_sparse_core")
+           "ctd_memory_usage", "ctd_sparse_core", "ctd_save_state",
+           "ctd_load_state")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -70,10 +71,16 @@ _hip = None
 
 
 def load_library():
-    """Load libctd.so (built by build_lib.py); raise if it is missing."""
+    """Load libctd.so (built by build_lib.py); raise if it is missing.
+
+    torch is imported first: its HIP runtime must be the one libctd.so binds
+    to.  Loaded the other way round, the library's dependency would pull a
+    second HIP (and HSA) runtime from the system into the process, and
+    whichever initializes second finds no device."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run python paper_1710_03608_amd/build_lib.py")
     lib = ctypes.CDLL(LIB_PATH)
@@ -96,10 +103,12 @@ def load_library():
                                           ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     lib.ctd_memory_usage.argtypes = [c_vp, ctypes.POINTER(MemoryStruct)]
     lib.ctd_sparse_core.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]
+    lib.ctd_save_state.argtypes = [c_vp, c_vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ctd_load_state.argtypes = [c_vp, c_vp, ctypes.c_size_t]
     for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
                  "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
                  "ctd_sync", "ctd_get_result", "ctd_attack_candidates", "ctd_memory_usage",
-                 "ctd_sparse_core"):
+                 "ctd_sparse_core", "ctd_save_state", "ctd_load_state"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -195,7 +204,7 @@ class Ctd:
         h = c_vp()
         rc = lib.ctd_create(ctypes.byref(h), ctypes.byref(opt), c_vp(stream.cuda_stream))
         if rc != 0:
-            raise CtdError(rc, "ctd_create")
+            raise CtdError(rc, "ctd_create: " + lib.ctd_last_error(None).decode())
         self.h = h
         self._keep = []
 
@@ -275,18 +284,32 @@ class Ctd:
         """C_(alpha) = R^T X_(alpha) in compressed-column form (col_ptr, row_idx,
         vals as numpy arrays); device buffers sized from a first call with cap 0."""
         import torch
+        fn = self.lib.ctd_sparse_core
         n_f = self.result(arrays=False)["n_f"]
         col_ptr = torch.empty(n_f + 1, dtype=torch.int64, device="cuda")
         nnz = c_i64(0)
-        rc = self.lib.ctd_sparse_core(self.h, col_ptr.data_ptr(), None, None, 0, ctypes.byref(nnz))
+        rc = fn(self.h, col_ptr.data_ptr(), None, None, 0, ctypes.byref(nnz))
         if rc != CTD_ERR_CAPACITY or nnz.value == 0:
             self._check(rc)
         row_idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
         vals = torch.empty(max(nnz.value, 1), dtype=torch.float64, device="cuda")
-        self._check(self.lib.ctd_sparse_core(self.h, col_ptr.data_ptr(), row_idx.data_ptr(),
-                                          vals.data_ptr(), nnz.value, ctypes.byref(nnz)))
+        self._check(fn(self.h, col_ptr.data_ptr(), row_idx.data_ptr(), vals.data_ptr(), nnz.value,
+                       ctypes.byref(nnz)))
         n = nnz.value
         return (col_ptr.cpu().numpy(), row_idx[:n].cpu().numpy(), vals[:n].cpu().numpy())
+
+    def save_state(self):
+        """Checkpoint of the CTD-D stream as a numpy uint8 array (host memory)."""
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.ctd_save_state(self.h, None, ctypes.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.ctd_save_state(self.h, buf.ctypes.data_as(c_vp), ctypes.byref(n)))
+        return buf
+
+    def load_state(self, buf):
+        """Resume the CTD-D stream of a checkpoint made by save_state."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.ctd_load_state(self.h, buf.ctypes.data_as(c_vp), buf.nbytes))
 
     def memory_usage(self):
         """Eq. 15: nnz of C, U (structural) and R, nnz of the input, and the ratio."""

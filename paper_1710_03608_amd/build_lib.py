@@ -9,7 +9,7 @@ SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libctd.so")
 SOURCES = ["sort.hip", "fibers.hip", "sample.hip", "factor.hip", "basis.hip", "project.hip", "dynamic.hip",
-           "api.hip", "batch.hip", "readout.hip", "tune.hip", "sparse_c.hip"]
+           "api.hip", "batch.hip", "readout.hip", "tune.hip", "sparse_c.hip", "state_io.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

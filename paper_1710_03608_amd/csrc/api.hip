@@ -429,9 +429,15 @@ ctd_status run_static(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, i
 
 }  // namespace ctd
 
+namespace {
+// Message of the last failed ctd_create on this thread (there is no handle to hold it).
+thread_local std::string g_create_error;
+}  // namespace
+
 extern "C" {
 
 ctd_status ctd_create(ctd_handle** out, const ctd_options* opt, void* hip_stream) {
+  g_create_error.clear();
   if (!out) return CTD_ERR_INVALID_ARG;
   ctd_handle* h = new ctd_handle();
   h->stream = (hipStream_t)hip_stream;
@@ -450,7 +456,10 @@ ctd_status ctd_create(ctd_handle** out, const ctd_options* opt, void* hip_stream
     }
     h->opt = *opt;
   }
-  if (hipMalloc(&h->d_sc, sizeof(DevScalars)) != hipSuccess) {
+  const hipError_t e = hipMalloc(&h->d_sc, sizeof(DevScalars));
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipMalloc of the device scalars: ") + hipGetErrorName(e) + ": " +
+                     hipGetErrorString(e);
     (void)hipGetLastError();
     delete h;
     return CTD_ERR_OOM;
@@ -533,7 +542,10 @@ ctd_status ctd_get_result(ctd_handle* h, ctd_result* out) {
   return CTD_OK;
 }
 
-const char* ctd_last_error(const ctd_handle* h) { return h ? h->last_error.c_str() : "null handle"; }
+const char* ctd_last_error(const ctd_handle* h) {
+  if (h) return h->last_error.c_str();
+  return g_create_error.empty() ? "null handle" : g_create_error.c_str();
+}
 
 void ctd_destroy(ctd_handle* h) {
   if (!h) return;

@@ -768,6 +768,8 @@ ctd_status dyn_sync_sizes(ctd_handle* h) {
 
 }  // namespace
 
+ctd_status dyn_resize(ctd_handle* h, int64_t capD, int64_t capN) { return dyn_reserve(h, capD, capN); }
+
 void launch_reset_scalars(hipStream_t st, DevScalars* sc, bool keep_stream) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, sc, keep_stream);
 }

@@ -180,6 +180,8 @@ void launch_static_totals(hipStream_t st, DevScalars* sc);
 void launch_core_static(hipStream_t st, StaticBufs& b, int64_t n_rows, int64_t nnz_max,
                         DevScalars* sc);
 ctd_status dyn_begin(ctd_handle* h, const ctd_coo* X);
+// (Re)allocate the CTD-D state with at least these capacities, keeping what it holds.
+ctd_status dyn_resize(ctd_handle* h, int64_t capD, int64_t capN);
 void dyn_free(ctd_handle* h);
 void fill_result(ctd_handle* h, const DevScalars& sc, ctd_result* out);
 void batch_free_storage(BatchState* B);
