@@ -26,6 +26,7 @@ METRIC = ("nonzeros/sec and HBM GB/s (% roofline) for CTD-S/CTD-D, mixed vs FP64
           "error")
 PEAK_FP64_VALU = 78.6    # TFLOP/s, MI355X vector fp64
 PEAK_FP32_VALU = 157.3   # TFLOP/s, MI355X vector fp32
+PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense fp64 matrix
 PEAK_HBM = 8000.0        # GB/s
 S_DRAWS = 2000
 SEED = 0
@@ -266,23 +267,43 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(X):
-    """The oracle (numpy/scipy float64) on a bounded sample of the same workload."""
+def _oracle_runs(X, n, reps, threads):
+    """Wall times (s) of `reps` oracle CTD-S runs on the first n nonzeros of X with the
+    BLAS pool limited to `threads` (None: all), and the threads the pool used."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import ctd as ora
-    n = 2_000_000
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
-    t = time.perf_counter()
-    r = ora.ctd_s(X.dims, X.idx[:, :n], X.val[:n], 0, S_DRAWS, SEED)
-    dt = time.perf_counter() - t
-    return {"value": n / dt, "unit": "nnz/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"first {n} of the 5M nonzeros (a uniform 40% subset: COO order is random), "
+    times, kept = [], 0
+    with threadpool_limits(limits=threads):
+        used = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = ora.ctd_s(X.dims, X.idx[:, :n], X.val[:n], 0, S_DRAWS, SEED)
+            times.append(time.perf_counter() - t)
+            kept = len(r.accepted)
+    return sorted(times), int(used), kept
+
+
+def cpu_baseline(X, n=2_000_000, reps=3):
+    """The oracle (numpy/scipy float64) on a bounded sample of the same workload: the
+    median of `reps` runs with all BLAS threads (`value`), and one single-thread run."""
+    times, cores, kept = _oracle_runs(X, n, reps, None)
+    t1, _, _ = _oracle_runs(X, n, 1, 1)
+    med = times[len(times) // 2]
+    return {"value": n / med, "unit": "nnz/s", "cores": cores, "kind": "oracle",
+            "value_1_thread": n / t1[0],
+            "sample": (f"first {n} of the {X.nnz} nonzeros (a uniform subset: COO order is random), "
                        f"same dims, mode 0, s={S_DRAWS}, seed {SEED}; oracle CTD-S end to end "
                        f"(matricize, weights, Philox draws, independence loop, projection "
-                       f"error) in {dt:.1f} s, s~={len(r.accepted)}")}
+                       f"error), s~={kept}; median of {reps} runs with {cores} BLAS threads "
+                       f"({', '.join(f'{x:.1f}' for x in times)} s); one run with 1 thread "
+                       f"{t1[0]:.1f} s")}
+
+
+def basis_flops(n_rows, s_unique, s_tilde):
+    """Algorithmic flops of the independence filter and basis of one input: the Gram of
+    the candidates 2 I s'^2, the Cholesky with drop s'^3 / 3 multiply-adds and the
+    basis Q = R L^{-T} I s~^2 multiply-adds."""
+    return 2.0 * n_rows * s_unique ** 2 + 2.0 * s_unique ** 3 / 3 + 2.0 * n_rows * s_tilde ** 2
 
 
 def main():
@@ -303,6 +324,9 @@ def main():
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the sample-size sweep (Fig. 5 methodology) on the Haggle-shaped "
                          "tensor and print it as one JSON line")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="run only the CPU oracle on the full 5M-nonzero workload (median of 3 "
+                         "with all BLAS threads and with one) and print it as one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -317,6 +341,20 @@ def main():
 
     import paper_1710_03608_amd as ctd
     from workloads import synth
+
+    if args.cpu_baseline_full:
+        X = synth.traffic_5m()
+        out = {}
+        for label, threads in (("all_threads", None), ("one_thread", 1)):
+            times, used, kept = _oracle_runs(X, X.nnz, 3, threads)
+            med = times[len(times) // 2]
+            out[label] = {"threads": used, "runs_s": times, "median_s": med,
+                          "nnz_per_s": X.nnz / med, "s_tilde": kept}
+            log(f"oracle, {used} threads: {', '.join(f'{x:.1f}' for x in times)} s")
+        print(json.dumps({"cpu_baseline_full": {
+            "workload": "ctd_s_traffic_10000x10000x1000_nnz5000000_zipf1.2_s2000", "kind": "oracle",
+            "host_cpus": os.cpu_count(), **out}}), flush=True)
+        return
 
     if args.sparse_only:
         X = synth.traffic_5m()
@@ -427,6 +465,17 @@ def main():
                            "(z_f = Q^T x_f over fibers with >= 2 nonzeros)"),
                 "work": f"2 * s~ ({s_t}) * nnz in multi-nonzero fibers ({stats['nnz_multi']})",
                 "kernel_ms": spmm_ms}
+    # the independence filter and basis, the largest stage: algorithmic flops over its
+    # HIP-event time, against the float64 matrix-core peak
+    b_ms = m["stages_ms"]["basis"]
+    b_flops = basis_flops(X.dims[0], m["s_unique"], s_t)
+    basis_roof = {"bound": "mfma", "achieved": b_flops / (b_ms * 1e-3) / 1e12 if b_ms > 0 else 0.0,
+                  "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "kernel_ms": b_ms,
+                  "kernel": "independence filter and basis (k_blk_* sequence, float64 and "
+                            "double-double)",
+                  "work": (f"2 I s'^2 + s'^3/3 FMA + I s~^2 FMA with I = {X.dims[0]}, "
+                           f"s' = {m['s_unique']}, s~ = {s_t}")}
+    basis_roof["frac"] = basis_roof["achieved"] / basis_roof["peak"]
     # end-to-end algorithmic HBM bytes of one decomposition (float64): COO read
     # (12 + 8 B/nnz), sort passes, fiber layout, projection stream, Q once
     nnz = X.nnz
@@ -449,6 +498,7 @@ def main():
                    "n_f": stats["n_f"], "nnz_multi": stats["nnz_multi"]},
         "hbm_GBps_end_to_end": e2e_bytes / (m["ms_per_step"] * 1e-3) / 1e9,
         "roofline": roofline,
+        "basis_roofline": basis_roof,
         "modes": results,
         "oracle_rel_err": rel_o,
     }

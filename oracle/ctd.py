@@ -550,7 +550,8 @@ class Dynamic:
         info = dict(step=self.step, draws=u.fids[draws] + offset if len(draws) else draws,
                     uniq=u.fids[uniq] + offset if len(uniq) else uniq,
                     kept=kept, rho=np.array(rho), d_tilde=self.basis.k,
-                    added=self.basis.k - k_old, err2=self.err2, norm2=self.norm2)
+                    added=self.basis.k - k_old, err2=self.err2, norm2=self.norm2,
+                    n_cols=self.col_fids.shape[0])
         self.history.append(info)
         return info
 
