@@ -68,6 +68,7 @@ def test_many_tensors_full_size(many, precision):
         for b, t in enumerate(ts):
             r = h.batch_result(b, arrays=False)
             assert r["s"] == s[b] and 1 <= r["s_tilde"] <= min(r["s_unique"], t.dims[0]), b
-            assert 0.0 <= r["rel_err"] <= 1.0, b
+            # a tensor whose kept fibers span all its rows has error 0 up to rounding
+            assert -atol <= r["rel_err"] <= 1.0, (b, r["rel_err"])
     finally:
         h.close()
