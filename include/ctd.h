@@ -275,6 +275,23 @@ ctd_status ctd_memory_usage(ctd_handle* h, ctd_memory* out);
 ctd_status ctd_sparse_core(ctd_handle* h, int64_t* col_ptr, int32_t* row_idx, double* vals,
                         int64_t cap, int64_t* nnz_out);
 
+/* The same as ctd_sparse_core, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): this call allocates and frees nothing.  Its workspace
+ * (R's row pointers, (I_alpha + 1) int64; the scan's block sums; R's row
+ * lists, nnz(R) (int32, float64) pairs; each part aligned to 256 bytes) lives
+ * in a static device array of CTD_NOALLOC_SCRATCH_BYTES bytes that each GPU
+ * the library runs on holds until the process ends.  Arguments, outputs,
+ * the capacity protocol and the results are those of ctd_sparse_core;
+ * a workspace beyond the scratch size returns CTD_ERR_CAPACITY before any
+ * kernel touches it (I_alpha up to about 8M rows, nnz(R) up to about 5M at
+ * small I_alpha).  Every call on one GPU shares that GPU's scratch and leaves
+ * its contents behind (each call writes every workspace entry it reads before
+ * reading it), so calls that overlap on one GPU, from several handles or
+ * threads, race: the caller serializes them. */
+ctd_status ctd_sparse_core_noalloc(ctd_handle* h, int64_t* col_ptr, int32_t* row_idx, double* vals,
+                                int64_t cap, int64_t* nnz_out);
+
 /* Wait for the stream and return the latched device status. */
 ctd_status ctd_sync(ctd_handle* h);
 
@@ -293,6 +310,7 @@ void ctd_destroy(ctd_handle* h);
 #define CTD_MAX_DRAWS 16384
 #define CTD_MAX_BATCH 256
 #define CTD_MAX_TENSORS 65536
+#define CTD_NOALLOC_SCRATCH_BYTES (64u << 20)   /* per-GPU scratch of ctd_sparse_core_noalloc */
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ CTD_ERR_CAPACITY = 9
 EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
            "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result", "ctd_sync",
            "ctd_get_result", "ctd_last_error", "ctd_destroy", "ctd_attack_candidates",
-           "ctd_memory_usage", "ctd_sparse_core", "ctd_save_state",
+           "ctd_memory_usage", "ctd_sparse_core", "ctd_sparse_core_noalloc", "ctd_save_state",
            "ctd_load_state")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
@@ -103,12 +103,13 @@ def load_library():
                                           ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]
     lib.ctd_memory_usage.argtypes = [c_vp, ctypes.POINTER(MemoryStruct)]
     lib.ctd_sparse_core.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]
+    lib.ctd_sparse_core_noalloc.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]
     lib.ctd_save_state.argtypes = [c_vp, c_vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.ctd_load_state.argtypes = [c_vp, c_vp, ctypes.c_size_t]
     for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
                  "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
                  "ctd_sync", "ctd_get_result", "ctd_attack_candidates", "ctd_memory_usage",
-                 "ctd_sparse_core", "ctd_save_state", "ctd_load_state"):
+                 "ctd_sparse_core", "ctd_sparse_core_noalloc", "ctd_save_state", "ctd_load_state"):
         getattr(lib, name).restype = c_i32
     _lib = lib
     return lib
@@ -280,11 +281,13 @@ class Ctd:
     def sync(self):
         self._check(self.lib.ctd_sync(self.h))
 
-    def sparse_core(self):
+    def sparse_core(self, noalloc=False):
         """C_(alpha) = R^T X_(alpha) in compressed-column form (col_ptr, row_idx,
-        vals as numpy arrays); device buffers sized from a first call with cap 0."""
+        vals as numpy arrays); device buffers sized from a first call with cap 0.
+        noalloc=True calls ctd_sparse_core_noalloc (workspace in the library's
+        static scratch) instead of ctd_sparse_core."""
         import torch
-        fn = self.lib.ctd_sparse_core
+        fn = self.lib.ctd_sparse_core_noalloc if noalloc else self.lib.ctd_sparse_core
         n_f = self.result(arrays=False)["n_f"]
         col_ptr = torch.empty(n_f + 1, dtype=torch.int64, device="cuda")
         nnz = c_i64(0)

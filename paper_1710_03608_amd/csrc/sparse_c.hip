@@ -12,6 +12,7 @@
 // pass counts the nonzero entries per column, an exclusive scan gives the
 // column pointers, and a second pass, which repeats the same additions,
 // writes the entries in increasing a.
+#include <mutex>
 #include <string>
 
 #include "state.h"
@@ -201,8 +202,119 @@ using namespace ctd;
     }                                                                           \
   } while (0)
 
+namespace {
+
+// Scratch of ctd_sparse_core_noalloc: one array per GPU, resident until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is a stand-in, not a device address): the device address of
+// each GPU's copy is looked up once with hipGetSymbolAddress and kept.
+__device__ __align__(256) unsigned char scratch[CTD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (the GPU of the handle's stream).
+ctd_status scratch_address(ctd_handle* h, void** out) {
+  hipDevice_t dev = 0;
+  hipError_t e = hipStreamGetDevice(h->stream, &dev);
+  if (e != hipSuccess) return fail(h, CTD_ERR_HIP, std::string("hipStreamGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(h, CTD_ERR_CAPACITY, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return fail(h, CTD_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess)
+      return fail(h, CTD_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return fail(h, CTD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CTD_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace of one sparse-core call: R's row pointers, the scan's block sums
+// and R's row lists.  `base` null: each buffer is allocated (and freed by
+// release); otherwise they are carved from `base`, `cap` bytes long.
+struct CoreWs {
+  char* base = nullptr;
+  size_t cap = 0;
+  bool owned = false;
+  int64_t* rptr = nullptr;
+  int64_t* part = nullptr;
+  int32_t* rcol = nullptr;
+  double* rval = nullptr;
+  size_t head = 0;       // bytes of rptr and part in the carved layout
+
+  hipError_t front(int64_t n_rows, int64_t nparts) {
+    if (!base) {
+      owned = true;
+      hipError_t e = hipMalloc(&rptr, (size_t)(n_rows + 1) * sizeof(int64_t));
+      if (e != hipSuccess) return e;
+      return hipMalloc(&part, (size_t)nparts * sizeof(int64_t));
+    }
+    rptr = (int64_t*)base;
+    part = (int64_t*)(base + align256((size_t)(n_rows + 1) * sizeof(int64_t)));
+    head = align256((size_t)(n_rows + 1) * sizeof(int64_t)) + align256((size_t)nparts * sizeof(int64_t));
+    return hipSuccess;
+  }
+  static size_t front_bytes(int64_t n_rows, int64_t nparts) {
+    return align256((size_t)(n_rows + 1) * sizeof(int64_t)) + align256((size_t)nparts * sizeof(int64_t));
+  }
+  size_t lists_bytes(int64_t nnz_r) const {
+    const size_t n = (size_t)std::max<int64_t>(nnz_r, 1);
+    return align256(n * sizeof(double)) + align256(n * sizeof(int32_t));
+  }
+  hipError_t lists(int64_t nnz_r) {
+    const size_t n = (size_t)std::max<int64_t>(nnz_r, 1);
+    if (owned) {
+      hipError_t e = hipMalloc(&rcol, n * sizeof(int32_t));
+      if (e != hipSuccess) return e;
+      return hipMalloc(&rval, n * sizeof(double));
+    }
+    rval = (double*)(base + head);
+    rcol = (int32_t*)(base + head + align256(n * sizeof(double)));
+    return hipSuccess;
+  }
+  void release() {
+    if (!owned) return;
+    if (rptr) (void)hipFree(rptr);
+    if (part) (void)hipFree(part);
+    if (rcol) (void)hipFree(rcol);
+    if (rval) (void)hipFree(rval);
+  }
+};
+
+ctd_status sparse_core_impl(ctd_handle* h, int64_t* col_ptr, int32_t* row_idx, double* vals,
+                            int64_t cap, int64_t* nnz_out, char* ws_base, size_t ws_cap);
+
+}  // namespace
+
 extern "C" ctd_status ctd_sparse_core(ctd_handle* h, int64_t* col_ptr, int32_t* row_idx, double* vals,
                                    int64_t cap, int64_t* nnz_out) {
+  return sparse_core_impl(h, col_ptr, row_idx, vals, cap, nnz_out, nullptr, 0);
+}
+
+extern "C" ctd_status ctd_sparse_core_noalloc(ctd_handle* h, int64_t* col_ptr, int32_t* row_idx,
+                                           double* vals, int64_t cap, int64_t* nnz_out) {
+  if (!h) return CTD_ERR_INVALID_ARG;
+  void* p = nullptr;
+  const ctd_status st = scratch_address(h, &p);
+  if (st != CTD_OK) return st;
+  return sparse_core_impl(h, col_ptr, row_idx, vals, cap, nnz_out, (char*)p, CTD_NOALLOC_SCRATCH_BYTES);
+}
+
+namespace {
+
+ctd_status sparse_core_impl(ctd_handle* h, int64_t* col_ptr, int32_t* row_idx, double* vals,
+                            int64_t cap, int64_t* nnz_out, char* ws_base, size_t ws_cap) {
   if (!h) return CTD_ERR_INVALID_ARG;
   h->last_error.clear();
   if (!col_ptr || !nnz_out || cap < 0 || (cap > 0 && (!row_idx || !vals)))
@@ -227,32 +339,38 @@ extern "C" ctd_status ctd_sparse_core(ctd_handle* h, int64_t* col_ptr, int32_t* 
   const StaticBufs& b = h->sb;
   hipStream_t st = h->stream;
   ctd_status rc = CTD_OK;
-  int64_t *rptr = nullptr, *part = nullptr;
-  int32_t* rcol = nullptr;
-  double* rval = nullptr;
+  CoreWs ws;
+  ws.base = ws_base;
+  ws.cap = ws_cap;
   int64_t nnz_r = 0, nnz_c = 0;
   const int64_t nparts = std::max<int64_t>(
       1, (std::max(n_rows, n_f) + kScanTile - 1) / kScanTile);
+  if (ws_base && CoreWs::front_bytes(n_rows, nparts) + ws.lists_bytes(0) > ws_cap)
+    return fail(h, CTD_ERR_CAPACITY, "the workspace for " + std::to_string(n_rows) + " rows exceeds the " +
+                                         std::to_string(ws_cap) + "-byte scratch");
   const int waves = (int)std::max<int64_t>(1, std::min<int64_t>(4, kMaxLdsDoubles / std::max<int64_t>(k, 1)));
   const size_t lds = (size_t)waves * std::max<int64_t>(k, 1) * sizeof(double);
   const unsigned grid_rows = (unsigned)std::max<int64_t>(1, (n_rows * kWave + kBlock - 1) / kBlock);
   const unsigned grid_f = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, (n_f + waves - 1) / waves));
-  SC_HIP(hipMalloc(&rptr, (size_t)(n_rows + 1) * sizeof(int64_t)));
-  SC_HIP(hipMalloc(&part, (size_t)nparts * sizeof(int64_t)));
+  SC_HIP(ws.front(n_rows, nparts));
   // R's rows as lists
   hipLaunchKernelGGL(k_r_rowcount, dim3(grid_rows), dim3(kBlock), 0, st, res.R, res.ldr, n_rows, k,
-                     rptr);
-  scan_excl(st, rptr, n_rows, part);
-  SC_HIP(hipMemcpyAsync(&nnz_r, rptr + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                     ws.rptr);
+  scan_excl(st, ws.rptr, n_rows, ws.part);
+  SC_HIP(hipMemcpyAsync(&nnz_r, ws.rptr + n_rows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   SC_HIP(hipStreamSynchronize(st));
-  SC_HIP(hipMalloc(&rcol, (size_t)std::max<int64_t>(nnz_r, 1) * sizeof(int32_t)));
-  SC_HIP(hipMalloc(&rval, (size_t)std::max<int64_t>(nnz_r, 1) * sizeof(double)));
+  if (ws_base && ws.head + ws.lists_bytes(nnz_r) > ws_cap) {
+    rc = fail(h, CTD_ERR_CAPACITY, "R's " + std::to_string(nnz_r) + " nonzeros exceed the " +
+                                       std::to_string(ws_cap) + "-byte scratch");
+    goto done;
+  }
+  SC_HIP(ws.lists(nnz_r));
   hipLaunchKernelGGL(k_r_rowfill, dim3(grid_rows), dim3(kBlock), 0, st, res.R, res.ldr, n_rows, k,
-                     rptr, rcol, rval);
+                     ws.rptr, ws.rcol, ws.rval);
   // counts per column, pointers, total
   hipLaunchKernelGGL((k_c_columns<false>), dim3(grid_f), dim3(waves * kWave), lds, st, b.fptr, b.row,
-                     b.val, h->d_sc, k, rptr, rcol, rval, col_ptr, nullptr, nullptr);
-  scan_excl(st, col_ptr, n_f, part);
+                     b.val, h->d_sc, k, ws.rptr, ws.rcol, ws.rval, col_ptr, nullptr, nullptr);
+  scan_excl(st, col_ptr, n_f, ws.part);
   SC_HIP(hipMemcpyAsync(&nnz_c, col_ptr + n_f, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   SC_HIP(hipStreamSynchronize(st));
   *nnz_out = nnz_c;
@@ -262,13 +380,12 @@ extern "C" ctd_status ctd_sparse_core(ctd_handle* h, int64_t* col_ptr, int32_t* 
     goto done;
   }
   hipLaunchKernelGGL((k_c_columns<true>), dim3(grid_f), dim3(waves * kWave), lds, st, b.fptr, b.row,
-                     b.val, h->d_sc, k, rptr, rcol, rval, col_ptr, row_idx, vals);
+                     b.val, h->d_sc, k, ws.rptr, ws.rcol, ws.rval, col_ptr, row_idx, vals);
   SC_HIP(hipGetLastError());
   SC_HIP(hipStreamSynchronize(st));
 done:
-  if (rptr) (void)hipFree(rptr);
-  if (part) (void)hipFree(part);
-  if (rcol) (void)hipFree(rcol);
-  if (rval) (void)hipFree(rval);
+  ws.release();
   return rc;
 }
+
+}  // namespace

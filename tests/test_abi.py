@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
                             "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
                             "ctd_sync", "ctd_get_result", "ctd_last_error", "ctd_destroy",
                             "ctd_attack_candidates", "ctd_memory_usage", "ctd_sparse_core",
-                            "ctd_save_state", "ctd_load_state"])
+                            "ctd_sparse_core_noalloc", "ctd_save_state", "ctd_load_state"])
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libctd.so not built")
@@ -48,6 +48,7 @@ def test_binding_struct_layout_matches_exports():
     assert lib.ctd_attack_candidates(None, 1, None, None, 0, None, None) == 1
     assert lib.ctd_memory_usage(None, None) == 1
     assert lib.ctd_sparse_core(None, None, None, None, 0, None) == 1
+    assert lib.ctd_sparse_core_noalloc(None, None, None, None, 0, None) == 1
     assert lib.ctd_save_state(None, None, None) == 1
     assert lib.ctd_load_state(None, None, 0) == 1
 
@@ -76,6 +77,7 @@ for name, args in (("ctd_decompose", (None, None, 0, 1, 0)), ("ctd_update", (Non
                    ("ctd_update_batched", (None, None, 1, 1)), ("ctd_sync", (None,)),
                    ("ctd_get_result", (None, None)), ("ctd_memory_usage", (None, None)),
                    ("ctd_sparse_core", (None, None, None, None, 0, None)),
+                   ("ctd_sparse_core_noalloc", (None, None, None, None, 0, None)),
                    ("ctd_save_state", (None, None, None)), ("ctd_load_state", (None, None, 0)),
                    ("ctd_decompose_batched", (None, None, 1, 0, None, 0)),
                    ("ctd_get_batch_result", (None, 0, None)),
