@@ -253,6 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 // in registers while the current one is in the MFMAs.  C is read once per
 // 16 RT new rows.
 constexpr int kCrossCols = 256;
+
 template <int RT>
 __global__ __launch_bounds__(kCrossCols) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 3 : 1)))
 void k_cross_term(double* __restrict__ C, int64_t ldc,
@@ -457,7 +458,9 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term32(float* __restrict__
 // lane (i, g) reads rows k0 + 8 g .. + 8 of its column (32 bytes) as the B
 // operand as laid out (no permutation); Y is rounded to float32 and split as
 // it is staged in LDS.  Lane l holds D[4 (l / 16) + r][l % 16] of a 16 x 16
-// float32 tile.
+// float32 tile.  Each column tile of C is split just before its MFMAs (so the
+// next tile's split overlaps them and one tile's parts are live at a time:
+// two waves per SIMD); PF chunks of C and Y are in flight per wave.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 struct Split3 {
   bf8 hi, mid, lo;
@@ -476,8 +479,9 @@ __device__ inline Split3 split3(const float* x) {
   }
   return s;
 }
-template <int RT>
-__global__ __launch_bounds__(kCrossCols) void k_cross_term_bf3(float* __restrict__ C, int64_t ldc,
+template <int RT, int PF>
+__global__ __launch_bounds__(kCrossCols) __attribute__((amdgpu_waves_per_eu(2)))
+void k_cross_term_bf3(float* __restrict__ C, int64_t ldc,
                                                              const double* __restrict__ Yall,
                                                              int64_t ldy, int64_t ystride,
                                                              const int64_t* rng_all) {
@@ -515,14 +519,15 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term_bf3(float* __restrict
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = flt4{0, 0, 0, 0};
-    flt8 cf[4], yv;
-    auto load = [&](int64_t ch) {
+    // PF chunks of C (and of Y) in flight: slot u holds chunk ch0 + u
+    flt8 cf[PF][4], yv[PF];
+    auto load = [&](int64_t ch, flt8 (&cfs)[4], flt8& yvs) {
       const int64_t k = ch * 32 + 8 * g;
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
-        cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const flt8*)(cp[ct] + ch * 32)
-                                                 : flt8{0, 0, 0, 0, 0, 0, 0, 0};
-        cf[ct] = mask8(cf[ct], k);
+        cfs[ct] = (ch < nch && cin[ct] && k < d) ? *(const flt8*)(cp[ct] + ch * 32)
+                                                  : flt8{0, 0, 0, 0, 0, 0, 0, 0};
+        cfs[ct] = mask8(cfs[ct], k);
       }
       const int64_t ky = ch * 32 + 8 * yg;
       dbl4 ya = {0, 0, 0, 0}, yb = {0, 0, 0, 0};
@@ -530,43 +535,49 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term_bf3(float* __restrict
         ya = *(const dbl4*)(yrow + ch * 32);
         yb = *(const dbl4*)(yrow + ch * 32 + 4);
       }
-      yv = mask8(flt8{(float)ya[0], (float)ya[1], (float)ya[2], (float)ya[3],
-                      (float)yb[0], (float)yb[1], (float)yb[2], (float)yb[3]}, ky);
+      yvs = mask8(flt8{(float)ya[0], (float)ya[1], (float)ya[2], (float)ya[3],
+                       (float)yb[0], (float)yb[1], (float)yb[2], (float)yb[3]}, ky);
     };
-    load(0);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) load(u, cf[u], yv[u]);
     int buf = 0;
-    for (int64_t ch = 0; ch < nch; ++ch) {
-      if (yr < kRows) {
-        float yf[8];
+    for (int64_t ch0 = 0; ch0 < nch; ch0 += PF) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) yf[e] = yv[e];
-        Ys[buf][yr][yg] = split3(yf);
-      }
-      Split3 cs[4];
+      for (int u = 0; u < PF; ++u) {
+        const int64_t ch = ch0 + u;
+        if (ch >= nch) break;
+        if (yr < kRows) {
+          float yf[8];
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        float cf8[8];
+          for (int e = 0; e < 8; ++e) yf[e] = yv[u][e];
+          Ys[buf][yr][yg] = split3(yf);
+        }
+        __syncthreads();
+        Split3 ya[RT];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) cf8[e] = cf[ct][e];
-        cs[ct] = split3(cf8);
-      }
-      __syncthreads();
-      load(ch + 1);
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const Split3 ya = Ys[buf][rt * 16 + i][g];
+        for (int rt = 0; rt < RT; ++rt) ya[rt] = Ys[buf][rt * 16 + i][g];
+        // each column tile is split just before its MFMAs, so the split of the
+        // next tile overlaps them; the slot is refilled once all are split
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-          flt4 c = acc[rt][ct];
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.mid, cs[ct].mid, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.lo, cs[ct].hi, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.hi, cs[ct].lo, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.mid, cs[ct].hi, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.hi, cs[ct].mid, c, 0, 0, 0);
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya.hi, cs[ct].hi, c, 0, 0, 0);
+          float cf8[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) cf8[e] = cf[u][ct][e];
+          const Split3 cs = split3(cf8);
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            flt4 c = acc[rt][ct];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[rt].mid, cs.mid, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[rt].lo, cs.hi, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[rt].hi, cs.lo, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[rt].mid, cs.hi, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[rt].hi, cs.mid, c, 0, 0, 0);
+            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[rt].hi, cs.hi, c, 0, 0, 0);
+          }
         }
+        load(ch + PF, cf[u], yv[u]);
+        buf ^= 1;
       }
-      buf ^= 1;
     }
     // lane (i, g) holds D[4 g + r][i] of tile (rt, ct): new row rt * 16 + 4 g + r, column ct * 16 + i
 #pragma unroll
@@ -1100,7 +1111,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
         hipLaunchKernelGGL((k_cross_term32<1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
                            S.capD, Y, S.capD, ystride, rng);
       else
-        hipLaunchKernelGGL((k_cross_term_bf3<4>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
+        hipLaunchKernelGGL((k_cross_term_bf3<4, 1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
                            S.capD, Y, S.capD, ystride, rng);
     } else if (tiles > 0) {
       if (kept_max <= 16)
