@@ -19,11 +19,15 @@
 // product of the inverse transposed Cholesky factors.  Sizes are read on the
 // device, so one block is a fixed sequence of launches.
 //
-// For few inputs the first pass of the next block runs on a second stream:
-// its part against the columns already final while this block decides, its
-// part against this block's new columns (coefficients Q_new^T Y, equal to
-// Q_new^T x to working accuracy and exactly what is subtracted) while M and
-// the book-keeping finish.  Consecutive blocks use two sets of W, g and Y.
+// For few inputs the projection of block b + 1 runs on a second stream, in
+// two panels: both passes against the columns final once block b - 1 has
+// finished (while block b decides), then both passes against block b's new
+// columns (as soon as they are final, while M and the book-keeping finish).
+// Each panel is Gram-Schmidt applied twice against an orthonormal set, so the
+// residual ends orthogonal to both panels to working accuracy, as with the
+// two passes over all columns at once (the second panel's coefficients
+// Q_new^T Y equal Q_new^T x to working accuracy and are exactly what is
+// subtracted).  Consecutive blocks use two sets of W, g and Y.
 #include <algorithm>
 #include <vector>
 
@@ -129,11 +133,11 @@ __device__ inline double* y_of(const BasisDev& d, int64_t b0) {
   return d.Ybuf + blk_par(b0) * kB * d.a.n_rows;
 }
 
-// First-pass column ranges: the whole of [0, k) at once, or split into an
-// early part [0, kcut) (run ahead on a second stream against the columns
-// already final) and the late part [kcut, k) (the previous step's new
-// columns, at most 64, whose coefficients come from the early residual).
-enum Pass1 : int { kPassAll = 0, kPassEarly = 1, kPassLate = 2 };
+// Column ranges of a projection: the whole of [0, k) at once, or split into
+// an early panel [0, kcut) (run ahead on a second stream against the columns
+// already final) and the late panel [kcut, k) (the previous step's new
+// columns, at most 64, projected out of the early residual).
+enum Range : int { kAll = 0, kEarly = 1, kLate = 2 };
 
 __device__ inline int64_t blk_count(const DevScalars* sc, int64_t b0) {
   const int64_t sp = sc->status == 0 ? sc->s_unique : 0;
@@ -157,6 +161,17 @@ __device__ inline int64_t late_end(const BasisDev& d, int64_t b0) {
 __device__ inline int64_t late_work(const BasisDev& d, int64_t b0) {
   return late_end(d, b0) >= d.a.n_rows ? 0 : blk_count(d.sc, b0);
 }
+// Columns [lo, hi) of a range and the candidates of the step it serves.
+struct ColRange {
+  int64_t lo, hi, nb;
+};
+__device__ inline ColRange col_range(const BasisDev& d, int64_t b0, int range) {
+  const DevScalars* sc = d.sc;
+  const int64_t kc = d.kcut[blk_par(b0)];
+  if (range == kEarly) return {0, kc, kc >= d.a.n_rows ? 0 : blk_count(sc, b0)};
+  if (range == kLate) return {kc, late_end(d, b0), late_work(d, b0)};
+  return {0, (int64_t)sc->n_accept_total, blk_work(sc, b0, d.a.n_rows)};
+}
 
 // W[j][c] = sum_e v_e Q[r_e][c] for c in the first pass's range (all of
 // [0, k), or the early part [0, kcut)), and g[j] = ||x_{b0+j}||^2.
@@ -167,7 +182,7 @@ __device__ inline int64_t late_work(const BasisDev& d, int64_t b0) {
 constexpr int kWWaves = 8;
 constexpr int kWCols = 2 * kWave;
 __global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(const BasisDev* __restrict__ bd,
-                                                            int64_t b0, int pass) {
+                                                            int64_t b0, int range) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Q = d.a.Q;
   const int64_t ldq = d.a.ldq, ldw = d.a.cap;
@@ -177,14 +192,11 @@ __global__ __launch_bounds__(kWWaves * kWave) void k_blk_w(const BasisDev* __res
   const double* __restrict__ val = d.a.val;
   double* __restrict__ W = w_of(d, b0);
   double* __restrict__ g = g_of(d, b0);
-  const DevScalars* sc = d.sc;
   constexpr int kU = 16;
   __shared__ double part[kWWaves][kWCols];
   __shared__ double gpart[kWWaves];
-  const int64_t kc = d.kcut[blk_par(b0)];
-  const int64_t nb = pass == kPassEarly ? (kc >= d.a.n_rows ? 0 : blk_count(sc, b0))
-                                        : blk_work(sc, b0, d.a.n_rows);
-  const int64_t k = pass == kPassEarly ? kc : (int64_t)sc->n_accept_total;
+  const ColRange cr = col_range(d, b0, range);   // kAll or kEarly: lo = 0
+  const int64_t nb = cr.nb, k = cr.hi;
   const int j = blockIdx.y;
   const int64_t cbase = (int64_t)blockIdx.x * kWCols;
   if (j >= nb || (blockIdx.x > 0 && cbase >= k)) return;
@@ -249,35 +261,28 @@ constexpr int kGK = 32;       // reduction chunk
 
 // Y[r][j] = P[r][b0 + j] - sum_c Q[r][c] W[j][c] for every candidate j of
 // the block (residuals against span(Q)), into Ybuf (n_rows x 64), over the
-// first-pass range of columns: all of [0, k) or the early part [0, kcut)
-// (kPassAll, kPassEarly); the late part subtracts the rest, Ybuf[r][j] -=
-// sum_{kcut <= c < k} Q[r][c] W[j][c] (kPassLate); the second projection pass
-// subtracts Ybuf[r][j] -= sum_{c < k} Q[r][c] W2[j][c] (kReproject).  One
-// workgroup per 32 rows; wave w of a group computes rows 16 (w / 2) .. + 16
-// and candidates 32 (w % 2) .. + 32 with two f64 MFMA accumulators.
-constexpr int kReproject = 3;
+// columns of the range: all of [0, k) or the early panel [0, kcut) (kAll,
+// kEarly); the late panel subtracts the rest, Ybuf[r][j] -= sum_{kcut <= c <
+// k} Q[r][c] W[j][c].  With second set, the second pass over the range,
+// Ybuf[r][j] -= sum_c Q[r][c] W2[j][c].  One workgroup per 32 rows; wave w of
+// a group computes rows 16 (w / 2) .. + 16 and candidates 32 (w % 2) .. + 32
+// with two f64 MFMA accumulators.
 __global__ __launch_bounds__(kGemm) void k_blk_form_y(const BasisDev* __restrict__ bd, int64_t b0,
-                                                      int pass) {
+                                                      int range, int second) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ P = d.a.P;
   const double* __restrict__ Q = d.a.Q;
-  const bool reproject = pass == kReproject, subtract = reproject || pass == kPassLate;
-  const double* __restrict__ W = reproject ? d.W2 : w_of(d, b0);
+  const bool subtract = second || range == kLate;
+  const double* __restrict__ W = second ? d.W2 : w_of(d, b0);
   const int64_t ldp = d.a.ldp, n_rows = d.a.n_rows, ldq = d.a.ldq, ldw = d.a.cap;
   double* __restrict__ Ybuf = y_of(d, b0);
-  const DevScalars* sc = d.sc;
   constexpr int kR = 32;
   __shared__ double As[2][kR][kGK + 1];   // Q tile [row][c]
   __shared__ double Bs[2][kGK][kB + 1];   // W^T tile [c][j]
-  const int64_t kc = d.kcut[blk_par(b0)];
-  const int64_t nb = pass == kPassEarly  ? (kc >= n_rows ? 0 : blk_count(sc, b0))
-                     : pass == kPassLate ? late_work(d, b0)
-                                         : blk_work(sc, b0, n_rows);
+  const ColRange cr = col_range(d, b0, range);
+  const int64_t nb = cr.nb;
   if (nb == 0) return;
-  const int64_t klo = pass == kPassLate ? kc : 0;
-  const int64_t k = pass == kPassEarly  ? kc
-                    : pass == kPassLate ? late_end(d, b0)
-                                        : (int64_t)sc->n_accept_total;
+  const int64_t klo = cr.lo, k = cr.hi;
   if (subtract && klo >= k) return;
   const int64_t r0 = (int64_t)blockIdx.x * kR;
   if (r0 >= n_rows) return;
@@ -377,31 +382,30 @@ __device__ inline int64_t w2_tiles(const BasisDev& d, int64_t t_launch) {
   return t_launch < tc ? t_launch : tc;
 }
 
-// Second projection coefficients W2[j][c] = sum_r Q[r][c] Y[r][j] for c < k,
-// partial over w2_splits row ranges: workgroup (ct, s) covers c in
-// [64 ct, 64 ct + 64) and writes W2p[s][j][c] (row length 64 T); wave w of a
-// group computes c rows 16 w .. + 16 against all 64 j with four f64 MFMA
-// tiles.  With late set, the same for the late part of the first pass, the
-// previous step's new columns c in [kcut, k) (at most 64) against the early
-// residual: W[j][c] = sum_r Q[r][c] Y[r][j] (these columns are orthogonal to
-// the ones the early part removed, so this equals Q^T x to working accuracy,
-// and it is exactly the coefficient the late pass subtracts); T is then 1 and
-// W2p[s][j][c - kcut].
+// Projection coefficients Wp[j][c] = sum_r Q[r][c] Y[r][j] for the columns c
+// of the range, partial over w2_splits row ranges: workgroup (ct, s) covers c
+// in [lo + 64 ct, lo + 64 ct + 64) and writes W2p[s][j][c - lo] (row length
+// 64 T); wave w of a group computes c rows 16 w .. + 16 against all 64 j with
+// four f64 MFMA tiles.  Over all columns or the early panel these are the
+// second pass's coefficients; over the late panel (the previous step's new
+// columns, at most 64, T = 1) first the late panel's first-pass coefficients
+// (those columns are orthogonal to the early panel, so Q_new^T Y equals
+// Q_new^T x to working accuracy, and it is exactly what the late pass
+// subtracts), then its second pass.
 __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restrict__ bd,
-                                                       int64_t b0, int64_t t_launch, int late) {
+                                                       int64_t b0, int64_t t_launch, int range) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Q = d.a.Q;
   const double* __restrict__ Y = y_of(d, b0);
   double* __restrict__ W2p = d.W2p;
   const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows;
-  const int64_t T = late ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
+  const int64_t T = range == kLate ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
   const int nsplit = w2_splits(n_rows, T, gridDim.z);
-  const DevScalars* sc = d.sc;
   __shared__ double Qs[2][kGK][kB + 1];   // [r][c]
   __shared__ double Ys[2][kGK][kB + 1];   // [r][j]
-  const int64_t nb = late ? late_work(d, b0) : blk_work(sc, b0, d.a.n_rows);
-  const int64_t k = late ? late_end(d, b0) : (int64_t)sc->n_accept_total;
-  const int64_t cw = late ? d.kcut[blk_par(b0)] : 0;   // first column held
+  const ColRange cr = col_range(d, b0, range);
+  const int64_t nb = cr.nb, k = cr.hi;
+  const int64_t cw = cr.lo;   // first column held
   const int64_t c0 = cw + (int64_t)blockIdx.x * kB;
   if (nb == 0 || c0 >= k || (int)blockIdx.y >= nsplit) return;
   const int64_t chunk = (n_rows + nsplit - 1) / nsplit;
@@ -463,25 +467,27 @@ __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restric
     }
 }
 
-// W2[j][c] = sum_s W2p[s][j][c] (fixed order); W[j][c] += W2[j][c] (late:
-// W[j][kcut + c] = sum_s W2p[s][j][c] for the late first-pass columns).  A
+// s = sum_s W2p[s][j][c] (fixed order) for column lo + c of the range: with
+// second set W2[j][lo + c] = s and W[j][lo + c] += s (second-pass
+// coefficients), else W[j][lo + c] = s (the late panel's first pass).  A
 // workgroup takes 32 consecutive entries per pass, each summed by kW2Ways
 // threads over every kW2Ways-th partial (all loads in flight together), and
 // the ways are added in order.
 constexpr int kW2Ways = 8, kW2Per = kBlock / kW2Ways;
 __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restrict__ bd,
-                                                       int64_t b0, int64_t t_launch, int late) {
+                                                       int64_t b0, int64_t t_launch, int range,
+                                                       int second) {
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ W2p = d.W2p;
   double* __restrict__ W2 = d.W2;
   double* __restrict__ W = w_of(d, b0);
   const int64_t ldw = d.a.cap;
-  const int64_t T = late ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
+  const int64_t T = range == kLate ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
   const int nsplit = w2_splits(d.a.n_rows, T, gridDim.z);
-  const DevScalars* sc = d.sc;
-  const int64_t nb = late ? late_work(d, b0) : blk_work(sc, b0, d.a.n_rows);
-  const int64_t cw = late ? d.kcut[blk_par(b0)] : 0;   // first column
-  const int64_t k = (late ? late_end(d, b0) : (int64_t)sc->n_accept_total) - cw;   // columns
+  const ColRange cr = col_range(d, b0, range);
+  const int64_t nb = cr.nb;
+  const int64_t cw = cr.lo;          // first column
+  const int64_t k = cr.hi - cw;      // columns
   const int64_t total = k > 0 ? nb * k : 0;
   __shared__ double sh[kBlock];
   const int e = threadIdx.x % kW2Per, q = threadIdx.x / kW2Per;
@@ -504,11 +510,11 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
     __syncthreads();
     if (q == 0 && t < total) {
       for (int w = 1; w < kW2Ways; ++w) s += sh[w * kW2Per + e];
-      if (late) {
-        W[j * ldw + cw + c] = s;
+      if (second) {
+        W2[j * ldw + cw + c] = s;
+        W[j * ldw + cw + c] += s;
       } else {
-        W2[j * ldw + c] = s;
-        W[j * ldw + c] += s;
+        W[j * ldw + cw + c] = s;
       }
     }
     __syncthreads();
@@ -1602,82 +1608,80 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     };
     const dim3 wthreads(kWWaves * kWave);
     hipLaunchKernelGGL(k_begin_basis, dim3(1, 1, nz_all), dim3(1), 0, st, bd);
+    const int64_t s_all = hd[z0].a.s_max;
+    // W2 = Q^T Y over the columns of `range` (host bound kb), partial over row
+    // splits then summed, and Y -= Q W2^T: one projection pass of step bx
+    auto coef_pass = [&](hipStream_t s, int64_t bx, const Bounds& nx, int64_t kb, int range,
+                         int second) {
+      const int64_t tl = range == kLate ? 1 : div_up(kb, kB);
+      int w = 1;
+      for (int i = z0; i < z0 + nx.nz; ++i)
+        w = std::max(w, w2_splits(hd[i].a.n_rows,
+                                  range == kLate ? 1 : std::min<int64_t>(tl, div_up(kmax_of(hd[i].a), kB)),
+                                  nx.nz));
+      // (workgroups loop over their entries: with many inputs a few per input suffice)
+      const int sum_grid = std::max(1, std::min({4096, div_up((int64_t)kB * kb, kW2Per),
+                                                 std::max(8, 65536 / nx.nz)}));
+      hipLaunchKernelGGL(k_blk_w2_part, dim3(range == kLate ? 1 : tl, w, nx.nz), dim3(kGemm), 0, s,
+                         bd, bx, tl, range);
+      hipLaunchKernelGGL(k_blk_w2_sum, dim3(sum_grid, 1, nx.nz), dim3(kBlock), 0, s, bd, bx, tl,
+                         range, second);
+      hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0, s, bd,
+                         bx, range, second);
+    };
+    // both passes of step bx against the columns [0, kb) of range kAll or
+    // kEarly: the sparse coefficients Q^T x, Y = P - Q W^T, then the second pass
+    auto project = [&](hipStream_t s, int64_t bx, const Bounds& nx, int64_t kb, int range) {
+      hipLaunchKernelGGL(k_blk_w, dim3(div_up(kb, kWCols), kB, nx.nz), wthreads, 0, s, bd, bx,
+                         range);
+      hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0, s, bd,
+                         bx, range, 0);
+      coef_pass(s, bx, nx, kb, range, 1);
+    };
+    // With the side stream, step bx's early panel (the columns held once step
+    // bx - 2 finished, host bound kb) runs there as soon as that step's
+    // book-keeping is done, and its late panel (step bx - 1's new columns)
+    // once those are final; step bx then waits for done[bx's parity].
+    // The W2 partials and sums are shared by the two streams' passes, so the
+    // first early panel starts after step 0's own passes.
     bool done_ok[2] = {true, true};
-    for (int64_t b0 = 0; b0 < hd[z0].a.s_max; b0 += kB) {
+    for (int64_t b0 = 0; b0 < s_all; b0 += kB) {
       const Bounds bn = bounds(b0);
       const int nz = bn.nz;
       const int64_t k1 = std::max<int64_t>(bn.kub, 1);
-      const int rows_tiles32 = div_up(bn.rows, 32);
       const int rows4 = div_up(bn.rows, kB);
-      // column tiles of Q at this step (per input: capped by its capacity)
-      const int64_t t_launch = div_up(k1, kB);
-      int w_max = 1;
-      for (int i = z0; i < z0 + nz; ++i)
-        w_max = std::max(w_max, w2_splits(hd[i].a.n_rows,
-                                          std::min<int64_t>(t_launch, div_up(kmax_of(hd[i].a), kB)), nz));
       const int par = (int)((b0 / kB) & 1);
-      // first projection pass: at the first step (or without the side
-      // stream) all of it here; later both its parts ran on the side stream
-      // during the previous step (early: the columns then final; late: that
-      // step's new columns), and this step waits for them
       if (ahead && b0 > 0) {
-        // both parts ran on the side; a failed record or wait falls back to the host
+        // both panels ran on the side; a failed record or wait falls back to the host
         if (!done_ok[par] || hipStreamWaitEvent(st, side->done[par], 0) != hipSuccess) {
           (void)hipGetLastError();
           (void)hipStreamSynchronize(side->st);
         }
       } else {
-        hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nz), wthreads, 0, st, bd, b0,
-                           (int)kPassAll);
-        hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0,
-                           (int)kPassAll);
+        // block classical Gram-Schmidt against all of Q, twice
+        project(st, b0, bn, k1, kAll);
+        if (ahead && b0 == 0 && s_all > kB) {
+          order_after(side->st, st, side->start);
+          project(side->st, kB, bounds(kB), std::max<int64_t>(bn.kub, 1), kEarly);
+        }
       }
-      // second projection against Q (block classical Gram-Schmidt, twice)
-      hipLaunchKernelGGL(k_blk_w2_part, dim3(div_up(k1, kB), w_max, nz), dim3(kGemm), 0, st, bd, b0,
-                         t_launch, 0);
-      // (workgroups loop over their entries: with many inputs a few per input suffice)
-      const int sum_grid = std::max(1, std::min({4096, div_up((int64_t)kB * k1, kW2Per),
-                                                 std::max(8, 65536 / nz)}));
-      hipLaunchKernelGGL(k_blk_w2_sum, dim3(sum_grid, 1, nz), dim3(kBlock), 0, st, bd, b0, t_launch,
-                         0);
-      hipLaunchKernelGGL(k_blk_form_y, dim3(rows_tiles32, 1, nz), dim3(kGemm), 0, st, bd, b0,
-                         kReproject);
       if (nz <= kFewInputs)
         hipLaunchKernelGGL(k_blk_gram_dd<4>, dim3(bn.dd_max, 1, nz), dim3(kBlock * 4), 0, st, bd, b0);
       else
         hipLaunchKernelGGL(k_blk_gram_dd<1>, dim3(bn.dd_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
       hipLaunchKernelGGL(k_blk_sum_dd, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd, b0);
-      // early part of the next step's first pass, against the k columns held
-      // at the start of this step (final once the previous step finished),
-      // started as this step's single-workgroup decisions begin; it writes
-      // the other set of W, g and Ybuf
-      if (ahead && b0 + kB < hd[z0].a.s_max) {
-        const Bounds nx = bounds(b0 + kB);
-        order_after(side->st, st, side->start);
-        hipLaunchKernelGGL(k_blk_w, dim3(div_up(k1, kWCols), kB, nx.nz), wthreads, 0, side->st, bd,
-                           b0 + kB, (int)kPassEarly);
-        hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0,
-                           side->st, bd, b0 + kB, (int)kPassEarly);
-      }
       hipLaunchKernelGGL(k_blk_decide, dim3(1, 1, nz), dim3(kChol), 0, st, bd, b0);
       hipLaunchKernelGGL(k_blk_take, dim3(bn.take_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
       hipLaunchKernelGGL(k_blk_sum_parts, dim3(sums, 1, nz), dim3(kBlock), 0, st, bd);
       hipLaunchKernelGGL(k_blk_cholinv, dim3(1, 1, nz), dim3(kChol), 0, st, bd);
       hipLaunchKernelGGL(k_blk_apply, dim3(rows4, 1, nz), dim3(kBlock), 0, st, bd);
-      // late part of the next step's first pass: this step's new columns
-      // are final here, and M's new columns and the book-keeping follow on st
-      if (ahead && b0 + kB < hd[z0].a.s_max) {
+      // the late panel of the next step: this step's new columns are final
+      // here, and M's new columns and the book-keeping follow on st
+      if (ahead && b0 + kB < s_all) {
         const Bounds nx = bounds(b0 + kB);
-        int w_late = 1;
-        for (int i = z0; i < z0 + nx.nz; ++i)
-          w_late = std::max(w_late, w2_splits(hd[i].a.n_rows, 1, nx.nz));
         order_after(side->st, st, side->mid);
-        hipLaunchKernelGGL(k_blk_w2_part, dim3(1, w_late, nx.nz), dim3(kGemm), 0, side->st, bd,
-                           b0 + kB, (int64_t)1, 1);
-        hipLaunchKernelGGL(k_blk_w2_sum, dim3(div_up((int64_t)kB * kB, kW2Per), 1, nx.nz),
-                           dim3(kBlock), 0, side->st, bd, b0 + kB, (int64_t)1, 1);
-        hipLaunchKernelGGL(k_blk_form_y, dim3(div_up(nx.rows, 32), 1, nx.nz), dim3(kGemm), 0,
-                           side->st, bd, b0 + kB, (int)kPassLate);
+        coef_pass(side->st, b0 + kB, nx, kB, kLate, 0);
+        coef_pass(side->st, b0 + kB, nx, kB, kLate, 1);
         done_ok[1 - par] = hipEventRecord(side->done[1 - par], side->st) == hipSuccess;
         if (!done_ok[1 - par]) (void)hipGetLastError();
       }
@@ -1687,6 +1691,13 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
                          st, bd, b0, jw);
       hipLaunchKernelGGL(k_blk_newm_fin, dim3(div_up(k1, 32), 1, nz), dim3(kGemm), 0, st, bd, jw);
       hipLaunchKernelGGL(k_blk_finish, dim3(1, 1, nz), dim3(256), 0, st, bd, b0);
+      // the early panel of the step after next, against the columns held
+      // now: its W, g and Ybuf set (this step's) is free once finish has run
+      if (ahead && b0 + 2 * kB < s_all) {
+        order_after(side->st, st, side->start);
+        project(side->st, b0 + 2 * kB, bounds(b0 + 2 * kB),
+                std::max<int64_t>(bounds(b0 + kB).kub, 1), kEarly);
+      }
     }
     hipLaunchKernelGGL(k_lev, dim3(div_up(rows_all * kWave, kBlock), 1, nz_all), dim3(kBlock), 0, st,
                        bd);
