@@ -881,7 +881,7 @@ constexpr int kPanel = 8;
 __device__ uint64_t wg_chol_drop_blocked(LdsMat& Ah, LdsMat& Al, const double* gs, int n,
                                          double eps2, int64_t room, uint64_t* s_mask) {
   constexpr int kWaves = kChol / kWave;
-  const int w = threadIdx.x / kWave, i = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), i = lane_id();
   uint64_t mask = 0;   // wave 0's
   int kept = 0;
   for (int c0 = 0; c0 < n; c0 += kPanel) {
@@ -899,7 +899,9 @@ __device__ uint64_t wg_chol_drop_blocked(LdsMat& Ah, LdsMat& Al, const double* g
         const int j = c0 + jj;
         if (j >= n) break;
         const double dh = bcast(h[jj], j), dl = bcast(l[jj], j);
-        const bool keep = ((dh - eps2 * gs[j]) + dl > 0.0) && kept < room;
+        // the same in every lane: taken as a scalar branch
+        const bool keep =
+            __builtin_amdgcn_readfirstlane((((dh - eps2 * gs[j]) + dl > 0.0) && kept < room) ? 1 : 0);
         if (keep) {
           double rh, rl;
           dd_rsqrt(dh, dl, rh, rl);
@@ -928,16 +930,23 @@ __device__ uint64_t wg_chol_drop_blocked(LdsMat& Ah, LdsMat& Al, const double* g
     }
     __syncthreads();
     // A[i][c] -= sum_{j in panel} L[i][j] L[c][j] for c past the panel, i >= c
-    for (int c = c0 + kPanel + w; c < n; c += kWaves) {
-      if (i >= c && i < n) {
-        double ah = Ah[i][c], al = Al[i][c];
+    // (row i of the panel read once; L[c][j] is the same address in every lane)
+    if (i < n && c0 + kPanel + w < n) {
+      double lh[kPanel], ll[kPanel];
 #pragma unroll
-        for (int jj = 0; jj < kPanel; ++jj) {
-          const int j = c0 + jj;
-          dd_fnma(ah, al, Ah[i][j], Al[i][j], Ah[c][j], Al[c][j]);
+      for (int jj = 0; jj < kPanel; ++jj) {
+        lh[jj] = Ah[i][c0 + jj];
+        ll[jj] = Al[i][c0 + jj];
+      }
+      for (int c = c0 + kPanel + w; c < n; c += kWaves) {
+        if (i >= c) {
+          double ah = Ah[i][c], al = Al[i][c];
+#pragma unroll
+          for (int jj = 0; jj < kPanel; ++jj)
+            dd_fnma(ah, al, lh[jj], ll[jj], Ah[c][c0 + jj], Al[c][c0 + jj]);
+          Ah[i][c] = ah;
+          Al[i][c] = al;
         }
-        Ah[i][c] = ah;
-        Al[i][c] = al;
       }
     }
     __syncthreads();
@@ -952,10 +961,12 @@ __device__ uint64_t wg_chol_drop_blocked(LdsMat& Ah, LdsMat& Al, const double* g
 // restricted to the kept set is the inverse of the kept factor.  Ld (the
 // float64 L, built here) and X are kB x kB; wave w solves L x = e_c for its
 // columns c = w + 16 q by forward substitution, lane i holding row i, x_m
-// reaching the other lanes by readlane: no barrier inside the solve.
+// reaching the other lanes by readlane: no barrier inside the solve.  Lane
+// m's entry is final once step m has read it, so X is written after the solve.
 __device__ void wg_lower_inverse(const LdsMat& Ah, LdsMat& Ld, LdsMat& X, uint64_t mask, int n) {
   constexpr int kWaves = kChol / kWave;
-  const int tid = threadIdx.x, w = tid / kWave, i = lane_id();
+  const int tid = threadIdx.x, i = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
   for (int e = tid; e < kB * kB; e += kChol) {
     const int r = e / kB, c = e % kB;
     const bool kr = r < n && ((mask >> r) & 1ull), kc = c < n && ((mask >> c) & 1ull);
@@ -971,6 +982,7 @@ __device__ void wg_lower_inverse(const LdsMat& Ah, LdsMat& Ld, LdsMat& X, uint64
   double acc[kSlots];   // the wave's four columns advance together (independent chains)
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) acc[q] = i == w + kWaves * q ? 1.0 : 0.0;
+#pragma unroll 2
   for (int m = w; m < kB; ++m) {
     const double lim = Ld[i][m];
 #pragma unroll
@@ -979,13 +991,14 @@ __device__ void wg_lower_inverse(const LdsMat& Ah, LdsMat& Ld, LdsMat& X, uint64
       if (m >= c) {
         const double xm = bcast(acc[q] * inv_d, m);
         if (i > m) acc[q] = fma(-lim, xm, acc[q]);
-        if (i == m) X[m][c] = xm;
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < kSlots; ++q)
-    if (i < w + kWaves * q) X[i][w + kWaves * q] = 0.0;
+  for (int q = 0; q < kSlots; ++q) {
+    const int c = w + kWaves * q;
+    X[i][c] = i >= c ? acc[q] * inv_d : 0.0;   // X[m][c] = x_m, the value lane m gave
+  }
   __syncthreads();
 }
 
