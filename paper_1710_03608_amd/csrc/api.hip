@@ -120,7 +120,7 @@ struct PlanItem {
 };
 // The workspace of one CTD-S call (or one CTD-D slice), as a list of buffers.
 void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_C, bool want_R,
-                  int64_t max_cols, StaticBufs* b, std::vector<PlanItem>& items) {
+                  int64_t max_cols, int w2_sets, StaticBufs* b, std::vector<PlanItem>& items) {
   const int64_t n = std::max<int64_t>(nnz, 1);
   const int64_t ld = round8(s);
   const int64_t nb = (int64_t)segment_blocks(nnz);
@@ -148,7 +148,7 @@ void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_
   add(&b->accept, s * 4);
   add(&b->acc_fid, s * 8);
   add(&b->M, s * ld * 8);
-  add(&b->scratch, basis_scratch_doubles(n_rows, ld) * 8);
+  add(&b->scratch, basis_scratch_doubles(n_rows, ld, w2_sets) * 8);
   add(&b->Q, n_rows * ld * 8);
   add(&b->Qf, mixed ? n_rows * ld * 4 : 4);
   add(&b->lev, n_rows * 8);
@@ -169,7 +169,7 @@ size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool wan
                     int64_t max_cols) {
   StaticBufs tmp{};
   std::vector<PlanItem> items;
-  static_items(nnz, s, n_rows, mixed, want_C, want_R, max_cols, &tmp, items);
+  static_items(nnz, s, n_rows, mixed, want_C, want_R, max_cols, 1, &tmp, items);
   Arena A;
   for (auto& it : items) (void)A.take(it.bytes);
   return A.off;
@@ -183,7 +183,7 @@ ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bo
   const int64_t ld = round8(s);
   const int64_t long_ld = kProjSlices;
   std::vector<PlanItem> items;
-  static_items(nnz, s, n_rows, mixed, want_C, want_R, max_cols, b, items);
+  static_items(nnz, s, n_rows, mixed, want_C, want_R, max_cols, h->w2_sets, b, items);
   std::vector<size_t> offs;
   for (auto& it : items) offs.push_back((size_t)A.take(it.bytes));
   if (A.off > A.cap) {
@@ -376,6 +376,7 @@ ctd_status static_front(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay,
   ba->ldwa = 0;
   ba->scratch = b.scratch;
   ba->cap = b.ld;
+  ba->w2_sets = h->w2_sets;
   return CTD_OK;
 }
 

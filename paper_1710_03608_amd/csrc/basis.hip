@@ -54,8 +54,9 @@ struct BasisDev {
   BasisArgs a;
   DevScalars* sc;
   double* W;        // 2 x 64 x cap: Q^T x rows of the candidates (even, odd steps)
-  double* W2p;      // w2_splits x 64 x 64 T partial second-pass coefficients
-  double* W2;       // 64 x cap
+  double* W2p[2];   // w2_splits x 64 x 64 T partial coefficients (even, odd steps)
+  double* W2[2];    // 64 x cap second-pass coefficients (even, odd steps; one set
+                    // serves both when the passes of consecutive steps never overlap)
   double* part;     // ntake x 64 x 64 partial Grams of the new columns
   double* part_hi;  // nsplit_dd x 64 x 64 partial double-double Grams
   double* part_lo;
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_form_y(const BasisDev* __restrict
   const double* __restrict__ P = d.a.P;
   const double* __restrict__ Q = d.a.Q;
   const bool subtract = second || range == kLate;
-  const double* __restrict__ W = second ? d.W2 : w_of(d, b0);
+  const double* __restrict__ W = second ? d.W2[blk_par(b0)] : w_of(d, b0);
   const int64_t ldp = d.a.ldp, n_rows = d.a.n_rows, ldq = d.a.ldq, ldw = d.a.cap;
   double* __restrict__ Ybuf = y_of(d, b0);
   constexpr int kR = 32;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(kGemm) void k_blk_w2_part(const BasisDev* __restric
   const BasisDev& d = bd[blockIdx.z];
   const double* __restrict__ Q = d.a.Q;
   const double* __restrict__ Y = y_of(d, b0);
-  double* __restrict__ W2p = d.W2p;
+  double* __restrict__ W2p = d.W2p[blk_par(b0)];
   const int64_t ldq = d.a.ldq, n_rows = d.a.n_rows;
   const int64_t T = range == kLate ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
   const int nsplit = w2_splits(n_rows, T, gridDim.z);
@@ -478,8 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
                                                        int64_t b0, int64_t t_launch, int range,
                                                        int second) {
   const BasisDev& d = bd[blockIdx.z];
-  const double* __restrict__ W2p = d.W2p;
-  double* __restrict__ W2 = d.W2;
+  const double* __restrict__ W2p = d.W2p[blk_par(b0)];
+  double* __restrict__ W2 = d.W2[blk_par(b0)];
   double* __restrict__ W = w_of(d, b0);
   const int64_t ldw = d.a.cap;
   const int64_t T = range == kLate ? 1 : w2_tiles(d, t_launch), ldp = T * kB;
@@ -1522,10 +1523,10 @@ size_t w2p_doubles(int64_t n_rows, int64_t cap) {
   return w2p;
 }
 
-size_t basis_scratch_doubles(int64_t n_rows, int64_t cap) {
+size_t basis_scratch_doubles(int64_t n_rows, int64_t cap, int w2_sets) {
   const Splits sp = splits_for(n_rows);
   return (size_t)2 * kB * cap                       // W (two sets)
-         + w2p_doubles(n_rows, cap) + (size_t)kB * cap   // W2p, W2
+         + (w2_sets > 1 ? 2 : 1) * (w2p_doubles(n_rows, cap) + (size_t)kB * cap)   // W2p, W2
          + (size_t)sp.take * kB * kB                // part
          + (size_t)sp.dd * kB * kB * 2 + (size_t)kB * kB   // part_hi/lo, G_lo
          + (size_t)kB * kB * 3                      // G, Tcur, Tacc
@@ -1566,9 +1567,18 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
     d.a = a;
     d.sc = scs[order[i]];
     d.W = a.scratch;
-    d.W2p = d.W + (size_t)2 * kB * a.cap;
-    d.W2 = d.W2p + w2p_doubles(a.n_rows, a.cap);
-    d.part = d.W2 + (size_t)kB * a.cap;
+    d.W2p[0] = d.W + (size_t)2 * kB * a.cap;
+    d.W2[0] = d.W2p[0] + w2p_doubles(a.n_rows, a.cap);
+    double* after = d.W2[0] + (size_t)kB * a.cap;
+    if (a.w2_sets > 1) {
+      d.W2p[1] = after;
+      d.W2[1] = d.W2p[1] + w2p_doubles(a.n_rows, a.cap);
+      after = d.W2[1] + (size_t)kB * a.cap;
+    } else {
+      d.W2p[1] = d.W2p[0];
+      d.W2[1] = d.W2[0];
+    }
+    d.part = after;
     d.part_hi = d.part + (size_t)sp.take * kB * kB;
     d.part_lo = d.part_hi + (size_t)sp.dd * kB * kB;
     d.Glo = d.part_lo + (size_t)sp.dd * kB * kB;
@@ -1594,7 +1604,13 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
   constexpr int kMaxZ = 65535;
   // the side stream fills CUs that single-workgroup steps leave idle: with
   // many inputs in a launch those steps fill the GPU by themselves
-  const bool ahead = side && side->st && count <= kFewInputs;
+  const bool ahead = side && side->st[0] && count <= kFewInputs;
+  // steps of either parity on a stream of their own when every input holds two
+  // sets of the W2 buffers: the late panel of step b + 1 then overlaps the
+  // early panel of step b + 2
+  bool two = ahead && side->st[1];
+  for (int i = 0; i < count; ++i) two = two && args[i].w2_sets > 1;
+  auto sst = [&](int64_t bx) { return side->st[two ? (int)((bx / kB) & 1) : 0]; };
   for (int z0 = 0; z0 < count; z0 += kMaxZ) {
     const int nz_all = std::min(kMaxZ, count - z0);
     const BasisDev* bd = dd + z0;
@@ -1668,14 +1684,14 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
         // both panels ran on the side; a failed record or wait falls back to the host
         if (!done_ok[par] || hipStreamWaitEvent(st, side->done[par], 0) != hipSuccess) {
           (void)hipGetLastError();
-          (void)hipStreamSynchronize(side->st);
+          (void)hipStreamSynchronize(sst(b0));
         }
       } else {
         // block classical Gram-Schmidt against all of Q, twice
         project(st, b0, bn, k1, kAll);
         if (ahead && b0 == 0 && s_all > kB) {
-          order_after(side->st, st, side->start);
-          project(side->st, kB, bounds(kB), std::max<int64_t>(bn.kub, 1), kEarly);
+          order_after(sst(kB), st, side->start);
+          project(sst(kB), kB, bounds(kB), std::max<int64_t>(bn.kub, 1), kEarly);
         }
       }
       if (nz <= kFewInputs)
@@ -1692,10 +1708,11 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       // here, and M's new columns and the book-keeping follow on st
       if (ahead && b0 + kB < s_all) {
         const Bounds nx = bounds(b0 + kB);
-        order_after(side->st, st, side->mid);
-        coef_pass(side->st, b0 + kB, nx, kB, kLate, 0);
-        coef_pass(side->st, b0 + kB, nx, kB, kLate, 1);
-        done_ok[1 - par] = hipEventRecord(side->done[1 - par], side->st) == hipSuccess;
+        hipStream_t s1 = sst(b0 + kB);
+        order_after(s1, st, side->mid);
+        coef_pass(s1, b0 + kB, nx, kB, kLate, 0);
+        coef_pass(s1, b0 + kB, nx, kB, kLate, 1);
+        done_ok[1 - par] = hipEventRecord(side->done[1 - par], s1) == hipSuccess;
         if (!done_ok[1 - par]) (void)hipGetLastError();
       }
       // M's new columns: split over j for few inputs, whole for many
@@ -1707,8 +1724,8 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
       // the early panel of the step after next, against the columns held
       // now: its W, g and Ybuf set (this step's) is free once finish has run
       if (ahead && b0 + 2 * kB < s_all) {
-        order_after(side->st, st, side->start);
-        project(side->st, b0 + 2 * kB, bounds(b0 + 2 * kB),
+        order_after(sst(b0 + 2 * kB), st, side->start);
+        project(sst(b0 + 2 * kB), b0 + 2 * kB, bounds(b0 + 2 * kB),
                 std::max<int64_t>(bounds(b0 + kB).kub, 1), kEarly);
       }
     }
@@ -1722,7 +1739,8 @@ bool basis_side_init(BasisSide* side) {
   // the events order work between two streams of one device: a device-scope
   // release suffices (no system-scope cache writeback at each record)
   const unsigned fl = hipEventDisableTiming | hipEventReleaseToDevice;
-  bool ok = hipStreamCreateWithFlags(&side->st, hipStreamNonBlocking) == hipSuccess;
+  bool ok = hipStreamCreateWithFlags(&side->st[0], hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&side->st[1], hipStreamNonBlocking) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&side->start, fl) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&side->mid, fl) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&side->done[0], fl) == hipSuccess;
@@ -1735,7 +1753,8 @@ bool basis_side_init(BasisSide* side) {
 }
 
 void basis_side_free(BasisSide* side) {
-  if (side->st) (void)hipStreamDestroy(side->st);
+  for (hipStream_t& x : side->st)
+    if (x) (void)hipStreamDestroy(x);
   if (side->start) (void)hipEventDestroy(side->start);
   if (side->mid) (void)hipEventDestroy(side->mid);
   for (hipEvent_t& e : side->done)

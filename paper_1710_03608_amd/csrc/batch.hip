@@ -35,6 +35,7 @@ ctd_status new_sub(ctd_handle* h, ctd_handle** out) {
   ctd_handle* sub = new ctd_handle();
   sub->opt = h->opt;
   sub->keep_R = false;
+  sub->w2_sets = 1;
   if (hipMalloc(&sub->d_sc, sizeof(DevScalars)) != hipSuccess) {
     (void)hipGetLastError();
     delete sub;

@@ -660,6 +660,7 @@ void launch_cols(hipStream_t st, const StaticBufs& b, int64_t nnz_max, DevScalar
       cols(c);
       (void)hipEventRecord(tev[2 * c + 1], st);
     }
+    tune_recorded(TUNE_COLS_FPW, prec, bucket);
   } else {
     cols(choice);
   }
@@ -997,7 +998,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
   // workspace: block-filter scratch, W rows of the batch's kept fibers, cross
   // rows, slice records and pass ranges
   const int64_t kept_max = std::min<int64_t>(n_rows, (int64_t)B * d);
-  const size_t ws_doubles = basis_scratch_doubles(n_rows, S.capD) +
+  const size_t ws_doubles = basis_scratch_doubles(n_rows, S.capD, 2) +
                             (size_t)(1 + B) * kept_max * S.capD + (size_t)2 * (B + 1) +
                             (size_t)5 * B + 64;
   if (ws_doubles * 8 > S.ws_bytes) {
@@ -1014,7 +1015,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
     S.ws_bytes = ws_doubles * 8;
   }
   double* scratch = (double*)S.ws;
-  double* Wacc = scratch + basis_scratch_doubles(n_rows, S.capD);
+  double* Wacc = scratch + basis_scratch_doubles(n_rows, S.capD, 2);
   double* Y = Wacc + (size_t)kept_max * S.capD;
   int64_t* info = (int64_t*)(Y + (size_t)B * kept_max * S.capD);   // Y: one block per pass
   int64_t* rng = info + 2 * (B + 1);
@@ -1067,6 +1068,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       ba.ldwa = S.capD;
       ba.scratch = scratch;
       ba.cap = S.capD;
+      ba.w2_sets = 2;
       rc = ensure_bdev(h, 1);
       if (rc != CTD_OK) return rc;
       launch_basis(st, &ba, &sc, 1, h->bdev, basis_side(h));

@@ -16,11 +16,14 @@ namespace ctd {
 // (tune_bucket(n) = ceil(log2 n)).  tune_get returns the chosen variant or -1
 // (undecided; a finished measurement is resolved here).  tune_begin returns
 // true, with 2 events per candidate, when the caller should time every
-// candidate now (event 2c before candidate c, 2c + 1 after it).
+// candidate now (event 2c before candidate c, 2c + 1 after it), and then
+// tune_recorded once every record is enqueued: until then no other thread
+// reads the events.  The table is shared by the threads of a process.
 enum { TUNE_PROJ_FPW = 0, TUNE_COLS_FPW = 1 };
 int tune_bucket(int64_t n);
 int tune_get(int knob, int prec, int bucket, int ncand);
 bool tune_begin(int knob, int prec, int bucket, int ncand, std::vector<hipEvent_t>* evs);
+void tune_recorded(int knob, int prec, int bucket);
 
 // ---- sort.hip --------------------------------------------------------------
 // Stable LSD radix sort of (key, payload) pairs on the low `nbits` bits of the
@@ -119,30 +122,31 @@ struct BasisArgs {
   uint64_t id_offset;        // added to fiber ids written to acc_fid
   double* Wacc;              // optional: Q^T x rows of the kept fibers (this call)
   int64_t ldwa;
-  double* scratch;           // basis_scratch_doubles(n_rows, cap)
+  double* scratch;           // basis_scratch_doubles(n_rows, cap, w2_sets)
   int64_t cap;               // column capacity of Q, M, W (>= final k + 64)
+  int w2_sets;               // 2: room for the side streams of a single input
 };
-size_t basis_scratch_doubles(int64_t n_rows, int64_t cap);
+size_t basis_scratch_doubles(int64_t n_rows, int64_t cap, int w2_sets);
 // Device bytes of the argument array for `count` inputs.
 size_t basis_dev_bytes(int count);
-// A second stream (default priority, non-blocking) and events on which the
-// first projection pass of each block step runs ahead, against the columns of
-// Q already final, while the previous step decides.  Owned by the caller.
+// Two more streams (default priority, non-blocking), one per block parity,
+// and events: the projection passes of each block step run there ahead of
+// the step, against the columns of Q already final.  Owned by the caller.
 struct BasisSide {
-  hipStream_t st = nullptr;
+  hipStream_t st[2] = {nullptr, nullptr};
   hipEvent_t start = nullptr, mid = nullptr;
   hipEvent_t done[2] = {nullptr, nullptr};
 };
-// Creates the stream and events on the current device; false (and nothing
+// Creates the streams and events on the current device; false (and nothing
 // held) if any creation fails.
 bool basis_side_init(BasisSide* side);
 void basis_side_free(BasisSide* side);
 // The basis of `count` independent inputs (args[i] with scalars scs[i]) in one
 // sequence of launches on st; dev holds basis_dev_bytes(count) device bytes
 // that stay untouched by others until the launches have run.  With a side
-// (may be null), part of each step runs on side->st, joined back to st by
-// events before the step's results are used: the work as a whole is ordered
-// on st like a single-stream launch sequence.
+// (may be null), part of each step runs on the side streams, joined back to
+// st by events before the step's results are used: the work as a whole is
+// ordered on st like a single-stream launch sequence.
 void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs, int count,
                   void* dev, BasisSide* side);
 

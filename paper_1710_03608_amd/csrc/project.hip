@@ -364,6 +364,7 @@ void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevSc
       multi(c);
       (void)hipEventRecord(tev[2 * c + 1], st);
     }
+    tune_recorded(TUNE_PROJ_FPW, prec, bucket);
   } else {
     multi(choice);
   }

@@ -136,6 +136,7 @@ struct ctd_handle {
   bool dyn_ready = false;
   bool last_was_update = false;
   bool keep_R = true;               // keep the dense kept fibers R (not needed inside a batch)
+  int w2_sets = 2;                  // basis W2 buffer sets (1 inside a batch: no side streams)
   int64_t nnz_seen = 0;             // nonzeros of all input held (CTD-D: initial plus slices)
   void* bdev = nullptr;             // device array of basis arguments
   int bdev_cap = 0;

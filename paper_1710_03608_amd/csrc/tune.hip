@@ -21,6 +21,7 @@ namespace {
 struct Entry {
   int choice = -1;
   std::vector<hipEvent_t> ev;   // 2 per candidate while a measurement is pending
+  bool recorded = false;        // the measuring caller has enqueued every record
 };
 
 std::mutex g_mu;
@@ -66,7 +67,9 @@ int tune_get(int knob, int prec, int bucket, int ncand) {
   if (it == g_table.end()) return -1;
   Entry& e = it->second;
   if (e.choice >= 0 && e.choice < ncand) return e.choice;
-  if ((int)e.ev.size() != 2 * ncand) return -1;
+  // a measurement another thread is still enqueueing (an event not yet
+  // recorded also reads as complete) is not looked at
+  if ((int)e.ev.size() != 2 * ncand || !e.recorded) return -1;
   if (hipEventQuery(e.ev.back()) != hipSuccess) {
     (void)hipGetLastError();   // not ready yet
     return -1;
@@ -108,6 +111,12 @@ bool tune_begin(int knob, int prec, int bucket, int ncand, std::vector<hipEvent_
   g_table[key].ev = ev;
   *evs = ev;
   return true;
+}
+
+void tune_recorded(int knob, int prec, int bucket) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_table.find(key_of(knob, prec, bucket));
+  if (it != g_table.end()) it->second.recorded = true;
 }
 
 }  // namespace ctd
