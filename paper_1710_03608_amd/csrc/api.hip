@@ -559,6 +559,7 @@ void ctd_destroy(ctd_handle* h) {
     if (B->start) (void)hipEventDestroy(B->start);
     if (B->based) (void)hipEventDestroy(B->based);
     for (hipStream_t st : B->pool) (void)hipStreamDestroy(st);
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
     ctd::batch_free_storage(B);
     delete B;
   }

@@ -9,6 +9,9 @@
 // span all tensors of the group.  The caller's stream is joined with events
 // at entry and exit.  After each tensor its scalars and index arrays are
 // copied into storage owned by the batch.
+#include <stdlib.h>
+#include <string.h>
+
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -72,6 +75,45 @@ void batch_free_storage(BatchState* B) {
 
 using namespace ctd;
 
+namespace {
+// Everything a batched call's launches depend on: the options, mode and seed,
+// and per tensor its shape, nonzero count, sample size and input pointers.
+std::vector<uint64_t> batch_signature(const ctd_handle* h, const ctd_coo* Xs, int32_t nb,
+                                      int32_t mode, const int64_t* s, uint64_t seed) {
+  std::vector<uint64_t> g;
+  uint64_t eps_bits = 0;
+  static_assert(sizeof(eps_bits) == sizeof(h->opt.eps), "eps is a double");
+  memcpy(&eps_bits, &h->opt.eps, sizeof(eps_bits));
+  g.insert(g.end(), {(uint64_t)nb, (uint64_t)(uint32_t)mode, seed, (uint64_t)h->opt.precision, eps_bits,
+                     (uint64_t)h->opt.want_C, (uint64_t)h->opt.want_fiber_stats,
+                     (uint64_t)h->opt.profile});
+  for (int b = 0; b < nb; ++b) {
+    const ctd_coo& X = Xs[b];
+    g.insert(g.end(), {(uint64_t)X.order, (uint64_t)X.nnz, (uint64_t)(uintptr_t)X.idx,
+                       (uint64_t)(uintptr_t)X.val, (uint64_t)X.val_dtype, (uint64_t)s[b]});
+    for (int m = 0; m < X.order; ++m) g.push_back((uint64_t)X.dims[m]);
+  }
+  return g;
+}
+
+void drop_graph(BatchState& B) {
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  B.exec = nullptr;
+  B.graph_sig.clear();
+}
+
+ctd_status batched_body(ctd_handle* h, const ctd_coo* Xs, int32_t nb, int32_t mode,
+                        const int64_t* s, uint64_t seed, const std::vector<FiberLayout>& lays,
+                        int64_t total_s);
+}  // namespace
+
+// Host checks, then the launches of the call, or the replay of a graph of
+// them: a call with the same signature as the call before it is captured
+// (its work then runs as a graph launch), and later calls with that
+// signature replay the graph.  Between calls nothing the launches read on
+// the host changes: with the same sizes no workspace is reallocated, and the
+// autotuner's choices were settled by the earlier calls.  Any failure of
+// capture, instantiation or launch falls back to direct launches.
 extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, int32_t nb,
                                             int32_t mode, const int64_t* s, uint64_t seed) {
   if (!h) return CTD_ERR_INVALID_ARG;
@@ -93,6 +135,50 @@ extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, in
     total_s += s[b];
   }
   if (!h->batch) h->batch = new BatchState();
+  BatchState& B = *h->batch;
+  std::vector<uint64_t> sig = batch_signature(h, Xs, nb, mode, s, seed);
+  if (B.exec && sig == B.graph_sig) {
+    if (hipGraphLaunch(B.exec, h->stream) == hipSuccess) {
+      B.host_valid = false;
+      return CTD_OK;
+    }
+    (void)hipGetLastError();
+    drop_graph(B);
+  }
+  drop_graph(B);
+  const char* off = getenv("CTD_NO_GRAPH");
+  const bool capture = sig == B.last_sig && !(off && *off && *off != '0');
+  B.last_sig = sig;
+  if (!capture) return batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
+  if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
+  }
+  ctd_status rc = batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->stream, &g);
+  hipGraphExec_t x = nullptr;
+  bool ok = rc == CTD_OK && ec == hipSuccess && g &&
+            hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  ok = ok && hipGraphLaunch(x, h->stream) == hipSuccess;
+  if (ok) {
+    B.exec = x;
+    B.graph_sig = sig;
+    return CTD_OK;
+  }
+  // nothing of the captured work ran: run it directly
+  (void)hipGetLastError();
+  if (x) (void)hipGraphExecDestroy(x);
+  B.last_sig.clear();
+  h->last_error.clear();
+  return batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
+}
+
+namespace {
+ctd_status batched_body(ctd_handle* h, const ctd_coo* Xs, int32_t nb, int32_t mode,
+                        const int64_t* s, uint64_t seed, const std::vector<FiberLayout>& lays,
+                        int64_t total_s) {
   BatchState& B = *h->batch;
   while ((int)B.pool.size() < kBatchStreams) {
     hipStream_t st = nullptr;
@@ -213,6 +299,8 @@ extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, in
   }
   return CTD_OK;
 }
+
+}  // namespace
 
 extern "C" ctd_status ctd_get_batch_result(ctd_handle* h, int32_t b, ctd_result* out) {
   if (!h) return CTD_ERR_INVALID_ARG;

@@ -110,6 +110,11 @@ struct BatchState {
   size_t cap_s = 0;
   std::vector<DevScalars> host;
   bool host_valid = false;
+  // A repeated call with the same inputs and sizes replays a captured graph
+  // of its launches (see ctd_decompose_batched).
+  std::vector<uint64_t> last_sig;  // the previous call's signature
+  std::vector<uint64_t> graph_sig; // the signature exec was captured for
+  hipGraphExec_t exec = nullptr;
 };
 
 }  // namespace ctd

@@ -127,3 +127,68 @@ def test_few_tensors_with_many_blocks(lib, precision):
             assert abs(g["rel_err"] - o.rel_err) <= rtol * o.rel_err + atol, (b, g["rel_err"], o.rel_err)
     finally:
         h.close()
+
+
+def _batch_snapshot(h, n):
+    out = []
+    for b in range(n):
+        r = h.batch_result(b)
+        out.append((r["draws"].copy(), r["unique"].copy(), r["counts"].copy(), r["accepted"].copy(),
+                    r["scale"].copy(), r["prob"].copy(), r["err2"], r["norm2"], r["s_tilde"], r["s_unique"]))
+    return out
+
+
+def _same(a, b):
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            if isinstance(u, np.ndarray):
+                assert u.dtype == v.dtype and np.array_equal(u.view(np.uint8), v.view(np.uint8))
+            else:
+                assert u == v
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_repeated_calls_replay_a_graph_bit_identically(lib, precision):
+    """A batched call repeated with the same inputs and sizes is captured once
+    (second call) and replayed after that: every replay, with eager work and
+    synchronizations of the program between them, gives the eager call's bits;
+    a call with other sizes runs directly, and a replay reads the current
+    values of the (same) input buffers."""
+    import torch
+    ts = _tensors(19, 7)
+    s = _sizes(ts)
+    devs = [lib.to_device(t, "cuda") for t in ts]
+    h = lib.Ctd(precision=precision)
+    other = lib.Ctd(precision=precision)
+    try:
+        h.decompose_batched(devs, 0, s, 5)
+        ref = _batch_snapshot(h, len(ts))
+        for rep in range(5):                      # capture at rep 0, replays after it
+            h.decompose_batched(devs, 0, s, 5)
+            other.decompose(*devs[rep], 0, s[rep], 9)   # eager work in between
+            other.result()
+            torch.cuda.synchronize()
+            _same(_batch_snapshot(h, len(ts)), ref)
+        s2 = list(s)
+        s2[0] += 1                                # another signature: direct launches
+        h.decompose_batched(devs, 0, s2, 5)
+        o = ora.ctd_s(ts[0].dims, ts[0].idx, ts[0].val, 0, s2[0], 5, tensor=0)
+        assert np.array_equal(h.batch_result(0)["accepted"], o.accepted.astype(np.uint64))
+        for rep in range(3):                      # back: direct, capture, replay
+            h.decompose_batched(devs, 0, s, 5)
+            _same(_batch_snapshot(h, len(ts)), ref)
+        # new values in the same buffers of tensor 3: the replay reads them
+        rng = np.random.default_rng(4)
+        newval = rng.uniform(0.5, 2.0, size=ts[3].val.shape)
+        devs[3][2].copy_(torch.as_tensor(newval, dtype=devs[3][2].dtype, device="cuda"))
+        h.decompose_batched(devs, 0, s, 5)
+        got = h.batch_result(3)
+        o = ora.ctd_s(ts[3].dims, ts[3].idx, newval, 0, s[3], 5, tensor=3)
+        assert np.array_equal(got["draws"], o.draws.astype(np.uint64))
+        assert np.array_equal(got["accepted"], o.accepted.astype(np.uint64))
+        rtol, atol = (1e-6, 1e-12) if precision == "fp64" else (1e-4, 1e-8)
+        assert abs(got["rel_err"] - o.rel_err) <= rtol * o.rel_err + atol
+    finally:
+        other.close()
+        h.close()

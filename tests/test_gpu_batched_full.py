@@ -7,7 +7,9 @@ draws with Philox counter word b).
 
 Checked per stored tensor: draws, unique fibers, multiplicities and kept
 fibers bit for bit, and the error (1e-6 relative in float64, 1e-4 in mixed
-mode); for every tensor of the call, the sizes and a finite error in [0, 1].
+mode); for every tensor of the call, the sizes and a finite error in [0, 1];
+and the same call three times more (captured as a graph, then replayed), the
+stored tensors' results bit for bit equal to the first call's.
 """
 import math
 import os
@@ -54,7 +56,8 @@ def test_many_tensors_full_size(many, precision):
     rtol, atol = (1e-6, 1e-12) if precision == "fp64" else (1e-4, 1e-8)
     h = ctd.Ctd(precision=precision)
     try:
-        h.decompose_batched([ctd.to_device(t, "cuda") for t in ts], 0, s, 0)
+        devs = [ctd.to_device(t, "cuda") for t in ts]
+        h.decompose_batched(devs, 0, s, 0)
         h.sync()
         for i, b in enumerate(sel.tolist()):
             r = h.batch_result(b)
@@ -70,5 +73,15 @@ def test_many_tensors_full_size(many, precision):
             assert r["s"] == s[b] and 1 <= r["s_tilde"] <= min(r["s_unique"], t.dims[0]), b
             # a tensor whose kept fibers span all its rows has error 0 up to rounding
             assert -atol <= r["rel_err"] <= 1.0, (b, r["rel_err"])
+        # the same call again is captured as a graph, then replayed: same bits
+        first = [h.batch_result(b) for b in sel.tolist()]
+        for rep in range(3):
+            h.decompose_batched(devs, 0, s, 0)
+            h.sync()
+            for i, b in enumerate(sel.tolist()):
+                r = h.batch_result(b)
+                for key in ("draws", "unique", "counts", "accepted", "prob", "scale"):
+                    assert np.array_equal(r[key], first[i][key]), (rep, b, key)
+                assert r["err2"] == first[i]["err2"] and r["norm2"] == first[i]["norm2"], (rep, b)
     finally:
         h.close()
