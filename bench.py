@@ -169,11 +169,19 @@ def time_many(ctd, tensors, sizes, precision, reps=3):
     os.environ.pop("CTD_NO_GRAPH")
     run(2)                                   # a direct call, then the captured one
     ms = run(reps)
-    rel = [h.batch_result(b, arrays=False)["rel_err"] for b in range(len(tensors))]
-    kept = [h.batch_result(b, arrays=False)["s_tilde"] for b in range(len(tensors))]
+    res = [h.batch_result(b, arrays=False) for b in range(len(tensors))]
     h.close()
+    rel = [r["rel_err"] for r in res]
+    flops = sum(basis_flops(t.dims[0], r["s_unique"], r["s_tilde"]) for t, r in zip(tensors, res))
+    tf = flops / (ms * 1e-3) / 1e12
     return {"ms": ms, "ms_direct": ms_direct, "mean_rel_err": float(sum(rel) / len(rel)),
-            "kept_total": int(sum(kept))}
+            "kept_total": int(sum(r["s_tilde"] for r in res)),
+            "basis_roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_FP64_MFMA,
+                               "unit": "TFLOP/s", "frac": tf / PEAK_FP64_MFMA,
+                               "work": "sum over the tensors of 2 I s'^2 + 2 s'^3/3 + 2 I s~^2 "
+                                       f"({flops:.3e} flop)",
+                               "time": "the whole batched call (every stage), so a lower bound "
+                                       "on the basis kernels' rate"}}
 
 
 SWEEP_S = (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000)

@@ -62,6 +62,14 @@ namespace {
 }  // namespace
 
 namespace ctd {
+// Zeroes n 64-bit words (a kernel rather than hipMemsetAsync, whose graph
+// nodes are unreliable on replay).
+__global__ void k_zero_words(uint64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n_max, const DevScalars* sc) {
   const int64_t n = std::min<int64_t>(n_max, sc->n_f);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -465,7 +473,10 @@ ctd_status ctd_create(ctd_handle** out, const ctd_options* opt, void* hip_stream
     delete h;
     return CTD_ERR_OOM;
   }
-  (void)hipMemsetAsync(h->d_sc, 0, sizeof(DevScalars), h->stream);
+  static_assert(sizeof(DevScalars) % 8 == 0, "DevScalars is zeroed as 64-bit words");
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, h->stream, (uint64_t*)h->d_sc,
+                     (int64_t)(sizeof(DevScalars) / 8));
+  (void)hipGetLastError();
   *out = h;
   return CTD_OK;
 }

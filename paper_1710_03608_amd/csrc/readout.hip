@@ -52,6 +52,10 @@ __global__ __launch_bounds__(kBlock) void k_col_norms(const double* __restrict__
 
 // Nonzero entries of an outer x inner strided block (element (o, i) at
 // p[o * ld + i]), added into *count.
+__global__ void k_zero2(unsigned long long* p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_count_nz(const T* __restrict__ p, int64_t outer,
                                                      int64_t inner, int64_t ld,
@@ -174,7 +178,8 @@ extern "C" ctd_status ctd_memory_usage(ctd_handle* h, ctd_memory* out) {
   out->nnz_X = h->nnz_seen;
   unsigned long long* d_cnt = nullptr;
   RO_HIP(h, hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)));
-  hipError_t e = hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), h->stream);
+  hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, h->stream, d_cnt);
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess && k > 0) {
     hipLaunchKernelGGL(k_count_nz<double>, dim3(1024), dim3(kBlock), 0, h->stream, res.R, n_rows,
                        k, res.ldr, d_cnt);
