@@ -215,7 +215,12 @@ ctd_status ctd_load_state(ctd_handle* h, const void* host_buf, size_t bytes);
  * work on it runs after all of them.
  * Per-tensor results are read with ctd_get_batch_result; the handle's own
  * CTD-S / CTD-D state is left as it was.  Host argument errors are returned
- * at once; device errors are latched per tensor. */
+ * at once; device errors are latched per tensor.  A call with the same
+ * tensors (pointers, shapes, nonzero counts), sizes, seed and mode as the
+ * call just before it on the handle is captured as a HIP graph, and later
+ * such calls replay it (same results, bit for bit; the inputs' current values
+ * are read); the environment variable CTD_NO_GRAPH=1 turns this off.  The
+ * caller's stream must not be capturing when the call is made. */
 ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, int32_t B, int32_t mode,
                                  const int64_t* s, uint64_t seed);
 
