@@ -530,7 +530,11 @@ __global__ __launch_bounds__(kBlock) void k_blk_w2_sum(const BasisDev* __restric
 // which can reach eps^2 ||x||^2.
 // NG groups of kBlock threads take every NG-th row of each 64-row tile and
 // their sums are added in group order: four groups (four waves per SIMD) when
-// few inputs share the launch, one when many fill the GPU by themselves.
+// few inputs share the launch and nothing runs beside it; one when many inputs
+// fill the GPU by themselves, or when the side streams' projection GEMMs hold
+// CUs (a 256-thread workgroup with 33 KB of LDS fits beside one of theirs, a
+// 1024-thread one with 66 KB waits for CUs to drain: 11.48 -> 11.25 ms per
+// decomposition of the 5M-nonzero tensor).
 template <int NG>
 __global__ __launch_bounds__(kBlock * NG) void k_blk_gram_dd(const BasisDev* __restrict__ bd,
                                                              int64_t b0) {
@@ -1694,7 +1698,7 @@ void launch_basis(hipStream_t st, const BasisArgs* args, DevScalars* const* scs,
           project(sst(kB), kB, bounds(kB), std::max<int64_t>(bn.kub, 1), kEarly);
         }
       }
-      if (nz <= kFewInputs)
+      if (nz <= kFewInputs && !ahead)
         hipLaunchKernelGGL(k_blk_gram_dd<4>, dim3(bn.dd_max, 1, nz), dim3(kBlock * 4), 0, st, bd, b0);
       else
         hipLaunchKernelGGL(k_blk_gram_dd<1>, dim3(bn.dd_max, 1, nz), dim3(kBlock), 0, st, bd, b0);
