@@ -27,6 +27,9 @@ METRIC = ("nonzeros/sec and HBM GB/s (% roofline) for CTD-S/CTD-D, mixed vs FP64
 PEAK_FP64_VALU = 78.6    # TFLOP/s, MI355X vector fp64
 PEAK_FP32_VALU = 157.3   # TFLOP/s, MI355X vector fp32
 PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense fp64 matrix
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, dense fp32 matrix
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s, dense bf16 matrix
+CROSS_NARROW_ROWS = 16   # kept fibers per update up to which the float32 C uses float32 MFMAs
 PEAK_HBM = 8000.0        # GB/s
 S_DRAWS = 2000
 SEED = 0
@@ -122,7 +125,7 @@ def stream_cross_roofline(ctd, st, precision, n_slices=64, batch=1):
     r = h.result(arrays=False)
     width = 8 if precision == "fp64" else 4
     k0, n0 = r["s_tilde"], r["n_cols"]
-    nbytes, ms, passes = 0, 0.0, 0
+    nbytes, flops, ms, passes = 0, 0.0, 0.0, 0
     for i in range(0, len(slices), batch):
         if batch == 1:
             h.update(*slices[i], STREAM_D)
@@ -132,16 +135,33 @@ def stream_cross_roofline(ctd, st, precision, n_slices=64, batch=1):
         k1, n1 = r["s_tilde"], r["n_cols"]
         if k1 > k0:
             nbytes += (k0 * n0 + (k1 - k0) * n0) * width
+            flops += 2.0 * (k1 - k0) * k0 * n0      # the new rows over the columns held
             ms += r["stage_ms"]["core"]
             passes += 1
         k0, n0 = k1, n1
     h.close()
     gbps = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    sample = (f"first {len(slices)} slices, " + ("unbatched" if batch == 1 else f"in batches of {batch}")
+              + f", {passes} cross-term passes, {nbytes / 1e9:.1f} GB read and written, "
+              f"{flops:.3e} flop")
+    # the matrix unit of the passes: float64 MFMA; a float32 C on float32 MFMA when
+    # an update can keep at most CROSS_NARROW_ROWS fibers (batch x d), else on
+    # bfloat16 MFMA with six products of three-part operands per multiply-add
+    if precision == "fp64":
+        mf = {"achieved": tf, "peak": PEAK_FP64_MFMA, "frac": tf / PEAK_FP64_MFMA,
+              "unit": "TFLOP/s", "kernel": "k_cross_term (float64 MFMA)"}
+    elif batch * STREAM_D <= CROSS_NARROW_ROWS:
+        mf = {"achieved": tf, "peak": PEAK_FP32_MFMA, "frac": tf / PEAK_FP32_MFMA,
+              "unit": "TFLOP/s", "kernel": "k_cross_term32 (float32 MFMA)"}
+    else:
+        mf = {"achieved": tf, "peak": PEAK_BF16_MFMA / 6, "frac": 6 * tf / PEAK_BF16_MFMA,
+              "unit": "TFLOP/s (float32-equivalent)",
+              "kernel": "k_cross_term_bf3 (bfloat16 MFMA, six products per multiply-add)"}
+    mf.update({"bound": "mfma", "sample": sample})
     return {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM, "unit": "GB/s",
-            "frac": gbps / PEAK_HBM, "kernel": "k_cross_term (float64) / k_cross_term32 (float32 C)",
-            "sample": f"first {len(slices)} slices, " + ("unbatched" if batch == 1 else
-                      f"in batches of {batch}") + f", {passes} cross-term passes, "
-                      f"{nbytes / 1e9:.1f} GB read and written"}
+            "frac": gbps / PEAK_HBM, "kernel": "k_cross_term (float64) / k_cross_term32 / "
+            "k_cross_term_bf3 (float32 C)", "sample": sample, "mfma": mf}
 
 
 def time_many(ctd, tensors, sizes, precision, reps=3):
@@ -439,7 +459,10 @@ def main():
                 r["batch"] = batch
                 r["cross_term_roofline"] = stream_cross_roofline(ctd, st, mode, batch=batch)
                 log(f"  cross term: {r['cross_term_roofline']['achieved']:.0f} GB/s "
-                    f"({100 * r['cross_term_roofline']['frac']:.1f}% of HBM)")
+                    f"({100 * r['cross_term_roofline']['frac']:.1f}% of HBM), "
+                    f"{r['cross_term_roofline']['mfma']['achieved']:.1f} TF/s "
+                    f"({100 * r['cross_term_roofline']['mfma']['frac']:.1f}% of "
+                    f"{r['cross_term_roofline']['mfma']['kernel'].split(' ')[0]}'s matrix peak)")
                 r["slice_nnz_per_s"] = slice_nnz / (r["slices_ms"] * 1e-3)
                 r["slices_per_s"] = len(st.slices) / (r["slices_ms"] * 1e-3)
                 stream_line["modes"][key] = r
