@@ -251,11 +251,13 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 // rows in a fixed permutation.  The 16 RT x 16 Y chunk is shared through LDS
 // (double-buffered, one barrier per chunk); the next chunk of C is in flight
 // in registers while the current one is in the MFMAs.  C is read once per
-// 16 RT new rows.
+// 16 RT new rows.  NW waves a workgroup (64 NW columns; the Y chunk needs
+// 4 x 16 RT threads): every wave computes its columns the same way whatever
+// NW is, so the autotuner may pick NW.
 constexpr int kCrossCols = 256;
 
-template <int RT>
-__global__ __launch_bounds__(kCrossCols) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 3 : 1)))
+template <int RT, int NW = 4>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 3 : 1)))
 void k_cross_term(double* __restrict__ C, int64_t ldc,
                                                            const double* __restrict__ Yall,
                                                            int64_t ldy, int64_t ystride,
@@ -265,7 +267,8 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
   const int64_t* rng = rng_all + 5 * blockIdx.y;
   const double* Y = Yall + blockIdx.y * ystride;
   const int64_t d = rng[0], na = rng[2], ncols = rng[4];
-  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
+  static_assert(64 * NW >= 4 * 16 * RT, "the Y chunk needs 4 threads per row");
+  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * (64 * NW);
   if (na <= 0 || f0 >= ncols) return;
   const int t = threadIdx.x, w = t / kWave, l = lane_id(), i = l % 16, g = l / 16;
   const int64_t nch = (d + 15) / 16;
@@ -348,9 +351,9 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
 // float32 as it is staged.  The reduction runs in chunks of 32 rows so that a
 // lane still reads 32 bytes of its column (8 consecutive rows, k0 + 8 g ..),
 // and MFMA t (t < 8) takes element t of them.  Lane l holds D[4 (l / 16) +
-// r][l % 16] of a 16 x 16 float32 tile.
-template <int RT>
-__global__ __launch_bounds__(kCrossCols) void k_cross_term32(float* __restrict__ C, int64_t ldc,
+// r][l % 16] of a 16 x 16 float32 tile.  NW waves a workgroup, as above.
+template <int RT, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void k_cross_term32(float* __restrict__ C, int64_t ldc,
                                                              const double* __restrict__ Yall,
                                                              int64_t ldy, int64_t ystride,
                                                              const int64_t* rng_all) {
@@ -361,7 +364,8 @@ __global__ __launch_bounds__(kCrossCols) void k_cross_term32(float* __restrict__
   const int64_t* rng = rng_all + 5 * blockIdx.y;
   const double* Y = Yall + blockIdx.y * ystride;
   const int64_t d = rng[0], na = rng[2], ncols = rng[4];
-  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * kCrossCols;
+  static_assert(64 * NW >= 4 * 16 * RT, "the Y chunk needs 4 threads per row");
+  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * (64 * NW);
   if (na <= 0 || f0 >= ncols) return;
   const int t = threadIdx.x, w = t / kWave, l = lane_id(), i = l % 16, g = l / 16;
   const int64_t nch = (d + 31) / 32;
@@ -1101,27 +1105,67 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
   // before the batch, pass b + 1 over the columns of slice b
   mark(h, MARK_CROSS0);
   {
-    int64_t tiles = (S.n_cols_ub + kCrossCols - 1) / kCrossCols;
-    for (int p = 1; p < B; ++p)
-      tiles = std::max<int64_t>(tiles, (slices[p - 1].nnz + kCrossCols - 1) / kCrossCols);
+    // columns of the widest pass: those held before the batch, or a slice's
+    int64_t cols_max = S.n_cols_ub;
+    for (int p = 1; p < B; ++p) cols_max = std::max<int64_t>(cols_max, slices[p - 1].nnz);
+    auto tiles_of = [&](int cols) { return (cols_max + cols - 1) / cols; };
     const int64_t ystride = kept_max * S.capD;
     hipLaunchKernelGGL(k_cross_setup, dim3(1), dim3(CTD_MAX_BATCH), 0, st, info, B, sc, rng);
     hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave), B), dim3(kBlock), 0, st, S.Xt,
                        S.capD, Wacc, S.capD, Y, S.capD, ystride, rng);
-    if (tiles > 0 && S.Cf) {
-      if (kept_max <= 16)
-        hipLaunchKernelGGL((k_cross_term32<1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
-                           S.capD, Y, S.capD, ystride, rng);
-      else
+    if (cols_max > 0 && kept_max > 16) {
+      const int64_t tiles = tiles_of(kCrossCols);
+      if (S.Cf)
         hipLaunchKernelGGL((k_cross_term_bf3<4, 1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
-                           S.capD, Y, S.capD, ystride, rng);
-    } else if (tiles > 0) {
-      if (kept_max <= 16)
-        hipLaunchKernelGGL((k_cross_term<1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
                            S.capD, Y, S.capD, ystride, rng);
       else
         hipLaunchKernelGGL((k_cross_term<4>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
                            S.capD, Y, S.capD, ystride, rng);
+    } else if (cols_max > 0) {
+      // at most 16 new rows: waves per workgroup (2, 4 or 8) chosen by the
+      // autotuner per bucket of the column count (every choice writes the same
+      // values; a measuring call runs all three, each reading rows < d only)
+      constexpr int kNCand = 3;
+      const int prec = S.Cf ? 1 : 0, bucket = tune_bucket(cols_max);
+      int choice = tune_get(TUNE_CROSS_NW, prec, bucket, kNCand);
+      std::vector<hipEvent_t> tev;
+      const bool measure = choice < 0 && tune_begin(TUNE_CROSS_NW, prec, bucket, kNCand, &tev);
+      if (choice < 0) choice = 1;
+      auto cross = [&](int c) {
+        const int nw = 2 << c;
+        const dim3 grid((unsigned)tiles_of(64 * nw), B);
+        if (S.Cf) {
+          if (nw == 2)
+            hipLaunchKernelGGL((k_cross_term32<1, 2>), grid, dim3(128), 0, st, S.Cf, S.capD, Y, S.capD,
+                               ystride, rng);
+          else if (nw == 4)
+            hipLaunchKernelGGL((k_cross_term32<1, 4>), grid, dim3(256), 0, st, S.Cf, S.capD, Y, S.capD,
+                               ystride, rng);
+          else
+            hipLaunchKernelGGL((k_cross_term32<1, 8>), grid, dim3(512), 0, st, S.Cf, S.capD, Y, S.capD,
+                               ystride, rng);
+        } else {
+          if (nw == 2)
+            hipLaunchKernelGGL((k_cross_term<1, 2>), grid, dim3(128), 0, st, S.C, S.capD, Y, S.capD,
+                               ystride, rng);
+          else if (nw == 4)
+            hipLaunchKernelGGL((k_cross_term<1, 4>), grid, dim3(256), 0, st, S.C, S.capD, Y, S.capD,
+                               ystride, rng);
+          else
+            hipLaunchKernelGGL((k_cross_term<1, 8>), grid, dim3(512), 0, st, S.C, S.capD, Y, S.capD,
+                               ystride, rng);
+        }
+      };
+      if (measure) {
+        for (int c = 0; c < kNCand; ++c) {
+          (void)hipEventRecord(tev[2 * c], st);
+          cross(c);
+          (void)hipEventRecord(tev[2 * c + 1], st);
+        }
+        tune_recorded(TUNE_CROSS_NW, prec, bucket);
+      } else {
+        cross(choice);
+      }
     }
   }
   mark(h, MARK_CORE);

@@ -12,14 +12,16 @@
 namespace ctd {
 
 // ---- tune.hip --------------------------------------------------------------
-// Per-process choice among bit-identical kernel variants, by shape bucket
+// Per-process choice among bit-identical kernel variants (fibers per wave of
+// the projection and of C's columns, waves per workgroup of the CTD-D cross
+// term for at most 16 new rows), by shape bucket
 // (tune_bucket(n) = ceil(log2 n)).  tune_get returns the chosen variant or -1
 // (undecided; a finished measurement is resolved here).  tune_begin returns
 // true, with 2 events per candidate, when the caller should time every
 // candidate now (event 2c before candidate c, 2c + 1 after it), and then
 // tune_recorded once every record is enqueued: until then no other thread
 // reads the events.  The table is shared by the threads of a process.
-enum { TUNE_PROJ_FPW = 0, TUNE_COLS_FPW = 1 };
+enum { TUNE_PROJ_FPW = 0, TUNE_COLS_FPW = 1, TUNE_CROSS_NW = 2 };
 int tune_bucket(int64_t n);
 int tune_get(int knob, int prec, int bucket, int ncand);
 bool tune_begin(int knob, int prec, int bucket, int ncand, std::vector<hipEvent_t>* evs);
