@@ -286,8 +286,7 @@ def calibrate_copy():
 
 
 def measured_traffic():
-    """HBM bytes of one projection SpMM (k_proj_multi, k_proj_multi_fin when column-sliced,
-    k_proj_long, k_proj_long_fin) from the
+    """HBM bytes of one projection SpMM (the k_hot_* and k_proj_* kernels of one call) from the
     committed rocprofv3 counter summary, or None when the summary is missing or the kernel
     sources changed since the counters were taken."""
     import hashlib
@@ -506,9 +505,10 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak,
                 "traffic": measured_traffic() if main_mode == "fp64" else None,
-                "kernel": ("projection SpMM: k_proj_multi (+ k_proj_multi_fin when column-sliced) "
-                           "+ k_proj_long + k_proj_long_fin "
-                           "(z_f = Q^T x_f over fibers with >= 2 nonzeros)"),
+                "kernel": ("projection SpMM: hot-row selection and G = Q Q_H^T (k_hot_*), "
+                           "k_proj_multi_hot (+ k_proj_cold, k_proj_cold_fin in float64), "
+                           "k_proj_long, k_proj_long_fin_hot "
+                           "(||Q^T x_f||^2 over fibers with >= 2 nonzeros)"),
                 "work": f"2 * s~ ({s_t}) * nnz in multi-nonzero fibers ({stats['nnz_multi']})",
                 "kernel_ms": spmm_ms}
     # the independence filter and basis, the largest stage: algorithmic flops over its

@@ -168,6 +168,15 @@ void static_items(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool want_
   add(&b->long_part, n_long * long_ld * 8);
   add(&b->zpart, (size_t)kProjSlices * n * 8);
   add(&b->partial, ((n + 8191) / 8192 + 1) * 8);
+  b->hot_id = b->hot_meta = nullptr;
+  b->GH = nullptr;
+  b->cold_list = nullptr;
+  if (nnz > kHotMinNnz && n_rows <= kHotMaxRows) {
+    add(&b->hot_id, n_rows * 4);
+    add(&b->hot_meta, (kHotMax + 1) * 4);
+    add(&b->GH, n_rows * kHotMax * 8);
+    add(&b->cold_list, (n / 2 + 1) * 4);
+  }
   add(&b->Rs, want_R ? n_rows * ld * 8 : 8);
   add(&b->C, want_C ? (size_t)ld * n * 8 : 8);
 }
@@ -280,7 +289,8 @@ int key_bits(const FiberLayout& lay) {
 }
 
 ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const float* Qf,
-                         int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max) {
+                         int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max,
+                         int64_t n_rows) {
   const bool mixed = h->opt.precision == CTD_PREC_MIXED;
   ProjectArgs pa{};
   pa.fptr = b.fptr;
@@ -302,6 +312,11 @@ ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const fl
   pa.zpart_ld = b.zpart_ld;
   pa.partial = b.partial;
   pa.mixed = mixed;
+  pa.n_rows = n_rows;
+  pa.hot_id = b.hot_id;
+  pa.hot_meta = b.hot_meta;
+  pa.GH = b.GH;
+  pa.cold_list = b.cold_list;
   return pa;
 }
 
@@ -396,7 +411,8 @@ ctd_status static_back(ctd_handle* h, const ctd_coo* X, const FiberLayout& lay, 
   StaticBufs& b = h->sb;
   DevScalars* sc = h->d_sc;
   // s~ <= min(s, I_alpha): the bound sets the projection's column slices
-  ProjectArgs pa = project_args(h, b, b.Q, b.Qf, b.ld, b.lev, &sc->s_tilde, std::min(s, n_rows));
+  ProjectArgs pa = project_args(h, b, b.Q, b.Qf, b.ld, b.lev, &sc->s_tilde, std::min(s, n_rows),
+                                n_rows);
   if (h->opt.profile) {
     mark(h, MARK_PROJ0);
     mark(h, MARK_SPMM0);

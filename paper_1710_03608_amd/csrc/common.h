@@ -19,6 +19,17 @@ constexpr int kWave = 64;
 constexpr int kLongFiber = 64;
 constexpr int kLongWaves = 8;
 constexpr int kProjSlices = 8;
+// Hot rows of the projection of a large input: at most kHotMax rows, counted
+// over every kHotSample-th fiber of 2 .. kLongFiber nonzeros and each holding
+// at least kHotMinCount nonzeros of that sample, for inputs of more than
+// kHotMinNnz nonzeros over at most kHotMaxRows rows (an LDS histogram in
+// each of kHotParts workgroups).
+constexpr int kHotMax = 64;
+constexpr int kHotSample = 8;
+constexpr int kHotMinCount = 64;
+constexpr int64_t kHotMinNnz = int64_t(1) << 18;
+constexpr int kHotMaxRows = 16384;
+constexpr int kHotParts = 256;
 
 struct DevScalars {
   uint64_t W;            // total integer sampling weight of the last input
@@ -40,6 +51,7 @@ struct DevScalars {
   int32_t n_long;        // fibers listed for the workgroup-per-chunk gather
   int32_t blk_na;        // fibers kept by the current candidate block
   int32_t blk_reorth;    // the block's first Cholesky-QR pass left it non-orthonormal
+  int32_t n_cold;        // fibers listed for the gather over their cold rows
 };
 __device__ inline void latch_status(DevScalars* sc, int code) {
   atomicCAS(&sc->status, 0, code);

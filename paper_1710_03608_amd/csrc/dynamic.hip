@@ -1087,7 +1087,8 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       hipLaunchKernelGGL(k_append_ids, dim3(grid_for(nnz)), dim3(kBlock), 0, st, b.fid, &sc->n_f,
                          S.col_fid, nullptr, &sc->n_cols_total, t_off);
       // slice residual against the grown basis
-      ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total, d_next);
+      ProjectArgs pa = project_args(h, b, S.Q, S.Qf, S.capD, S.lev, &sc->n_accept_total, d_next,
+                                    S.rows);
       if (h->opt.profile) {
         mark(h, MARK_PROJ0);
         mark(h, MARK_SPMM0);

@@ -175,6 +175,12 @@ struct ProjectArgs {
   int64_t zpart_ld;        // >= number of fibers
   double* partial;         // workspace
   bool mixed;
+  int64_t n_rows;          // rows of Q
+  // hot-row path (null when the input is too small or has too many rows)
+  int32_t* hot_id;         // [n_rows] hot index of each row, -1 when cold
+  int32_t* hot_meta;       // [kHotMax + 1] hot rows in row order, then their count
+  double* GH;              // [n_rows x kHotMax] GH[r][a] = Q_r . Q_{hot row a}
+  int32_t* cold_list;      // [nnz / 2 + 1] fibers with two or more cold nonzeros
 };
 // ev0/ev1 (optional) are recorded right before and after the multi-nonzero SpMM kernel.
 void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevScalars* sc,

@@ -56,6 +56,10 @@ struct StaticBufs {
   double* zpart;
   int64_t zpart_ld;
   double* partial;
+  int32_t* hot_id;     // hot-row projection (null when not planned)
+  int32_t* hot_meta;
+  double* GH;
+  int32_t* cold_list;
   double* Rs;
   double* C;
   int64_t ld;
@@ -180,7 +184,8 @@ size_t static_bytes(int64_t nnz, int64_t s, int64_t n_rows, bool mixed, bool wan
                     int64_t max_cols);
 int key_bits(const FiberLayout& lay);
 ProjectArgs project_args(ctd_handle* h, StaticBufs& b, const double* Q, const float* Qf,
-                         int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max);
+                         int64_t ldq, const double* lev, const int32_t* d_ncols, int64_t ncols_max,
+                         int64_t n_rows);
 void launch_reset_scalars(hipStream_t st, DevScalars* sc, bool keep_stream);
 void launch_static_totals(hipStream_t st, DevScalars* sc);
 void launch_core_static(hipStream_t st, StaticBufs& b, int64_t n_rows, int64_t nnz_max,

@@ -136,9 +136,9 @@ def test_projection_in_column_slices(lib, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_large_input_runs_are_bit_identical(lib, precision):
-    """Above 2^18 nonzeros the projection uses two column slices in float64
-    and whole rows in float32; the first call of a size (which times every
-    fibers-per-wave variant) and later calls agree bit for bit."""
+    """Above 2^18 nonzeros over at most 16384 rows the projection splits off
+    the hot rows; the first call of a size (which times every fibers-per-wave
+    variant) and later calls agree bit for bit."""
     X = synth.power_law_tensor((2000, 600, 40), 400000, 32, zipf_a=1.1)
     runs = [run_gpu(lib, X, 0, 1200, 6, precision=precision) for _ in range(3)]
     for r in runs[1:]:
@@ -151,6 +151,47 @@ def test_large_input_runs_are_bit_identical(lib, precision):
         check_parity(runs[0], o)
     else:
         check_parity(runs[0], o, rtol=RTOL_MIXED, atol=1e-6)
+
+
+def _multi_row_counts(X, mode=0):
+    """Nonzeros per row of X_(mode) over the fibers of 2..64 nonzeros."""
+    fid = ora.fiber_ids(X.dims, X.idx, mode)
+    _, inv, lens = np.unique(fid, return_inverse=True, return_counts=True)
+    m = (lens[inv] >= 2) & (lens[inv] <= 64)
+    return np.bincount(X.idx[mode][m], minlength=X.dims[mode])
+
+
+@pytest.mark.parametrize("case", ["zipf1.3-fp64", "zipf1.3-mixed", "zipf1.1-fp64",
+                                  "uniform-fp64", "rows20000-fp64", "rows20000-mixed"])
+def test_projection_hot_rows(lib, case):
+    """The hot-row split of the projection (above 2^18 nonzeros, at most 16384
+    rows): a steep source law with a few dozen hot rows; a flatter one where
+    about a hundred rows clear the count floor of 512, so the cut by count
+    class decides which at most 64 are taken; uniform rows, where no row
+    reaches the floor and every fiber is gathered; and 20000 rows, where the
+    split is off and the column-sliced gather runs."""
+    kind, precision = case.split("-")
+    if kind == "zipf1.3":
+        X = synth.power_law_tensor((1500, 500, 40), 300000, 45, zipf_a=1.3)
+        assert 0 < (_multi_row_counts(X) >= 512).sum() <= 64
+    elif kind == "zipf1.1":
+        X = synth.power_law_tensor((2000, 600, 40), 700000, 47, zipf_a=1.1)
+        assert (_multi_row_counts(X) >= 512).sum() > 64
+    elif kind == "uniform":
+        X = synth.uniform_tensor((2000, 400, 30), 300000, 42)
+        assert (_multi_row_counts(X) < 512).all()
+    else:
+        X = synth.power_law_tensor((20000, 300, 20), 300000, 43, zipf_a=1.2)
+    o = ora.ctd_s(X.dims, X.idx, X.val, 0, 900, 7)
+    g = run_gpu(lib, X, 0, 900, 7, precision=precision)
+    again = run_gpu(lib, X, 0, 900, 7, precision=precision)
+    assert again["err2"] == g["err2"]
+    if borderline(o):
+        pytest.skip("candidate within rounding of the threshold")
+    if precision == "fp64":
+        check_parity(g, o)
+    else:
+        check_parity(g, o, rtol=RTOL_MIXED, atol=1e-6)
 
 
 def test_all_fibers_drawn_gives_zero_residual(lib):
