@@ -45,6 +45,7 @@ constexpr int kLongBatch = 16;   // nonzeros per wave and step in k_proj_long
 constexpr int kColdSlices = 4;   // column slices of k_proj_cold
 constexpr int kHotGroup = 32;    // GH entries per lane in flight in k_proj_long_fin_hot
 constexpr int kFinWaves = 2;     // waves per long fiber in k_proj_long_fin_hot
+constexpr int kSmallFiber = 16;  // k_proj_multi_hot: fibers up to this size go four to a wave
 static_assert(kHotMax % kHotGroup == 0, "whole groups of GH entries");
 
 // z += sum_e v_e A[r_e, c .. c + VEC) over the n (<= 64) nonzeros whose
@@ -402,39 +403,75 @@ __global__ __launch_bounds__(kBlock) void k_hot_gram(ProjectArgs a, const DevSca
   }
 }
 
+// This lane's share of ||z_C||^2 = ||sum over the cold lanes c of v_c Q[r_c, :]||^2
+// (whole rows of hi columns), the cold lanes (mask mc) packed into lanes
+// 0 .. |mc| - 1 first.
+template <typename T, int VEC>
+__device__ inline double cold_rows_z2(uint64_t mc, int32_t rr, T vv, const T* Qb, int64_t ldq,
+                                      int64_t hi) {
+  constexpr int kCols = VEC * kWave;
+  const int lane = lane_id();
+  const int nc = __popcll(mc);
+  const int src = packed_source(mc, lane);
+  const int32_t rc = __shfl(rr, src, kWave);
+  const T vc = __shfl(vv, src, kWave);
+  double z2 = 0.0;
+  for (int64_t c0 = 0; c0 < hi; c0 += 2 * kCols) {
+    const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
+    const bool ina = ca < hi, inb = cb < hi;
+    T acc0[VEC], acc1[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) acc0[j] = acc1[j] = T(0);
+    gather_batch<T, VEC>(rc, vc, nc, Qb + (ina ? ca : 0), Qb + (inb ? cb : 0), ina, inb, ldq, acc0,
+                         acc1);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+      const double d0 = (double)acc0[j], d1 = (double)acc1[j];
+      z2 += (ca + j < hi) ? d0 * d0 : 0.0;
+      z2 += (cb + j < hi) ? d1 * d1 : 0.0;
+    }
+  }
+  return z2;
+}
+
 // The fibers of k_proj_multi with the hot-row split.  Per fiber, the hot
-// nonzeros' part of ||z||^2 comes from lookups into GH (hot lanes packed into
-// lanes 0 .. n_hot - 1, four lookups in flight) and the cold part from the
-// row leverage when the fiber has one cold nonzero.  With two or more cold
-// nonzeros, kInline gathers ||z_C||^2 over the packed cold lanes here, whole
-// rows at a time; otherwise the fiber gets resid[f] = ||x_f||^2 - (hot part)
-// and is listed for k_proj_cold, which subtracts ||z_C||^2 in column slices.
-// Every other fiber is handled as in k_proj_multi.
+// nonzeros' part of ||z||^2 comes from lookups into GH (hot lanes packed,
+// four lookups in flight) and the cold part from the row leverage when the
+// fiber has one cold nonzero.  With two or more cold nonzeros, kInline
+// gathers ||z_C||^2 over the packed cold lanes here, whole rows at a time;
+// otherwise the fiber gets resid[f] = ||x_f||^2 - (hot part) and is listed
+// for k_proj_cold, which subtracts ||z_C||^2 in column slices.  Fibers of up
+// to kSmallFiber nonzeros take their hot part four at a time, one per 16-lane
+// group, so that the wave's memory round trips serve four fibers; longer
+// ones take the whole wave.  Every other fiber is handled as in k_proj_multi.
 template <typename T, int VEC, bool kInline>
 __global__ __launch_bounds__(kBlock) void k_proj_multi_hot(ProjectArgs a, DevScalars* sc, int fpw) {
-  constexpr int kCols = VEC * kWave;
+  constexpr int kG = kSmallFiber;
   if (sc->status != 0) return;
   const int64_t n_f = sc->n_f;
   const int64_t hi = *a.d_ncols;
   const T* Qb = sizeof(T) == 8 ? (const T*)a.Q : (const T*)a.Qf;
   const T* vals = sizeof(T) == 8 ? (const T*)a.val : (const T*)a.val32;
   const int lane = lane_id();
+  const int grp = lane / kG, sub = lane % kG;
   const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
   const uint64_t lt = lane == 0 ? 0ull : ((~0ull) >> (kWave - lane));
   for (int64_t fb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave * fpw; fb < n_f;
        fb += nwaves * fpw) {
     const int64_t fl = fb + lane;
     bool multi = false, lng = false;
+    int32_t s0 = 0, len = 0;
     if (lane < fpw && fl < n_f) {
-      const int32_t s0 = a.fptr[fl], s1 = a.fptr[fl + 1];
+      s0 = a.fptr[fl];
+      len = a.fptr[fl + 1] - s0;
       const bool kept = a.fiber_mark && a.fiber_mark[fl];
       if (kept) {
         a.resid[fl] = 0.0;
-      } else if (s1 - s0 == 1) {
+      } else if (len == 1) {
         const double v = a.val[s0];
         const double x2 = v * v;
         a.resid[fl] = x2 - x2 * a.lev[a.row[s0]];
-      } else if (s1 - s0 > kLongFiber) {
+      } else if (len > kLongFiber) {
         lng = true;
       } else {
         multi = true;
@@ -447,7 +484,101 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi_hot(ProjectArgs a, DevSca
       base = __shfl(base, 0, kWave);
       if (lng) a.long_list[base + __popcll(ml & lt)] = (int32_t)fl;
     }
-    uint64_t todo = __ballot(multi), cold = 0;
+    uint64_t small = __ballot(multi && len <= kG), todo = __ballot(multi && len > kG);
+    uint64_t cold = 0, inl = 0;
+    double keep = 0.0;   // lane i: ||x_f||^2 - (hot part) of fiber fb + i, gathered below
+    while (small) {
+      int ig[kWave / kG];
+#pragma unroll
+      for (int g = 0; g < kWave / kG; ++g) {
+        ig[g] = small ? __builtin_ctzll(small) : -1;
+        small &= small - 1;
+      }
+      int my = ig[0];
+#pragma unroll
+      for (int g = 1; g < kWave / kG; ++g) my = grp == g ? ig[g] : my;
+      // (the shuffles run on every lane: a lane that sits out a shuffle
+      // gives 0 to the lanes reading it)
+      const int from = my < 0 ? 0 : my;
+      const int32_t e0 = __shfl(s0, from, kWave);
+      const int32_t n_from = __shfl(len, from, kWave);
+      const int n = my < 0 ? 0 : n_from;
+      const bool in_f = sub < n;
+      const int32_t rr = in_f ? a.row[e0 + sub] : 0;
+      const double v64 = in_f ? a.val[e0 + sub] : 0.0;
+      const int32_t hid = in_f ? a.hot_id[rr] : -1;
+      const bool hot = hid >= 0;
+      const uint64_t mh = __ballot(hot), mc = __ballot(in_f && !hot);
+      const uint64_t gm = (1ull << kG) - 1;
+      const int nh = __popcll((mh >> (grp * kG)) & gm), nc = __popcll((mc >> (grp * kG)) & gm);
+      int nh_max = 0;
+#pragma unroll
+      for (int g = 0; g < kWave / kG; ++g) nh_max = max(nh_max, __popcll((mh >> (g * kG)) & gm));
+      double t = 0.0;
+      if (nh_max > 0) {
+        const int pos = packed_source((mh >> (grp * kG)) & gm, sub) % kG;
+        const int32_t hp = __shfl(hid, grp * kG + pos, kWave);
+        const double vp = __shfl(v64, grp * kG + pos, kWave);
+        const double* g = a.GH + (int64_t)rr * kHotMax;
+        for (int k = 0; k < nh_max; k += 4) {
+          int h[4];
+          double w[4], x[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            h[j] = __shfl(hp, grp * kG + k + j, kWave);
+            w[j] = __shfl(vp, grp * kG + k + j, kWave);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[j] = (in_f && k + j < nh) ? g[h[j]] : 0.0;
+          if (in_f) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[j] = k + j < nh ? w[j] : 0.0;
+            t += (w[0] * x[0] + w[1] * x[1]) + (w[2] * x[2] + w[3] * x[3]);
+          }
+        }
+      }
+      double part = hot ? v64 * t : 2.0 * v64 * t;
+      if (nc == 1 && in_f && !hot) part += v64 * v64 * a.lev[rr];
+      double x2 = v64 * v64;
+#pragma unroll
+      for (int off = kG / 2; off > 0; off >>= 1) {
+        part += __shfl_xor(part, off, kWave);
+        x2 += __shfl_xor(x2, off, kWave);
+      }
+      const double rest = x2 - part;
+      const uint64_t need = __ballot(sub == 0 && my >= 0 && nc >= 2);
+      if (kInline) {
+#pragma unroll
+        for (int g = 0; g < kWave / kG; ++g) {
+          const double r = __shfl(rest, g * kG, kWave);
+          if (((need >> (g * kG)) & 1) && lane == ig[g]) keep = r;
+        }
+      }
+      if (sub == 0 && my >= 0 && !(kInline && nc >= 2)) a.resid[fb + my] = rest;
+#pragma unroll
+      for (int g = 0; g < kWave / kG; ++g)
+        if ((need >> (g * kG)) & 1) {
+          if (kInline)
+            inl |= 1ull << ig[g];
+          else
+            cold |= 1ull << ig[g];
+        }
+    }
+    if (kInline) {
+      // the small fibers with two or more cold nonzeros: their cold rows
+      while (inl) {
+        const int i = __builtin_ctzll(inl);
+        inl &= inl - 1;
+        const int32_t e0 = a.fptr[fb + i];
+        const int n = a.fptr[fb + i + 1] - e0;
+        const bool in_f = lane < n;
+        const int32_t rr = in_f ? a.row[e0 + lane] : 0;
+        const T vv = in_f ? vals[e0 + lane] : T(0);
+        const uint64_t mc = __ballot(in_f && a.hot_id[rr] < 0);
+        const double z2 = wave_sum(cold_rows_z2<T, VEC>(mc, rr, vv, Qb, a.ldq, hi));
+        if (lane == 0) a.resid[fb + i] = read_lane(keep, i) - z2;
+      }
+    }
     while (todo) {
       const int i = __builtin_ctzll(todo);
       todo &= todo - 1;
@@ -486,25 +617,8 @@ __global__ __launch_bounds__(kBlock) void k_proj_multi_hot(ProjectArgs a, DevSca
       if (nc == 1 && in_f && !hot) part += v64 * v64 * a.lev[rr];
       if (nc >= 2 && !kInline) cold |= 1ull << i;
       if (nc >= 2 && kInline) {
-        const int src = packed_source(mc, lane);
-        const int32_t rc = __shfl(rr, src, kWave);
-        const T vr = in_f ? vals[e0 + lane] : T(0);
-        const T vc = __shfl(vr, src, kWave);
-        for (int64_t c0 = 0; c0 < hi; c0 += 2 * kCols) {
-          const int64_t ca = c0 + (int64_t)VEC * lane, cb = ca + kCols;
-          const bool ina = ca < hi, inb = cb < hi;
-          T acc0[VEC], acc1[VEC];
-#pragma unroll
-          for (int j = 0; j < VEC; ++j) acc0[j] = acc1[j] = T(0);
-          gather_batch<T, VEC>(rc, vc, nc, Qb + (ina ? ca : 0), Qb + (inb ? cb : 0), ina, inb,
-                               a.ldq, acc0, acc1);
-#pragma unroll
-          for (int j = 0; j < VEC; ++j) {
-            const double d0 = (double)acc0[j], d1 = (double)acc1[j];
-            part += (ca + j < hi) ? d0 * d0 : 0.0;
-            part += (cb + j < hi) ? d1 * d1 : 0.0;
-          }
-        }
+        const T vv = in_f ? vals[e0 + lane] : T(0);
+        part += cold_rows_z2<T, VEC>(mc, rr, vv, Qb, a.ldq, hi);
       }
       const double z2 = wave_sum(part);
       const double x2 = wave_sum(v64 * v64);
