@@ -953,7 +953,7 @@ void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevSc
   const int prec = a.mixed ? 1 : 0, bucket = tune_bucket(nnz_max);
   int choice = tune_get(TUNE_PROJ_FPW, prec, bucket, kNCand);
   std::vector<hipEvent_t> tev;
-  const bool measure = choice < 0 && tune_begin(TUNE_PROJ_FPW, prec, bucket, kNCand, &tev);
+  const bool measure = choice < 0 && tune_begin(st, TUNE_PROJ_FPW, prec, bucket, kNCand, &tev);
   if (choice < 0) choice = small ? 0 : 2;
   // Hot rows for a large input over few enough rows (whole rows: the hot
   // split leaves too few gathers to gain from column slices).

@@ -94,7 +94,14 @@ int tune_get(int knob, int prec, int bucket, int ncand) {
   return best;
 }
 
-bool tune_begin(int knob, int prec, int bucket, int ncand, std::vector<hipEvent_t>* evs) {
+bool tune_begin(hipStream_t st, int knob, int prec, int bucket, int ncand,
+                std::vector<hipEvent_t>* evs) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();   // a stream that cannot report it is not being captured
+    cs = hipStreamCaptureStatusNone;
+  }
+  if (cs != hipStreamCaptureStatusNone) return false;
   std::lock_guard<std::mutex> lock(g_mu);
   load_file_locked();
   const uint64_t key = key_of(knob, prec, bucket);
