@@ -346,6 +346,80 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
   }
 }
 
+// k_cross_term for at most 16 new rows (one row tile) without LDS: lane
+// (i, g) needs exactly Y[a0 + i][k0 + 4 g .. + 4] for its MFMAs, so it reads
+// that 32-byte vector itself (Y is small and stays in L2) and the waves run
+// with no barrier between chunks.  The MFMAs see the same operands in the same
+// order as in k_cross_term<1, NW>, so the values are identical.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)))
+void k_cross_term_direct(double* __restrict__ C, int64_t ldc, const double* __restrict__ Yall,
+                         int64_t ldy, int64_t ystride, const int64_t* rng_all) {
+  const int64_t* rng = rng_all + 5 * blockIdx.y;
+  const double* Y = Yall + blockIdx.y * ystride;
+  const int64_t d = rng[0], na = rng[2], ncols = rng[4];
+  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * (64 * NW);
+  if (na <= 0 || f0 >= ncols) return;
+  const int w = threadIdx.x / kWave, l = lane_id(), i = l % 16, g = l / 16;
+  const int64_t nch = (d + 15) / 16;
+  const double* cp[4];
+  bool cin[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int64_t f = f0 + 64 * w + 16 * ct + i;
+    cin[ct] = f < ncols;
+    cp[ct] = C + (cin[ct] ? f : f0) * ldc + 4 * g;
+  }
+  auto mask4 = [&](dbl4 v, int64_t k) -> dbl4 {
+    v[0] = k < d ? v[0] : 0.0;
+    v[1] = k + 1 < d ? v[1] : 0.0;
+    v[2] = k + 2 < d ? v[2] : 0.0;
+    v[3] = k + 3 < d ? v[3] : 0.0;
+    return v;
+  };
+  for (int64_t a0 = 0; a0 < na; a0 += 16) {
+    const int nr = (int)min<int64_t>(16, na - a0);
+    const bool yin = i < nr;
+    const double* yrow = Y + (a0 + (yin ? i : 0)) * ldy + 4 * g;
+    dbl4 acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = dbl4{0, 0, 0, 0};
+    dbl4 cf[4], yv;
+    auto load = [&](int64_t ch) {
+      const int64_t k = ch * 16 + 4 * g;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const dbl4*)(cp[ct] + ch * 16) : dbl4{0, 0, 0, 0};
+        cf[ct] = mask4(cf[ct], k);
+      }
+      yv = (ch < nch && yin && k < d) ? *(const dbl4*)(yrow + ch * 16) : dbl4{0, 0, 0, 0};
+      yv = mask4(yv, k);
+    };
+    load(0);
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      dbl4 cc[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) cc[ct] = cf[ct];
+      const dbl4 ya = yv;
+      load(ch + 1);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma16(ya[tt], cc[ct][tt], acc[ct]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (!cin[ct]) continue;
+      double* col = C + (f0 + 64 * w + 16 * ct + i) * ldc + d + a0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = g + 4 * r;
+        if (a < nr) col[a] = acc[ct][r];
+      }
+    }
+  }
+}
+
 // The same product for a mixed-precision handle, whose C is held in float32:
 // float32 MFMAs (v_mfma_f32_16x16x4f32) with float32 accumulation, Y rounded to
 // float32 as it is staged.  The reduction runs in chunks of 32 rows so that a
@@ -1147,13 +1221,13 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
                                ystride, rng);
         } else {
           if (nw == 2)
-            hipLaunchKernelGGL((k_cross_term<1, 2>), grid, dim3(128), 0, st, S.C, S.capD, Y, S.capD,
+            hipLaunchKernelGGL((k_cross_term_direct<2>), grid, dim3(128), 0, st, S.C, S.capD, Y, S.capD,
                                ystride, rng);
           else if (nw == 4)
-            hipLaunchKernelGGL((k_cross_term<1, 4>), grid, dim3(256), 0, st, S.C, S.capD, Y, S.capD,
+            hipLaunchKernelGGL((k_cross_term_direct<4>), grid, dim3(256), 0, st, S.C, S.capD, Y, S.capD,
                                ystride, rng);
           else
-            hipLaunchKernelGGL((k_cross_term<1, 8>), grid, dim3(512), 0, st, S.C, S.capD, Y, S.capD,
+            hipLaunchKernelGGL((k_cross_term_direct<8>), grid, dim3(512), 0, st, S.C, S.capD, Y, S.capD,
                                ystride, rng);
         }
       };
