@@ -220,7 +220,10 @@ ctd_status ctd_load_state(ctd_handle* h, const void* host_buf, size_t bytes);
  * call just before it on the handle is captured as a HIP graph, and later
  * such calls replay it (same results, bit for bit; the inputs' current values
  * are read); the environment variable CTD_NO_GRAPH=1 turns this off.  The
- * caller's stream must not be capturing when the call is made. */
+ * graph is captured on, and replayed on, a stream of the handle that forks
+ * from the caller's stream and joins it again, so any caller's stream works,
+ * the legacy default stream included.  The caller's stream must not be
+ * capturing when the call is made. */
 ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, int32_t B, int32_t mode,
                                  const int64_t* s, uint64_t seed);
 
@@ -229,6 +232,11 @@ ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, int32_t B, in
  * accepted; device memory owned by the handle until the next batched call).
  * Factor pointers are NULL.  Returns tensor b's latched device status. */
 ctd_status ctd_get_batch_result(ctd_handle* h, int32_t b, ctd_result* out);
+
+/* Number of ctd_decompose_batched calls on h whose work ran as a graph launch
+ * (the capturing call and every replay); 0 for a null handle.  For tests and
+ * diagnostics of the graph form; it does not synchronize. */
+int64_t ctd_batch_graph_launches(const ctd_handle* h);
 
 /* Attack candidates read off R (the online detection of the paper's
  * application section, Section 5).  The kept fibers, in order of acceptance,

@@ -25,7 +25,7 @@ EXPORTS = ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
            "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result", "ctd_sync",
            "ctd_get_result", "ctd_last_error", "ctd_destroy", "ctd_attack_candidates",
            "ctd_memory_usage", "ctd_sparse_core", "ctd_sparse_core_noalloc", "ctd_save_state",
-           "ctd_load_state")
+           "ctd_load_state", "ctd_batch_graph_launches")
 
 c_i32, c_i64, c_u64, c_dbl, c_vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_void_p)
@@ -106,6 +106,8 @@ def load_library():
     lib.ctd_sparse_core_noalloc.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, ctypes.POINTER(c_i64)]
     lib.ctd_save_state.argtypes = [c_vp, c_vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.ctd_load_state.argtypes = [c_vp, c_vp, ctypes.c_size_t]
+    lib.ctd_batch_graph_launches.argtypes = [c_vp]
+    lib.ctd_batch_graph_launches.restype = c_i64
     for name in ("ctd_create", "ctd_decompose", "ctd_decompose_given", "ctd_update",
                  "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
                  "ctd_sync", "ctd_get_result", "ctd_attack_candidates", "ctd_memory_usage",
@@ -262,6 +264,10 @@ class Ctd:
         rc = self.lib.ctd_decompose_batched(self.h, arr, len(coos), int(mode), sz, int(seed))
         self._hold(coos, arr, sz)
         self._check(rc)
+
+    def batch_graph_launches(self):
+        """Batched calls of this handle that ran as a graph launch (capture or replay)."""
+        return int(self.lib.ctd_batch_graph_launches(self.h))
 
     def batch_result(self, b, arrays=True):
         """Scalars (and index arrays) of tensor b of the last batched call."""

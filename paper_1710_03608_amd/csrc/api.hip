@@ -587,6 +587,12 @@ void ctd_destroy(ctd_handle* h) {
     if (B->based) (void)hipEventDestroy(B->based);
     for (hipStream_t st : B->pool) (void)hipStreamDestroy(st);
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->cap) {
+      (void)hipStreamSynchronize(B->cap);
+      (void)hipStreamDestroy(B->cap);
+    }
+    if (B->fork) (void)hipEventDestroy(B->fork);
+    if (B->join) (void)hipEventDestroy(B->join);
     ctd::batch_free_storage(B);
     delete B;
   }

@@ -110,10 +110,39 @@ ctd_status batched_body(ctd_handle* h, const ctd_coo* Xs, int32_t nb, int32_t mo
 // Host checks, then the launches of the call, or the replay of a graph of
 // them: a call with the same signature as the call before it is captured
 // (its work then runs as a graph launch), and later calls with that
-// signature replay the graph.  Between calls nothing the launches read on
-// the host changes: with the same sizes no workspace is reallocated, and the
-// autotuner's choices were settled by the earlier calls.  Any failure of
-// capture, instantiation or launch falls back to direct launches.
+// signature replay the graph.  Capture and replay run on a stream of the
+// batch state that forks from the caller's stream and joins it again, so the
+// caller's stream is never captured itself (the legacy default stream cannot
+// be).  Between calls nothing the launches read on the host changes: with
+// the same sizes no workspace is reallocated, and the autotuner's choices
+// were settled by the earlier calls.  Any failure of capture, instantiation
+// or launch falls back to direct launches on the caller's stream.
+
+// Replays B.exec on B.cap between a fork from and a join to the caller's stream.
+bool replay(BatchState& B, hipStream_t user) {
+  return hipEventRecord(B.fork, user) == hipSuccess &&
+         hipStreamWaitEvent(B.cap, B.fork, 0) == hipSuccess &&
+         hipGraphLaunch(B.exec, B.cap) == hipSuccess &&
+         hipEventRecord(B.join, B.cap) == hipSuccess &&
+         hipStreamWaitEvent(user, B.join, 0) == hipSuccess;
+}
+
+// The stream and events a capture uses, created at the first capture.
+bool capture_objects(BatchState& B) {
+  if (!B.cap && hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking) != hipSuccess) {
+    B.cap = nullptr;
+    return false;
+  }
+  if (!B.fork && hipEventCreateWithFlags(&B.fork, hipEventDisableTiming) != hipSuccess) {
+    B.fork = nullptr;
+    return false;
+  }
+  if (!B.join && hipEventCreateWithFlags(&B.join, hipEventDisableTiming) != hipSuccess) {
+    B.join = nullptr;
+    return false;
+  }
+  return true;
+}
 extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, int32_t nb,
                                             int32_t mode, const int64_t* s, uint64_t seed) {
   if (!h) return CTD_ERR_INVALID_ARG;
@@ -138,34 +167,47 @@ extern "C" ctd_status ctd_decompose_batched(ctd_handle* h, const ctd_coo* Xs, in
   BatchState& B = *h->batch;
   std::vector<uint64_t> sig = batch_signature(h, Xs, nb, mode, s, seed);
   if (B.exec && sig == B.graph_sig) {
-    if (hipGraphLaunch(B.exec, h->stream) == hipSuccess) {
+    if (replay(B, h->stream)) {
       B.host_valid = false;
+      ++B.graph_launches;
       return CTD_OK;
     }
     (void)hipGetLastError();
+    (void)hipStreamSynchronize(B.cap);
     drop_graph(B);
   }
   drop_graph(B);
   const char* off = getenv("CTD_NO_GRAPH");
   const bool capture = sig == B.last_sig && !(off && *off && *off != '0');
   B.last_sig = sig;
-  if (!capture) return batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
-  if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+  if (!capture || !capture_objects(B)) {
     (void)hipGetLastError();
     return batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
   }
+  hipStream_t user = h->stream;
+  if (hipEventRecord(B.fork, user) != hipSuccess || hipStreamWaitEvent(B.cap, B.fork, 0) != hipSuccess ||
+      hipStreamBeginCapture(B.cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
+  }
+  h->stream = B.cap;
   ctd_status rc = batched_body(h, Xs, nb, mode, s, seed, lays, total_s);
+  h->stream = user;
   hipGraph_t g = nullptr;
-  const hipError_t ec = hipStreamEndCapture(h->stream, &g);
+  const hipError_t ec = hipStreamEndCapture(B.cap, &g);
   hipGraphExec_t x = nullptr;
   bool ok = rc == CTD_OK && ec == hipSuccess && g &&
             hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) (void)hipGraphDestroy(g);
-  ok = ok && hipGraphLaunch(x, h->stream) == hipSuccess;
   if (ok) {
     B.exec = x;
     B.graph_sig = sig;
-    return CTD_OK;
+    if (replay(B, user)) {
+      ++B.graph_launches;
+      return CTD_OK;
+    }
+    B.exec = nullptr;
+    B.graph_sig.clear();
   }
   // nothing of the captured work ran: run it directly
   (void)hipGetLastError();
@@ -337,4 +379,8 @@ extern "C" ctd_status ctd_get_batch_result(ctd_handle* h, int32_t b, ctd_result*
   out->scale = B.scale + off;
   out->accepted = B.accepted + off;
   return sc.status ? (ctd_status)sc.status : CTD_OK;
+}
+
+extern "C" int64_t ctd_batch_graph_launches(const ctd_handle* h) {
+  return h && h->batch ? h->batch->graph_launches : 0;
 }

@@ -718,7 +718,7 @@ void launch_cols(hipStream_t st, const StaticBufs& b, int64_t nnz_max, DevScalar
   static const int kFpw[] = {2, 8, kWave};
   constexpr int kNCand = 3;
   const int bucket = tune_bucket(nnz_max), prec = sizeof(TO) == 4 ? 1 : 0;
-  int choice = tune_get(TUNE_COLS_FPW, prec, bucket, kNCand);
+  int choice = tune_get(st, TUNE_COLS_FPW, prec, bucket, kNCand);
   std::vector<hipEvent_t> tev;
   const bool measure = choice < 0 && tune_begin(st, TUNE_COLS_FPW, prec, bucket, kNCand, &tev);
   if (choice < 0) choice = nnz_max <= (int64_t(1) << 18) ? 0 : 2;
@@ -1202,7 +1202,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       // values; a measuring call runs all three, each reading rows < d only)
       constexpr int kNCand = 3;
       const int prec = S.Cf ? 1 : 0, bucket = tune_bucket(cols_max);
-      int choice = tune_get(TUNE_CROSS_NW, prec, bucket, kNCand);
+      int choice = tune_get(st, TUNE_CROSS_NW, prec, bucket, kNCand);
       std::vector<hipEvent_t> tev;
       const bool measure = choice < 0 && tune_begin(st, TUNE_CROSS_NW, prec, bucket, kNCand, &tev);
       if (choice < 0) choice = 1;

@@ -20,12 +20,14 @@ namespace ctd {
 // true, with 2 events per candidate, when the caller should time every
 // candidate now (event 2c before candidate c, 2c + 1 after it), and then
 // tune_recorded once every record is enqueued: until then no other thread
-// reads the events.  No measurement starts on a stream that is being captured
-// into a graph (its event records would become graph nodes that outlive the
-// events).  The table is shared by the threads of a process.
+// reads the events.  While st is being captured into a graph no measurement
+// starts (its event records would become graph nodes that outlive the
+// events) and none is resolved (querying an event invalidates the capture):
+// tune_get then returns only a choice already made.  The table is shared by
+// the threads of a process.
 enum { TUNE_PROJ_FPW = 0, TUNE_COLS_FPW = 1, TUNE_CROSS_NW = 2 };
 int tune_bucket(int64_t n);
-int tune_get(int knob, int prec, int bucket, int ncand);
+int tune_get(hipStream_t st, int knob, int prec, int bucket, int ncand);
 bool tune_begin(hipStream_t st, int knob, int prec, int bucket, int ncand,
                 std::vector<hipEvent_t>* evs);
 void tune_recorded(int knob, int prec, int bucket);

@@ -951,7 +951,7 @@ void launch_project(hipStream_t st, const ProjectArgs& a, int64_t nnz_max, DevSc
   constexpr int kNCand = 3;
   const bool small = nnz_max <= (int64_t(1) << 18);
   const int prec = a.mixed ? 1 : 0, bucket = tune_bucket(nnz_max);
-  int choice = tune_get(TUNE_PROJ_FPW, prec, bucket, kNCand);
+  int choice = tune_get(st, TUNE_PROJ_FPW, prec, bucket, kNCand);
   std::vector<hipEvent_t> tev;
   const bool measure = choice < 0 && tune_begin(st, TUNE_PROJ_FPW, prec, bucket, kNCand, &tev);
   if (choice < 0) choice = small ? 0 : 2;

@@ -119,6 +119,10 @@ struct BatchState {
   std::vector<uint64_t> last_sig;  // the previous call's signature
   std::vector<uint64_t> graph_sig; // the signature exec was captured for
   hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;       // the stream captured and replayed on
+  hipEvent_t fork = nullptr;       // caller's stream -> cap
+  hipEvent_t join = nullptr;       // cap -> caller's stream
+  int64_t graph_launches = 0;      // calls that ran as a graph launch
 };
 
 }  // namespace ctd

@@ -60,13 +60,26 @@ int tune_bucket(int64_t n) {
   return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)n - 1);
 }
 
-int tune_get(int knob, int prec, int bucket, int ncand) {
+// True when st is being captured into a graph (a stream that cannot report
+// it is taken as not captured).
+static bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
+int tune_get(hipStream_t st, int knob, int prec, int bucket, int ncand) {
   std::lock_guard<std::mutex> lock(g_mu);
   load_file_locked();
   auto it = g_table.find(key_of(knob, prec, bucket));
   if (it == g_table.end()) return -1;
   Entry& e = it->second;
   if (e.choice >= 0 && e.choice < ncand) return e.choice;
+  // querying an event invalidates a capture in progress: resolve later
+  if (capturing(st)) return -1;
   // a measurement another thread is still enqueueing (an event not yet
   // recorded also reads as complete) is not looked at
   if ((int)e.ev.size() != 2 * ncand || !e.recorded) return -1;
@@ -96,12 +109,7 @@ int tune_get(int knob, int prec, int bucket, int ncand) {
 
 bool tune_begin(hipStream_t st, int knob, int prec, int bucket, int ncand,
                 std::vector<hipEvent_t>* evs) {
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
-    (void)hipGetLastError();   // a stream that cannot report it is not being captured
-    cs = hipStreamCaptureStatusNone;
-  }
-  if (cs != hipStreamCaptureStatusNone) return false;
+  if (capturing(st)) return false;
   std::lock_guard<std::mutex> lock(g_mu);
   load_file_locked();
   const uint64_t key = key_of(knob, prec, bucket);

@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
                             "ctd_update_batched", "ctd_decompose_batched", "ctd_get_batch_result",
                             "ctd_sync", "ctd_get_result", "ctd_last_error", "ctd_destroy",
                             "ctd_attack_candidates", "ctd_memory_usage", "ctd_sparse_core",
-                            "ctd_sparse_core_noalloc", "ctd_save_state", "ctd_load_state"])
+                            "ctd_sparse_core_noalloc", "ctd_save_state", "ctd_load_state",
+                            "ctd_batch_graph_launches"])
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libctd.so not built")

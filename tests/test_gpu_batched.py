@@ -148,16 +148,15 @@ def _same(a, b):
                 assert u == v
 
 
-@pytest.mark.skip(reason="aborted once on the GPU (SIGABRT from a runtime thread, no message) "
-                         "during the eager single decomposition that follows a batched call; "
-                         "the cause is not found yet, so the case stays off the GPU")
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_repeated_calls_replay_a_graph_bit_identically(lib, precision):
     """A batched call repeated with the same inputs and sizes is captured once
     (second call) and replayed after that: every replay, with eager work and
     synchronizations of the program between them, gives the eager call's bits;
     a call with other sizes runs directly, and a replay reads the current
-    values of the (same) input buffers."""
+    values of the (same) input buffers.  The handles run on torch's default
+    stream, which cannot be captured itself: the graph runs on a stream of the
+    handle forked from it, and the launch count shows that it did."""
     import torch
     ts = _tensors(19, 7)
     s = _sizes(ts)
@@ -167,25 +166,30 @@ def test_repeated_calls_replay_a_graph_bit_identically(lib, precision):
     try:
         h.decompose_batched(devs, 0, s, 5)
         ref = _batch_snapshot(h, len(ts))
+        assert h.batch_graph_launches() == 0
         for rep in range(5):                      # capture at rep 0, replays after it
             h.decompose_batched(devs, 0, s, 5)
             other.decompose(*devs[rep], 0, s[rep], 9)   # eager work in between
             other.result()
             torch.cuda.synchronize()
             _same(_batch_snapshot(h, len(ts)), ref)
+            assert h.batch_graph_launches() == rep + 1
         s2 = list(s)
         s2[0] += 1                                # another signature: direct launches
         h.decompose_batched(devs, 0, s2, 5)
         o = ora.ctd_s(ts[0].dims, ts[0].idx, ts[0].val, 0, s2[0], 5, tensor=0)
         assert np.array_equal(h.batch_result(0)["accepted"], o.accepted.astype(np.uint64))
+        assert h.batch_graph_launches() == 5
         for rep in range(3):                      # back: direct, capture, replay
             h.decompose_batched(devs, 0, s, 5)
             _same(_batch_snapshot(h, len(ts)), ref)
+        assert h.batch_graph_launches() == 7
         # new values in the same buffers of tensor 3: the replay reads them
         rng = np.random.default_rng(4)
         newval = rng.uniform(0.5, 2.0, size=ts[3].val.shape)
         devs[3][2].copy_(torch.as_tensor(newval, dtype=devs[3][2].dtype, device="cuda"))
         h.decompose_batched(devs, 0, s, 5)
+        assert h.batch_graph_launches() == 8
         got = h.batch_result(3)
         o = ora.ctd_s(ts[3].dims, ts[3].idx, newval, 0, s[3], 5, tensor=3)
         assert np.array_equal(got["draws"], o.draws.astype(np.uint64))

@@ -78,6 +78,7 @@ def test_many_tensors_full_size(many, precision):
         for rep in range(3):
             h.decompose_batched(devs, 0, s, 0)
             h.sync()
+            assert h.batch_graph_launches() == rep + 1, rep   # capture, then replays
             for i, b in enumerate(sel.tolist()):
                 r = h.batch_result(b)
                 for key in ("draws", "unique", "counts", "accepted", "prob", "scale"):
