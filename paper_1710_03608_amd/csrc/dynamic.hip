@@ -242,8 +242,8 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 
 // Cross term: C[d + a][f] = sum_{k<d} Y[a][k] C[k][f] for f in [c_lo, c_hi)
 // (d = K of the pass; pass 0 reads all of C^(t): the HBM-bound step).  Pass
-// p = blockIdx.y.  A product of the 16 RT new rows with C, on f64 MFMAs: a
-// workgroup owns 256 columns, wave w the 64 columns 64 w .. + 64 (four 16-column
+// p = blockIdx.y.  A product of the 16 RT new rows with C, on f64 MFMAs: wave
+// w of a workgroup owns the 16 CT columns 16 CT w .. + 16 CT (CT 16-column
 // tiles) against all RT row tiles.  The reduction runs in chunks of 16 rows
 // of C; lane (i, g) = (l % 16, l / 16) reads C[k0 + 4 g .. + 4][f] of its
 // column as one 32-byte vector (C is column-major), and MFMA t multiplies
@@ -251,13 +251,13 @@ __global__ __launch_bounds__(kBlock) void k_cross_rows(const double* __restrict_
 // rows in a fixed permutation.  The 16 RT x 16 Y chunk is shared through LDS
 // (double-buffered, one barrier per chunk); the next chunk of C is in flight
 // in registers while the current one is in the MFMAs.  C is read once per
-// 16 RT new rows.  NW waves a workgroup (64 NW columns; the Y chunk needs
-// 4 x 16 RT threads): every wave computes its columns the same way whatever
-// NW is, so the autotuner may pick NW.
+// 16 RT new rows.  NW waves a workgroup (the Y chunk needs 4 x 16 RT
+// threads).  With RT = 4 two column tiles per wave (CT = 2) leave room for
+// three waves per SIMD instead of one: more of C in flight per CU.
 constexpr int kCrossCols = 256;
 
-template <int RT, int NW = 4>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 3 : 1)))
+template <int RT, int NW = 4, int CT = 2>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(CT < 4 ? 3 : 1)))
 void k_cross_term(double* __restrict__ C, int64_t ldc,
                                                            const double* __restrict__ Yall,
                                                            int64_t ldy, int64_t ystride,
@@ -268,15 +268,15 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
   const double* Y = Yall + blockIdx.y * ystride;
   const int64_t d = rng[0], na = rng[2], ncols = rng[4];
   static_assert(64 * NW >= 4 * 16 * RT, "the Y chunk needs 4 threads per row");
-  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * (64 * NW);
+  const int64_t f0 = rng[3] + (int64_t)blockIdx.x * (16 * CT * NW);
   if (na <= 0 || f0 >= ncols) return;
   const int t = threadIdx.x, w = t / kWave, l = lane_id(), i = l % 16, g = l / 16;
   const int64_t nch = (d + 15) / 16;
-  const double* cp[4];
-  bool cin[4];
+  const double* cp[CT];
+  bool cin[CT];
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int64_t f = f0 + 64 * w + 16 * ct + i;
+  for (int ct = 0; ct < CT; ++ct) {
+    const int64_t f = f0 + 16 * CT * w + 16 * ct + i;
     cin[ct] = f < ncols;
     cp[ct] = C + (cin[ct] ? f : f0) * ldc + 4 * g;
   }
@@ -293,16 +293,16 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
     const int nr = (int)min<int64_t>(kRows, na - a0);
     const bool yin = yr < nr;
     const double* yrow = Y + (a0 + (yin ? yr : 0)) * ldy + 4 * yg;
-    dbl4 acc[RT][4];
+    dbl4 acc[RT][CT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = dbl4{0, 0, 0, 0};
-    dbl4 cf[4], yv;
+      for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = dbl4{0, 0, 0, 0};
+    dbl4 cf[CT], yv;
     auto load = [&](int64_t ch) {
       const int64_t k = ch * 16 + 4 * g;
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
+      for (int ct = 0; ct < CT; ++ct) {
         cf[ct] = (ch < nch && cin[ct] && k < d) ? *(const dbl4*)(cp[ct] + ch * 16) : dbl4{0, 0, 0, 0};
         cf[ct] = mask4(cf[ct], k);
       }
@@ -314,9 +314,9 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
     int buf = 0;
     for (int64_t ch = 0; ch < nch; ++ch) {
       if (yr < kRows) Ys[buf][yr][yg] = yv;
-      dbl4 cc[4];
+      dbl4 cc[CT];
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) cc[ct] = cf[ct];
+      for (int ct = 0; ct < CT; ++ct) cc[ct] = cf[ct];
       __syncthreads();
       load(ch + 1);
 #pragma unroll
@@ -325,15 +325,15 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
         for (int rt = 0; rt < RT; ++rt) {
           const double a = Ys[buf][rt * 16 + i][g][tt];
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = mfma16(a, cc[ct][tt], acc[rt][ct]);
+          for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma16(a, cc[ct][tt], acc[rt][ct]);
         }
       buf ^= 1;
     }
     // lane (i, g) holds D[g + 4 r][i] of tile (rt, ct): new row rt * 16 + g + 4 r, column ct * 16 + i
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
+    for (int ct = 0; ct < CT; ++ct) {
       if (!cin[ct]) continue;
-      double* col = C + (f0 + 64 * w + 16 * ct + i) * ldc + d + a0;
+      double* col = C + (f0 + 16 * CT * w + 16 * ct + i) * ldc + d + a0;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -350,7 +350,7 @@ void k_cross_term(double* __restrict__ C, int64_t ldc,
 // (i, g) needs exactly Y[a0 + i][k0 + 4 g .. + 4] for its MFMAs, so it reads
 // that 32-byte vector itself (Y is small and stays in L2) and the waves run
 // with no barrier between chunks.  The MFMAs see the same operands in the same
-// order as in k_cross_term<1, NW>, so the values are identical.
+// order as when the chunk was staged through LDS, so the values are the same.
 template <int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)))
 void k_cross_term_direct(double* __restrict__ C, int64_t ldc, const double* __restrict__ Yall,
@@ -1189,13 +1189,12 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
     hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave), B), dim3(kBlock), 0, st, S.Xt,
                        S.capD, Wacc, S.capD, Y, S.capD, ystride, rng);
     if (cols_max > 0 && kept_max > 16) {
-      const int64_t tiles = tiles_of(kCrossCols);
       if (S.Cf)
-        hipLaunchKernelGGL((k_cross_term_bf3<4, 1>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.Cf,
-                           S.capD, Y, S.capD, ystride, rng);
+        hipLaunchKernelGGL((k_cross_term_bf3<4, 1>), dim3(tiles_of(kCrossCols), B), dim3(kCrossCols),
+                           0, st, S.Cf, S.capD, Y, S.capD, ystride, rng);
       else
-        hipLaunchKernelGGL((k_cross_term<4>), dim3(tiles, B), dim3(kCrossCols), 0, st, S.C,
-                           S.capD, Y, S.capD, ystride, rng);
+        hipLaunchKernelGGL((k_cross_term<4, 4, 2>), dim3(tiles_of(128), B), dim3(kCrossCols), 0, st,
+                           S.C, S.capD, Y, S.capD, ystride, rng);
     } else if (cols_max > 0) {
       // at most 16 new rows: waves per workgroup (2, 4 or 8) chosen by the
       // autotuner per bucket of the column count (every choice writes the same
