@@ -150,7 +150,7 @@ def stream_cross_roofline(ctd, st, precision, n_slices=64, batch=1):
     # bfloat16 MFMA with six products of three-part operands per multiply-add
     if precision == "fp64":
         mf = {"achieved": tf, "peak": PEAK_FP64_MFMA, "frac": tf / PEAK_FP64_MFMA,
-              "unit": "TFLOP/s", "kernel": "k_cross_term (float64 MFMA)"}
+              "unit": "TFLOP/s", "kernel": "k_cross_term_direct / k_cross_term (float64 MFMA)"}
     elif batch * STREAM_D <= CROSS_NARROW_ROWS:
         mf = {"achieved": tf, "peak": PEAK_FP32_MFMA, "frac": tf / PEAK_FP32_MFMA,
               "unit": "TFLOP/s", "kernel": "k_cross_term32 (float32 MFMA)"}
@@ -160,8 +160,8 @@ def stream_cross_roofline(ctd, st, precision, n_slices=64, batch=1):
               "kernel": "k_cross_term_bf3 (bfloat16 MFMA, six products per multiply-add)"}
     mf.update({"bound": "mfma", "sample": sample})
     return {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM, "unit": "GB/s",
-            "frac": gbps / PEAK_HBM, "kernel": "k_cross_term (float64) / k_cross_term32 / "
-            "k_cross_term_bf3 (float32 C)", "sample": sample, "mfma": mf}
+            "frac": gbps / PEAK_HBM, "kernel": "k_cross_term_direct / k_cross_term (float64, up to "
+            "16 / more new rows) or k_cross_term32 / k_cross_term_bf3 (float32 C)", "sample": sample, "mfma": mf}
 
 
 def time_many(ctd, tensors, sizes, precision, reps=3):
