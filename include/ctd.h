@@ -31,6 +31,11 @@
  *    device and returned by ctd_sync / ctd_get_result.  After any error the
  *    handle only accepts ctd_decompose, ctd_get_result, ctd_last_error and
  *    ctd_destroy.
+ *  - Device allocations that fail return CTD_ERR_OOM with a message; the
+ *    handle then accepts the same call again.  For testing those paths, the
+ *    environment variable CTD_FAIL_ALLOC=k makes the k-th device allocation
+ *    the library attempts after the value was set (or changed) fail as if
+ *    the device were out of memory; the ones after it succeed.
  *  - Random draws are reproducible: draw j of a call uses Philox4x32-10
  *    (Salmon et al., SC'11) with key (seed mod 2^32, seed >> 32) and counter
  *    (j mod 2^32, j >> 32, step, tensor); step is 0 for ctd_decompose and t

@@ -211,7 +211,7 @@ ctd_status plan_static(ctd_handle* h, int64_t nnz, int64_t s, int64_t n_rows, bo
       A.cap = 0;
     }
     void* p = nullptr;
-    if (hipMalloc(&p, A.off) != hipSuccess) {
+    if (dev_alloc(&p, A.off) != hipSuccess) {
       (void)hipGetLastError();
       return fail(h, CTD_ERR_OOM, "workspace allocation of " + std::to_string(A.off) + " bytes failed");
     }
@@ -338,7 +338,7 @@ ctd_status ensure_bdev(ctd_handle* h, int count) {
     h->bdev = nullptr;
     h->bdev_cap = 0;
   }
-  if (hipMalloc(&h->bdev, basis_dev_bytes(count)) != hipSuccess) {
+  if (dev_alloc(&h->bdev, basis_dev_bytes(count)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(h, CTD_ERR_OOM, "basis argument array allocation failed");
   }
@@ -481,7 +481,7 @@ ctd_status ctd_create(ctd_handle** out, const ctd_options* opt, void* hip_stream
     }
     h->opt = *opt;
   }
-  const hipError_t e = hipMalloc(&h->d_sc, sizeof(DevScalars));
+  const hipError_t e = dev_alloc(&h->d_sc, sizeof(DevScalars));
   if (e != hipSuccess) {
     g_create_error = std::string("hipMalloc of the device scalars: ") + hipGetErrorName(e) + ": " +
                      hipGetErrorString(e);

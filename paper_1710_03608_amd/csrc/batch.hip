@@ -39,7 +39,7 @@ ctd_status new_sub(ctd_handle* h, ctd_handle** out) {
   sub->opt = h->opt;
   sub->keep_R = false;
   sub->w2_sets = 1;
-  if (hipMalloc(&sub->d_sc, sizeof(DevScalars)) != hipSuccess) {
+  if (dev_alloc(&sub->d_sc, sizeof(DevScalars)) != hipSuccess) {
     (void)hipGetLastError();
     delete sub;
     return fail(h, CTD_ERR_OOM, "batch scalar allocation failed");
@@ -239,13 +239,13 @@ ctd_status batched_body(ctd_handle* h, const ctd_coo* Xs, int32_t nb, int32_t mo
     if (rc != CTD_OK) return rc;
     batch_free_storage(&B);
     const size_t nt = (size_t)nb, ns = (size_t)std::max<int64_t>(total_s, 1);
-    bool ok = hipMalloc(&B.scal, nt * sizeof(DevScalars)) == hipSuccess &&
-              hipMalloc(&B.draws, ns * 8) == hipSuccess &&
-              hipMalloc(&B.unique, ns * 8) == hipSuccess &&
-              hipMalloc(&B.accepted, ns * 8) == hipSuccess &&
-              hipMalloc(&B.counts, ns * 4) == hipSuccess &&
-              hipMalloc(&B.prob, ns * 8) == hipSuccess &&
-              hipMalloc(&B.scale, ns * 8) == hipSuccess;
+    bool ok = dev_alloc(&B.scal, nt * sizeof(DevScalars)) == hipSuccess &&
+              dev_alloc(&B.draws, ns * 8) == hipSuccess &&
+              dev_alloc(&B.unique, ns * 8) == hipSuccess &&
+              dev_alloc(&B.accepted, ns * 8) == hipSuccess &&
+              dev_alloc(&B.counts, ns * 4) == hipSuccess &&
+              dev_alloc(&B.prob, ns * 8) == hipSuccess &&
+              dev_alloc(&B.scale, ns * 8) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       batch_free_storage(&B);

@@ -776,7 +776,7 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
   N.rows = n_rows;
   N.mixed = mixed;
   auto alloc = [&](void** p, size_t bytes) -> bool {
-    if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+    if (dev_alloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
       (void)hipGetLastError();
       return false;
     }
@@ -1085,7 +1085,7 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       (void)hipFree(S.ws);
       S.ws = nullptr;
     }
-    if (hipMalloc(&S.ws, ws_doubles * 8) != hipSuccess) {
+    if (dev_alloc(&S.ws, ws_doubles * 8) != hipSuccess) {
       (void)hipGetLastError();
       S.ws_bytes = 0;
       return fail(h, CTD_ERR_OOM, "CTD-D workspace allocation failed");

@@ -12,6 +12,16 @@
 namespace ctd {
 
 // ---- tune.hip --------------------------------------------------------------
+// Every device allocation of the library goes through dev_alloc.  With the
+// environment variable CTD_FAIL_ALLOC set to k, the k-th allocation after the
+// value was last set or changed fails with hipErrorOutOfMemory without calling
+// the runtime (fault injection for the error paths; later ones succeed).
+hipError_t dev_alloc_raw(void** p, size_t bytes);
+template <typename T>
+inline hipError_t dev_alloc(T** p, size_t bytes) {
+  return dev_alloc_raw((void**)p, bytes);
+}
+
 // Per-process choice among bit-identical kernel variants (fibers per wave of
 // the projection and of C's columns, waves per workgroup of the CTD-D cross
 // term for at most 16 new rows), by shape bucket

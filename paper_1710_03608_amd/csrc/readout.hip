@@ -125,7 +125,7 @@ extern "C" ctd_status ctd_attack_candidates(ctd_handle* h, int32_t group_mode, u
   *n_groups = 0;
   if (k <= 0) return CTD_OK;
   double* d_norm = nullptr;
-  RO_HIP(h, hipMalloc(&d_norm, (size_t)k * sizeof(double)));
+  RO_HIP(h, dev_alloc(&d_norm, (size_t)k * sizeof(double)));
   hipLaunchKernelGGL(k_col_norms, dim3((unsigned)((k + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      h->stream, res.R, res.ldr, h->n_rows, k, d_norm);
   std::vector<double> nrm(k);
@@ -177,7 +177,7 @@ extern "C" ctd_status ctd_memory_usage(ctd_handle* h, ctd_memory* out) {
   *out = ctd_memory{};
   out->nnz_X = h->nnz_seen;
   unsigned long long* d_cnt = nullptr;
-  RO_HIP(h, hipMalloc(&d_cnt, 2 * sizeof(unsigned long long)));
+  RO_HIP(h, dev_alloc(&d_cnt, 2 * sizeof(unsigned long long)));
   hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, h->stream, d_cnt);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && k > 0) {

@@ -256,9 +256,9 @@ struct CoreWs {
   hipError_t front(int64_t n_rows, int64_t nparts) {
     if (!base) {
       owned = true;
-      hipError_t e = hipMalloc(&rptr, (size_t)(n_rows + 1) * sizeof(int64_t));
+      hipError_t e = dev_alloc(&rptr, (size_t)(n_rows + 1) * sizeof(int64_t));
       if (e != hipSuccess) return e;
-      return hipMalloc(&part, (size_t)nparts * sizeof(int64_t));
+      return dev_alloc(&part, (size_t)nparts * sizeof(int64_t));
     }
     rptr = (int64_t*)base;
     part = (int64_t*)(base + align256((size_t)(n_rows + 1) * sizeof(int64_t)));
@@ -275,9 +275,9 @@ struct CoreWs {
   hipError_t lists(int64_t nnz_r) {
     const size_t n = (size_t)std::max<int64_t>(nnz_r, 1);
     if (owned) {
-      hipError_t e = hipMalloc(&rcol, n * sizeof(int32_t));
+      hipError_t e = dev_alloc(&rcol, n * sizeof(int32_t));
       if (e != hipSuccess) return e;
-      return hipMalloc(&rval, n * sizeof(double));
+      return dev_alloc(&rval, n * sizeof(double));
     }
     rval = (double*)(base + head);
     rcol = (int32_t*)(base + head + align256(n * sizeof(double)));

@@ -10,6 +10,7 @@
 #include <stdlib.h>
 
 #include <map>
+#include <string>
 #include <mutex>
 #include <vector>
 
@@ -132,6 +133,26 @@ void tune_recorded(int knob, int prec, int bucket) {
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_table.find(key_of(knob, prec, bucket));
   if (it != g_table.end()) it->second.recorded = true;
+}
+
+hipError_t dev_alloc_raw(void** p, size_t bytes) {
+  static std::mutex mu;
+  static std::string seen;
+  static long left = 0;
+  const char* e = getenv("CTD_FAIL_ALLOC");
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const std::string cur = e ? e : "";
+    if (cur != seen) {
+      seen = cur;
+      left = cur.empty() ? 0 : atol(cur.c_str());
+    }
+    if (left > 0 && --left == 0) {
+      *p = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  return hipMalloc(p, bytes);
 }
 
 }  // namespace ctd
