@@ -1,18 +1,19 @@
 // Stable LSD radix sort of 64-bit keys with a 32-bit payload (8-bit digits).
 //
-// Per digit pass: a histogram kernel counts digits per 4096-key tile, a spine
+// Per digit pass: a histogram kernel counts digits per 2048-key tile, a spine
 // kernel turns the digit-major (digit, tile) counts into exclusive offsets
 // (one workgroup per digit), and a scatter kernel ranks keys inside each
-// tile with wave ballots (stable: earlier keys of a digit get lower ranks)
-// and writes them to their final positions.  Integer work only, so results
-// are exact and independent of scheduling.
+// tile with wave ballots (stable: earlier keys of a digit get lower ranks),
+// orders the tile by digit in LDS and writes it out from there, so the keys
+// of one digit leave a tile as one contiguous run.  Integer work only, so
+// results are exact and independent of scheduling.
 #include "kernels.h"
 
 namespace ctd {
 
 namespace {
 constexpr int kSortBlock = 256;                 // 4 waves
-constexpr int kSortItems = 16;                  // keys per lane
+constexpr int kSortItems = 8;                   // keys per lane
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kRadix = 256;
 constexpr int kWavesPerBlock = kSortBlock / kWave;
@@ -63,9 +64,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const int32_t* d_n, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ dtot, int nblocks) {
   __shared__ uint32_t gofs[kRadix];
+  __shared__ uint32_t lofs[kRadix];
   __shared__ uint32_t wcnt[kWavesPerBlock][kRadix];
   __shared__ uint32_t wpre[kWavesPerBlock][kRadix];
   __shared__ uint32_t tmp[kWavesPerBlock + 1];
+  __shared__ uint64_t sk[kSortTile];   // the tile ordered by digit (stable)
+  __shared__ uint32_t sv[kSortTile];
   const int64_t n = d_n ? (int64_t)*d_n : n_max;
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= n) return;  // uniform for the whole block
@@ -107,25 +111,38 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     v[it] = val;
   }
   __syncthreads();
-  {
-    uint32_t run = 0;
+  uint32_t run = 0;   // the tile's count of digit threadIdx.x
 #pragma unroll
-    for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
-      const uint32_t c = wcnt[w2][threadIdx.x];
-      wpre[w2][threadIdx.x] = run;
-      run += c;
-    }
+  for (int w2 = 0; w2 < kWavesPerBlock; ++w2) {
+    const uint32_t c = wcnt[w2][threadIdx.x];
+    wpre[w2][threadIdx.x] = run;
+    run += c;
   }
+  uint32_t tile_tot;
+  lofs[threadIdx.x] = block_excl_scan<uint32_t, kSortBlock>(run, tmp, &tile_tot);
   __syncthreads();
+  // a key's place in the tile ordered by digit is its place among the
+  // tile's keys of that digit after the tile's keys of smaller digits; the
+  // ordered tile is then written out with neighbouring threads on
+  // neighbouring places, so each digit's run of the output is written whole
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     const int64_t e = base + (int64_t)w * kWaveSpan + (int64_t)it * kWave + lane;
     if (e < n) {
       const uint32_t d = (uint32_t)(k[it] >> shift) & 0xFFu;
-      const uint32_t pos = gofs[d] + wpre[w][d] + rk[it];
-      okeys[pos] = k[it];
-      ovals[pos] = v[it];
+      const uint32_t lp = lofs[d] + wpre[w][d] + rk[it];
+      sk[lp] = k[it];
+      sv[lp] = v[it];
     }
+  }
+  __syncthreads();
+  const int m = (int)min<int64_t>(kSortTile, n - base);
+  for (int j = threadIdx.x; j < m; j += kSortBlock) {
+    const uint64_t key = sk[j];
+    const uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+    const uint32_t pos = gofs[d] + ((uint32_t)j - lofs[d]);
+    okeys[pos] = key;
+    ovals[pos] = sv[j];
   }
 }
 }  // namespace
