@@ -90,6 +90,27 @@ def test_stream_matches_oracle(lib, seed, s, d, J):
     check_core(st, o, final, 1)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_slices_take_the_hot_row_projection(lib, precision):
+    """Slices of more than 2^18 nonzeros over 1500 rows: their residual runs
+    through the hot-row split of the projection, with Q of the grown basis
+    (leading dimension the stream's capacity) and its column count."""
+    st = synth.traffic_stream(dims=(1500, 2000, 4), nnz0=300000, n_slices=2,
+                              slice_nnz=(280000, 290000), zipf_a=1.1, n_anomalies=0, seed=21)
+    assert all(sl.nnz > 2 ** 18 for sl in st.slices)
+    o = ora.Dynamic(st.initial.dims, st.initial.idx, st.initial.val, 0, 600, 21)
+    steps, final = _run(lib, st, 600, 20, 21, precision=precision)
+    rtol, atol = (1e-6, 1e-12) if precision == "fp64" else (1e-4, 1e-8)
+    assert np.array_equal(steps[0]["accepted"], o.static.accepted.astype(np.uint64))
+    for t, sl in enumerate(st.slices):
+        info = o.update(sl.dims, sl.idx, sl.val, 20)
+        g = steps[t + 1]
+        assert g["s_tilde"] == info["d_tilde"], t
+        assert abs(g["rel_err"] - o.rel_err) <= rtol * o.rel_err + atol, (t, g["rel_err"], o.rel_err)
+    assert np.array_equal(np.sort(final["accepted"]), np.sort(np.array(o.accepted, dtype=np.uint64)))
+    check_core(st, o, final, 1, precision)
+
+
 def test_empty_and_zero_slices(lib):
     import torch
     st = _stream(9, n_slices=2)
