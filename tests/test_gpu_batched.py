@@ -129,6 +129,32 @@ def test_few_tensors_with_many_blocks(lib, precision):
         h.close()
 
 
+def test_large_tensor_in_a_batch_takes_the_hot_row_projection(lib):
+    """A tensor of more than 2^18 nonzeros among small ones: its projection
+    runs the hot-row split inside the batched call, also when the call is
+    captured as a graph and replayed."""
+    ts = [synth.power_law_tensor((1500, 500, 40), 300000, 45, zipf_a=1.3),
+          synth.power_law_tensor((90, 200, 10), 5000, 42, zipf_a=1.2, values="uniform"),
+          synth.power_law_tensor((200, 80, 15), 7000, 43, zipf_a=1.2, values="uniform")]
+    s = [900, 60, 90]
+    devs = [lib.to_device(t, "cuda") for t in ts]
+    h = lib.Ctd()
+    try:
+        h.decompose_batched(devs, 0, s, 7)
+        ref = _batch_snapshot(h, len(ts))
+        for b, t in enumerate(ts):
+            o = ora.ctd_s(t.dims, t.idx, t.val, 0, s[b], 7, tensor=b)
+            g = h.batch_result(b)
+            assert np.array_equal(g["accepted"], o.accepted.astype(np.uint64)), b
+            assert abs(g["rel_err"] - o.rel_err) <= 1e-6 * o.rel_err + 1e-12, (b, g["rel_err"], o.rel_err)
+        for rep in range(3):                      # captured, then replayed twice
+            h.decompose_batched(devs, 0, s, 7)
+            _same(_batch_snapshot(h, len(ts)), ref)
+        assert h.batch_graph_launches() == 3
+    finally:
+        h.close()
+
+
 def _batch_snapshot(h, n):
     out = []
     for b in range(n):
