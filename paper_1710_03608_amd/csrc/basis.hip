@@ -873,23 +873,43 @@ __device__ inline double bcast(double v, int src) {
 }
 
 // Double-double Cholesky with drop of the leading n x n block of (Ah, Al)
-// (lower triangle, kChol threads), blocked by panels of kPanel columns: wave
-// 0 factors a panel on its own (lane i holds row i of the panel's columns;
-// the pivot and L[c][j] come from their lanes by readlane, so a panel's steps
-// need no barrier), then all waves subtract the panel's rank-kPanel product
-// from the trailing columns (wave w: columns w + 16 q, lane i: row i), two
-// barriers per panel instead of one per column.  Candidate j is kept iff
+// (lower triangle, kChol threads), blocked by panels of kPanel columns, with
+// a one-panel lookahead.  For panel p: first waves 0 .. kPanel - 1 subtract
+// panel p - 1's rank-kPanel product from panel p's columns (wave w: column
+// c0 + w); then wave 0 factors panel p on its own (lane i holds row i of the
+// panel's columns; the pivot and L[c][j] come from their lanes by readlane,
+// so a panel's steps need no barrier) while the other waves subtract panel
+// p - 1's product from the columns past panel p (wave w: columns c0 + kPanel
+// + w - 1 + 15 q, lane i: row i).  Every entry still takes the panels'
+// products in panel order, as without the lookahead.  Candidate j is kept iff
 // its Schur pivot exceeds eps2 * gs[j] and fewer than `room` are kept so far;
 // a dropped candidate's column of L is zero.  L replaces (Ah, Al) in place;
 // returns the kept mask (same in every thread).
 constexpr int kPanel = 8;
+// A[i][c] -= sum_{j in the panel at p0} L[i][j] L[c][j] for i >= c
+__device__ inline void panel_update(LdsMat& Ah, LdsMat& Al, int i, int c, int p0) {
+  double ah = Ah[i][c], al = Al[i][c];
+#pragma unroll
+  for (int jj = 0; jj < kPanel; ++jj)
+    dd_fnma(ah, al, Ah[i][p0 + jj], Al[i][p0 + jj], Ah[c][p0 + jj], Al[c][p0 + jj]);
+  Ah[i][c] = ah;
+  Al[i][c] = al;
+}
 __device__ uint64_t wg_chol_drop_blocked(LdsMat& Ah, LdsMat& Al, const double* gs, int n,
                                          double eps2, int64_t room, uint64_t* s_mask) {
   constexpr int kWaves = kChol / kWave;
+  static_assert(kPanel <= kWaves, "one wave per column of the next panel");
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), i = lane_id();
   uint64_t mask = 0;   // wave 0's
   int kept = 0;
   for (int c0 = 0; c0 < n; c0 += kPanel) {
+    const int p0 = c0 - kPanel;   // the previous panel
+    if (c0 > 0) {
+      // panel p - 1's product on panel p's columns
+      const int c = c0 + w;
+      if (w < kPanel && c < n && i >= c && i < n) panel_update(Ah, Al, i, c, p0);
+      __syncthreads();
+    }
     if (w == 0) {
       double h[kPanel], l[kPanel];
 #pragma unroll
@@ -932,30 +952,14 @@ __device__ uint64_t wg_chol_drop_blocked(LdsMat& Ah, LdsMat& Al, const double* g
           Al[i][c] = l[cc];
         }
       }
-    }
-    __syncthreads();
-    // A[i][c] -= sum_{j in panel} L[i][j] L[c][j] for c past the panel, i >= c
-    // (row i of the panel read once; L[c][j] is the same address in every lane)
-    if (i < n && c0 + kPanel + w < n) {
-      double lh[kPanel], ll[kPanel];
-#pragma unroll
-      for (int jj = 0; jj < kPanel; ++jj) {
-        lh[jj] = Ah[i][c0 + jj];
-        ll[jj] = Al[i][c0 + jj];
-      }
-      for (int c = c0 + kPanel + w; c < n; c += kWaves) {
-        if (i >= c) {
-          double ah = Ah[i][c], al = Al[i][c];
-#pragma unroll
-          for (int jj = 0; jj < kPanel; ++jj)
-            dd_fnma(ah, al, lh[jj], ll[jj], Ah[c][c0 + jj], Al[c][c0 + jj]);
-          Ah[i][c] = ah;
-          Al[i][c] = al;
-        }
-      }
+    } else if (c0 > 0 && i < n) {
+      // panel p - 1's product on the columns past panel p
+      for (int c = c0 + kPanel + w - 1; c < n; c += kWaves - 1)
+        if (i >= c) panel_update(Ah, Al, i, c, p0);
     }
     __syncthreads();
   }
+  // the last panel's product is not needed: no column follows it
   if (threadIdx.x == 0) *s_mask = mask;
   __syncthreads();
   return *s_mask;
