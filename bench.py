@@ -112,12 +112,12 @@ def time_stream(ctd, st, precision, batch=1):
     return out
 
 
-def stream_cross_roofline(ctd, st, precision, n_slices=64, batch=1):
+def stream_cross_roofline(ctd, st, precision, n_slices=None, batch=1):
     """HBM roofline of the CTD-D cross term (Eq. 13): per update (one slice, or a
     batch of slices) that keeps fibers, one pass reads the d~_t x n_cols_t block of C
     held before it and writes the new rows over those columns.  Algorithmic bytes / the
-    cross-term stage time (HIP events on the library's stream), over the first n_slices
-    slices."""
+    cross-term stage time (HIP events on the library's stream), over the whole stream
+    (or its first n_slices slices)."""
     dims0, idx0, val0 = ctd.to_device(st.initial, "cuda")
     slices = [ctd.to_device(sl, "cuda") for sl in st.slices[:n_slices]]
     h = ctd.Ctd(precision=precision, want_C=True, profile=True)
@@ -142,7 +142,8 @@ def stream_cross_roofline(ctd, st, precision, n_slices=64, batch=1):
     h.close()
     gbps = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    sample = (f"first {len(slices)} slices, " + ("unbatched" if batch == 1 else f"in batches of {batch}")
+    sample = ((f"all {len(slices)} slices, " if len(slices) == len(st.slices) else f"first {len(slices)} slices, ")
+              + ("unbatched" if batch == 1 else f"in batches of {batch}")
               + f", {passes} cross-term passes, {nbytes / 1e9:.1f} GB read and written, "
               f"{flops:.3e} flop")
     # the matrix unit of the passes: float64 MFMA; a float32 C on float32 MFMA when
