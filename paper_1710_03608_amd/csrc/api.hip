@@ -26,10 +26,12 @@ void* Arena::take(size_t bytes) {
 }  // namespace ctd
 
 namespace ctd {
-void mark(ctd_handle* h, int i) {
+void mark(ctd_handle* h, int i) { mark_on(h, i, h->stream); }
+
+void mark_on(ctd_handle* h, int i, hipStream_t st) {
   if (!h->opt.profile) return;
   if (!h->ev[i]) (void)hipEventCreate(&h->ev[i]);
-  (void)hipEventRecord(h->ev[i], h->stream);
+  (void)hipEventRecord(h->ev[i], st);
   h->ev_used[i] = true;
 }
 
@@ -578,6 +580,7 @@ const char* ctd_last_error(const ctd_handle* h) {
 void ctd_destroy(ctd_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  if (h->xstream) (void)hipStreamSynchronize(h->xstream);
   if (h->batch) {
     ctd::BatchState* B = h->batch;
     for (hipStream_t st : B->pool) (void)hipStreamSynchronize(st);
@@ -601,6 +604,9 @@ void ctd_destroy(ctd_handle* h) {
   dyn_free(h);
   if (h->bdev) (void)hipFree(h->bdev);
   if (h->side_state > 0) basis_side_free(&h->side);
+  if (h->xstream) (void)hipStreamDestroy(h->xstream);
+  if (h->xfork) (void)hipEventDestroy(h->xfork);
+  if (h->xjoin) (void)hipEventDestroy(h->xjoin);
   if (h->arena.base) (void)hipFree(h->arena.base);
   if (h->d_sc) (void)hipFree(h->d_sc);
   delete h;

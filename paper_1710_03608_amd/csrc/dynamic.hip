@@ -844,6 +844,27 @@ ctd_status dyn_reserve(ctd_handle* h, int64_t capD, int64_t capN) {
   return CTD_OK;
 }
 
+// The handle's cross stream and its fork and join events, created at first
+// use (default priority); false if they cannot be created.
+bool cross_stream(ctd_handle* h) {
+  if (!h->xstream && hipStreamCreateWithFlags(&h->xstream, hipStreamNonBlocking) != hipSuccess) {
+    h->xstream = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  if (!h->xfork && hipEventCreateWithFlags(&h->xfork, hipEventDisableTiming) != hipSuccess) {
+    h->xfork = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  if (!h->xjoin && hipEventCreateWithFlags(&h->xjoin, hipEventDisableTiming) != hipSuccess) {
+    h->xjoin = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
 ctd_status dyn_sync_sizes(ctd_handle* h) {
   DevScalars sc{};
   HIP_CHECK(h, hipStreamSynchronize(h->stream));
@@ -1099,6 +1120,82 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
   int64_t* rng = info + 2 * (B + 1);
 
   for (bool& u : h->ev_used) u = false;
+  // C rows of the batch's kept fibers (Eq. 13): pass 0 over the columns held
+  // before the batch, pass b + 1 over the columns of slice b
+  auto cross_stage = [&](hipStream_t cs) {
+    mark_on(h, MARK_CROSS0, cs);
+    {
+      // columns of the widest pass: those held before the batch, or a slice's
+      int64_t cols_max = S.n_cols_ub;
+      for (int p = 1; p < B; ++p) cols_max = std::max<int64_t>(cols_max, slices[p - 1].nnz);
+      auto tiles_of = [&](int cols) { return (cols_max + cols - 1) / cols; };
+      const int64_t ystride = kept_max * S.capD;
+      hipLaunchKernelGGL(k_cross_setup, dim3(1), dim3(CTD_MAX_BATCH), 0, cs, info, B, sc, rng);
+      hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave), B), dim3(kBlock), 0, cs, S.Xt,
+                         S.capD, Wacc, S.capD, Y, S.capD, ystride, rng);
+      if (cols_max > 0 && kept_max > 16) {
+        if (S.Cf)
+          hipLaunchKernelGGL((k_cross_term_bf3<4, 1>), dim3(tiles_of(kCrossCols), B), dim3(kCrossCols),
+                             0, cs, S.Cf, S.capD, Y, S.capD, ystride, rng);
+        else
+          hipLaunchKernelGGL((k_cross_term<4, 4, 2>), dim3(tiles_of(128), B), dim3(kCrossCols), 0, cs,
+                             S.C, S.capD, Y, S.capD, ystride, rng);
+      } else if (cols_max > 0) {
+        // at most 16 new rows: waves per workgroup (2, 4 or 8) chosen by the
+        // autotuner per bucket of the column count (every choice writes the same
+        // values; a measuring call runs all three, each reading rows < d only)
+        constexpr int kNCand = 3;
+        const int prec = S.Cf ? 1 : 0, bucket = tune_bucket(cols_max);
+        int choice = tune_get(cs, TUNE_CROSS_NW, prec, bucket, kNCand);
+        std::vector<hipEvent_t> tev;
+        const bool measure = choice < 0 && tune_begin(cs, TUNE_CROSS_NW, prec, bucket, kNCand, &tev);
+        if (choice < 0) choice = 1;
+        auto cross = [&](int c) {
+          const int nw = 2 << c;
+          const dim3 grid((unsigned)tiles_of(64 * nw), B);
+          if (S.Cf) {
+            if (nw == 2)
+              hipLaunchKernelGGL((k_cross_term32<1, 2>), grid, dim3(128), 0, cs, S.Cf, S.capD, Y, S.capD,
+                                 ystride, rng);
+            else if (nw == 4)
+              hipLaunchKernelGGL((k_cross_term32<1, 4>), grid, dim3(256), 0, cs, S.Cf, S.capD, Y, S.capD,
+                                 ystride, rng);
+            else
+              hipLaunchKernelGGL((k_cross_term32<1, 8>), grid, dim3(512), 0, cs, S.Cf, S.capD, Y, S.capD,
+                                 ystride, rng);
+          } else {
+            if (nw == 2)
+              hipLaunchKernelGGL((k_cross_term_direct<2>), grid, dim3(128), 0, cs, S.C, S.capD, Y, S.capD,
+                                 ystride, rng);
+            else if (nw == 4)
+              hipLaunchKernelGGL((k_cross_term_direct<4>), grid, dim3(256), 0, cs, S.C, S.capD, Y, S.capD,
+                                 ystride, rng);
+            else
+              hipLaunchKernelGGL((k_cross_term_direct<8>), grid, dim3(512), 0, cs, S.C, S.capD, Y, S.capD,
+                                 ystride, rng);
+          }
+        };
+        if (measure) {
+          for (int c = 0; c < kNCand; ++c) {
+            (void)hipEventRecord(tev[2 * c], cs);
+            cross(c);
+            (void)hipEventRecord(tev[2 * c + 1], cs);
+          }
+          tune_recorded(TUNE_CROSS_NW, prec, bucket);
+        } else {
+          cross(choice);
+        }
+      }
+    }
+    mark_on(h, MARK_CORE, cs);
+  };
+  // A one-slice update's cross term needs only the rank after the slice's
+  // filter: it runs on the handle's cross stream beside the slice's own
+  // columns and residual (which write other parts of C and read neither Y
+  // nor the ranges), and the handle's stream waits for it before the call
+  // ends.
+  const bool early_cross = B == 1 && cross_stream(h);
+  bool cross_forked = false;
   mark(h, MARK_START);
   int64_t d_ub = S.d_ub;
   for (int bi = 0; bi < B; ++bi) {
@@ -1151,6 +1248,14 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
       if (rc != CTD_OK) return rc;
       launch_basis(st, &ba, &sc, 1, h->bdev, basis_side(h));
       mark(h, MARK_BASIS);
+      if (early_cross) {
+        hipLaunchKernelGGL(k_batch_mark, dim3(1), dim3(1), 0, st, sc, info, 1);
+        HIP_CHECK(h, hipEventRecord(h->xfork, st));
+        HIP_CHECK(h, hipStreamWaitEvent(h->xstream, h->xfork, 0));
+        cross_stage(h->xstream);
+        HIP_CHECK(h, hipEventRecord(h->xjoin, h->xstream));
+        cross_forked = true;
+      }
       // the slice's own columns R^(t+1)T dX (rows held after its filter)
       if (mixed)
         launch_cols<float>(st, b, nnz, sc, S.Rs, S.capD, &sc->n_accept_total, d_next, S.Cf, S.capD,
@@ -1175,74 +1280,12 @@ extern "C" ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, i
     hipLaunchKernelGGL(k_finish_slice, dim3(1), dim3(1), 0, st, sc);
     d_ub = d_next;
   }
-  hipLaunchKernelGGL(k_batch_mark, dim3(1), dim3(1), 0, st, sc, info, B);
-  // C rows of the batch's kept fibers (Eq. 13): pass 0 over the columns held
-  // before the batch, pass b + 1 over the columns of slice b
-  mark(h, MARK_CROSS0);
-  {
-    // columns of the widest pass: those held before the batch, or a slice's
-    int64_t cols_max = S.n_cols_ub;
-    for (int p = 1; p < B; ++p) cols_max = std::max<int64_t>(cols_max, slices[p - 1].nnz);
-    auto tiles_of = [&](int cols) { return (cols_max + cols - 1) / cols; };
-    const int64_t ystride = kept_max * S.capD;
-    hipLaunchKernelGGL(k_cross_setup, dim3(1), dim3(CTD_MAX_BATCH), 0, st, info, B, sc, rng);
-    hipLaunchKernelGGL(k_cross_rows, dim3(grid_for(S.capD * kWave), B), dim3(kBlock), 0, st, S.Xt,
-                       S.capD, Wacc, S.capD, Y, S.capD, ystride, rng);
-    if (cols_max > 0 && kept_max > 16) {
-      if (S.Cf)
-        hipLaunchKernelGGL((k_cross_term_bf3<4, 1>), dim3(tiles_of(kCrossCols), B), dim3(kCrossCols),
-                           0, st, S.Cf, S.capD, Y, S.capD, ystride, rng);
-      else
-        hipLaunchKernelGGL((k_cross_term<4, 4, 2>), dim3(tiles_of(128), B), dim3(kCrossCols), 0, st,
-                           S.C, S.capD, Y, S.capD, ystride, rng);
-    } else if (cols_max > 0) {
-      // at most 16 new rows: waves per workgroup (2, 4 or 8) chosen by the
-      // autotuner per bucket of the column count (every choice writes the same
-      // values; a measuring call runs all three, each reading rows < d only)
-      constexpr int kNCand = 3;
-      const int prec = S.Cf ? 1 : 0, bucket = tune_bucket(cols_max);
-      int choice = tune_get(st, TUNE_CROSS_NW, prec, bucket, kNCand);
-      std::vector<hipEvent_t> tev;
-      const bool measure = choice < 0 && tune_begin(st, TUNE_CROSS_NW, prec, bucket, kNCand, &tev);
-      if (choice < 0) choice = 1;
-      auto cross = [&](int c) {
-        const int nw = 2 << c;
-        const dim3 grid((unsigned)tiles_of(64 * nw), B);
-        if (S.Cf) {
-          if (nw == 2)
-            hipLaunchKernelGGL((k_cross_term32<1, 2>), grid, dim3(128), 0, st, S.Cf, S.capD, Y, S.capD,
-                               ystride, rng);
-          else if (nw == 4)
-            hipLaunchKernelGGL((k_cross_term32<1, 4>), grid, dim3(256), 0, st, S.Cf, S.capD, Y, S.capD,
-                               ystride, rng);
-          else
-            hipLaunchKernelGGL((k_cross_term32<1, 8>), grid, dim3(512), 0, st, S.Cf, S.capD, Y, S.capD,
-                               ystride, rng);
-        } else {
-          if (nw == 2)
-            hipLaunchKernelGGL((k_cross_term_direct<2>), grid, dim3(128), 0, st, S.C, S.capD, Y, S.capD,
-                               ystride, rng);
-          else if (nw == 4)
-            hipLaunchKernelGGL((k_cross_term_direct<4>), grid, dim3(256), 0, st, S.C, S.capD, Y, S.capD,
-                               ystride, rng);
-          else
-            hipLaunchKernelGGL((k_cross_term_direct<8>), grid, dim3(512), 0, st, S.C, S.capD, Y, S.capD,
-                               ystride, rng);
-        }
-      };
-      if (measure) {
-        for (int c = 0; c < kNCand; ++c) {
-          (void)hipEventRecord(tev[2 * c], st);
-          cross(c);
-          (void)hipEventRecord(tev[2 * c + 1], st);
-        }
-        tune_recorded(TUNE_CROSS_NW, prec, bucket);
-      } else {
-        cross(choice);
-      }
-    }
+  if (cross_forked) {
+    HIP_CHECK(h, hipStreamWaitEvent(st, h->xjoin, 0));
+  } else {
+    hipLaunchKernelGGL(k_batch_mark, dim3(1), dim3(1), 0, st, sc, info, B);
+    cross_stage(st);
   }
-  mark(h, MARK_CORE);
   mark(h, MARK_END);
   HIP_CHECK(h, hipGetLastError());
   h->s = d;

@@ -155,6 +155,10 @@ struct ctd_handle {
   int bdev_cap = 0;
   ctd::BasisSide side{};            // side stream of the basis (created at first use)
   int side_state = 0;               // 0 not yet tried, 1 held, -1 unavailable
+  // CTD-D cross term of a one-slice update, beside the slice's own columns
+  // and residual (created at first use; default priority)
+  hipStream_t xstream = nullptr;
+  hipEvent_t xfork = nullptr, xjoin = nullptr;
   ctd::BatchState* batch = nullptr;
 };
 
@@ -165,6 +169,7 @@ enum { MARK_START = 0, MARK_SORTED = 1, MARK_SAMPLED = 2, MARK_PANEL = 3, MARK_B
        MARK_SPMM0 = 5, MARK_SPMM1 = 6, MARK_PROJECTED = 7, MARK_CORE = 8, MARK_END = 9,
        MARK_PROJ0 = 10, MARK_CROSS0 = 11, MARK_COUNT = 12 };
 void mark(ctd_handle* h, int i);
+void mark_on(ctd_handle* h, int i, hipStream_t st);
 int bits_for(uint64_t n);
 int64_t round8(int64_t x);
 ctd_status fail(ctd_handle* h, ctd_status st, const std::string& msg);
