@@ -168,7 +168,11 @@ ctd_status ctd_decompose_given(ctd_handle* h, const ctd_coo* X, int32_t mode,
 
 /* CTD-D, Algorithm 2 (Section 3.2): one time slice dX whose dims equal the
  * stream's first N-1 dims with a last dim of 1, d draws (1 <= d <= dN_alpha).
- * Requires a prior ctd_decompose with want_C set and a non-time mode. */
+ * Requires a prior ctd_decompose with want_C set and a non-time mode.  The
+ * rows of C for the slice's kept fibers over the earlier columns (Eq. 13) are
+ * written on a stream of the handle (default priority) beside the slice's
+ * own columns and residual; the handle's stream waits for it before the call
+ * returns, so later work on that stream sees all of C. */
 ctd_status ctd_update(ctd_handle* h, const ctd_coo* slice, int64_t d);
 
 /* CTD-D on B consecutive slices (Algorithm 2 applied B times in order): the
