@@ -61,7 +61,7 @@ typedef enum {
   CTD_ERR_OOM = 6,          /* device allocation failed */
   CTD_ERR_HIP = 7,          /* a HIP runtime call failed */
   CTD_ERR_STATE = 8,        /* call not valid in the handle's state (update before decompose, shape mismatch) */
-  CTD_ERR_CAPACITY = 9      /* a size exceeds a documented limit of this build */
+  CTD_ERR_CAPACITY = 9      /* a size exceeds a documented limit of the library */
 } ctd_status;
 
 enum { CTD_F64 = 0, CTD_F32 = 1 };                 /* value dtype of a ctd_coo */
@@ -195,7 +195,7 @@ ctd_status ctd_update_batched(ctd_handle* h, const ctd_coo* slices, int32_t B, i
  * holds the size the state needs (about (2 I_alpha + n_cols) d~ values plus
  * the ids); host_buf == NULL only reports it (CTD_OK); a buffer smaller than
  * that returns CTD_ERR_CAPACITY and writes nothing.  The buffer is plain
- * bytes in this build's native layout (versioned header, then the arrays),
+ * bytes in the library's native layout (versioned header, then the arrays),
  * owned by the caller.  Needs a CTD-D stream: a ctd_decompose with want_C on
  * a non-time mode, with or without updates after it (else CTD_ERR_STATE). */
 ctd_status ctd_save_state(ctd_handle* h, void* host_buf, size_t* bytes);
@@ -327,7 +327,7 @@ const char* ctd_last_error(const ctd_handle* h);
 
 void ctd_destroy(ctd_handle* h);
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define CTD_MAX_ORDER 8
 #define CTD_MAX_DRAWS 16384
 #define CTD_MAX_BATCH 256
